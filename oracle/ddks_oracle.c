@@ -1,0 +1,387 @@
+/*
+ * ddks_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct CPU implementation of the exact ddKS
+ * statistic (Hagen et al., "Accelerated Computation of a High Dimensional
+ * Kolmogorov-Smirnov Distance", arXiv:2106.13706).  It exists to check the
+ * GPU library, never to serve it: only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load it.  It shares no code, header, table or
+ * helper with the HIP path.
+ *
+ * What it computes (all citations are to the paper):
+ *
+ *   Sec. 2.1, Eq. (ddks_tensor_definition): the cumulative-density tensors
+ *   C_{X,x} are evaluated at every point of both samples, origins taken in
+ *   the order P then T (the paper's T is called Q here).
+ *
+ *   Sec. 2.1 (loop method) / Sec. 2.2.1, Eq. (g): for each origin o and each
+ *   point x, the point lies on the upper side of dimension m when
+ *   x_m >= o_m (IEEE comparison: -0 == +0, ties go to the upper side, so the
+ *   origin counts itself in the all-upper orthant).  The orthant of x is
+ *   code = sum_m [x_m >= o_m] * 2^m; each of the 2^d orthants is one
+ *   "permutation of greater than or less than in each dimension".
+ *
+ *   Eq. (membership) counts the points of each sample per orthant; Eq. (d1)
+ *   takes the maximum absolute difference.  Reading of the normalisation:
+ *   the difference is between proportions, |c_P/n_P - c_Q/n_Q| (Fig. 2a
+ *   caption: "normalized maximum difference"; Sec. 3, Eq. abs_difference).
+ *   It is evaluated exactly in integers as |c_P*n_Q - c_Q*n_P| = num, with
+ *   den = n_P*n_Q and D = num/den.
+ *
+ *   Ties in the maximum are reported at the lowest origin index (P then Q
+ *   order), then the lowest orthant code (strict '>' while scanning in
+ *   ascending order).  D itself is unique.
+ *
+ *   Sec. 3: analytic significance S = 1 - prod_{orthant,origin}
+ *   P(delta <= D | n_P, n_T, lambda), lambda = (M_T + 1)/(N_T + 2) (Bayes
+ *   estimator with a uniform prior), delta the absolute difference of two
+ *   binomial proportions (Eq. abs_difference, Eq. binomial_probability,
+ *   Eq. ddks_significance).
+ *
+ *   Sec. 3 / Sec. 4.2: permutation test -- the statistic recomputed for
+ *   relabelled pooled samples; here each relabelling is rebuilt as two
+ *   samples in index order and the definition is re-run from scratch.
+ *
+ * Precision: the inputs are fp32; comparisons are done on their exact
+ * double-precision values (identical to fp32 comparison), counts are
+ * uint32, scores int64, D one double division, S in fp64.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL -1
+#define ORACLE_ENOMEM -4
+
+/* ------------------------------------------------------------------------- */
+/* Exact statistic by the definition                                         */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    /* inputs */
+    const float *P, *Q;
+    int64_t n_p, n_q;
+    int d;
+    int64_t k_begin, k_end; /* origin range [k_begin, k_end) in P-then-Q order */
+    uint32_t *counts;       /* nullable, [N][2^d][2] */
+    uint64_t *origin_num;   /* nullable, [N] best score per origin */
+    int32_t *origin_code;   /* nullable, [N] its (lowest) orthant */
+    /* outputs of this chunk */
+    uint64_t best_num;
+    int64_t best_k;
+    int32_t best_j;
+    int status;
+} chunk_job;
+
+/* The k-th origin of the concatenation P then Q (Eq. ddks_tensor_definition). */
+static const float *origin_at(const chunk_job *job, int64_t k)
+{
+    if (k < job->n_p) return job->P + k * job->d;
+    return job->Q + (k - job->n_p) * job->d;
+}
+
+/* Orthant code of x relative to o: bit m set when x_m >= o_m (Eq. g). */
+static uint32_t orthant_code(const float *x, const float *o, int d)
+{
+    uint32_t code = 0;
+    for (int m = 0; m < d; ++m) {
+        double xm = (double)x[m];
+        double om = (double)o[m];
+        if (xm >= om) code |= (uint32_t)1 << m;
+    }
+    return code;
+}
+
+static void *run_chunk(void *arg)
+{
+    chunk_job *job = (chunk_job *)arg;
+    const int d = job->d;
+    const uint32_t bins = (uint32_t)1 << d;
+    uint32_t *cP = (uint32_t *)calloc(bins, sizeof(uint32_t));
+    uint32_t *cQ = (uint32_t *)calloc(bins, sizeof(uint32_t));
+    job->best_num = 0;
+    job->best_k = -1;
+    job->best_j = -1;
+    job->status = ORACLE_OK;
+    if (!cP || !cQ) {
+        free(cP);
+        free(cQ);
+        job->status = ORACLE_ENOMEM;
+        return NULL;
+    }
+    for (int64_t k = job->k_begin; k < job->k_end; ++k) {
+        const float *o = origin_at(job, k);
+        memset(cP, 0, bins * sizeof(uint32_t));
+        memset(cQ, 0, bins * sizeof(uint32_t));
+        /* Eq. (membership): count the points of each sample per orthant. */
+        for (int64_t i = 0; i < job->n_p; ++i) cP[orthant_code(job->P + i * d, o, d)] += 1;
+        for (int64_t i = 0; i < job->n_q; ++i) cQ[orthant_code(job->Q + i * d, o, d)] += 1;
+        /* Eq. (d1), normalised: |cP/nP - cQ/nQ| scaled by nP*nQ. */
+        uint64_t k_best = 0;
+        int32_t k_best_j = 0;
+        for (uint32_t j = 0; j < bins; ++j) {
+            int64_t a = (int64_t)cP[j] * job->n_q;
+            int64_t b = (int64_t)cQ[j] * job->n_p;
+            uint64_t s = (uint64_t)(a > b ? a - b : b - a);
+            if (s > k_best) {
+                k_best = s;
+                k_best_j = (int32_t)j;
+            }
+            if (job->counts) {
+                job->counts[((size_t)k * bins + j) * 2 + 0] = cP[j];
+                job->counts[((size_t)k * bins + j) * 2 + 1] = cQ[j];
+            }
+        }
+        if (job->origin_num) job->origin_num[k] = k_best;
+        if (job->origin_code) job->origin_code[k] = k_best_j;
+        /* first origin attaining a strictly larger score wins */
+        if (job->best_k < 0 || k_best > job->best_num) {
+            job->best_num = k_best;
+            job->best_k = k;
+            job->best_j = k_best_j;
+        }
+    }
+    free(cP);
+    free(cQ);
+    return NULL;
+}
+
+/*
+ * ddks_oracle_distance: exact ddKS of P (n_p x d, row-major fp32) and
+ * Q (n_q x d).  n_threads >= 1 splits the origins into contiguous chunks.
+ * counts (nullable): [n_p+n_q][2^d][2] uint32, sample 0 = P.
+ * origin_num / origin_code (nullable): per-origin maximum score and orthant.
+ * Outputs num (den = n_p*n_q) and the argmax (origin in P-then-Q order,
+ * orthant code).
+ */
+int ddks_oracle_distance(const float *P, int64_t n_p, const float *Q, int64_t n_q, int32_t d,
+                         int32_t n_threads, uint32_t *counts, uint64_t *origin_num,
+                         int32_t *origin_code, uint64_t *num, int64_t *arg_origin,
+                         int32_t *arg_orthant)
+{
+    if (!P || !Q || !num || n_p < 1 || n_q < 1 || d < 1 || d > 16) return ORACLE_EINVAL;
+    if (n_p > 0x7fffffffLL || n_q > 0x7fffffffLL) return ORACLE_EINVAL;
+    const int64_t N = n_p + n_q;
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > N) n_threads = (int32_t)N;
+
+    chunk_job *jobs = (chunk_job *)calloc((size_t)n_threads, sizeof(chunk_job));
+    pthread_t *tids = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !tids) {
+        free(jobs);
+        free(tids);
+        return ORACLE_ENOMEM;
+    }
+    for (int t = 0; t < n_threads; ++t) {
+        jobs[t].P = P;
+        jobs[t].Q = Q;
+        jobs[t].n_p = n_p;
+        jobs[t].n_q = n_q;
+        jobs[t].d = d;
+        jobs[t].k_begin = N * t / n_threads;
+        jobs[t].k_end = N * (t + 1) / n_threads;
+        jobs[t].counts = counts;
+        jobs[t].origin_num = origin_num;
+        jobs[t].origin_code = origin_code;
+    }
+    int spawned = 0;
+    for (int t = 1; t < n_threads; ++t) {
+        if (pthread_create(&tids[t], NULL, run_chunk, &jobs[t]) != 0) break;
+        spawned = t;
+    }
+    run_chunk(&jobs[0]);
+    for (int t = 1; t <= spawned; ++t) pthread_join(tids[t], NULL);
+    for (int t = spawned + 1; t < n_threads; ++t) run_chunk(&jobs[t]); /* threads we could not start */
+
+    /* Merge chunk results in ascending origin order with strict '>',
+       identical to the serial scan. */
+    int status = ORACLE_OK;
+    uint64_t best = 0;
+    int64_t bk = -1;
+    int32_t bj = -1;
+    for (int t = 0; t < n_threads; ++t) {
+        if (jobs[t].status != ORACLE_OK) status = jobs[t].status;
+        if (jobs[t].best_k < 0) continue;
+        if (bk < 0 || jobs[t].best_num > best) {
+            best = jobs[t].best_num;
+            bk = jobs[t].best_k;
+            bj = jobs[t].best_j;
+        }
+    }
+    free(jobs);
+    free(tids);
+    if (status != ORACLE_OK) return status;
+    *num = best;
+    if (arg_origin) *arg_origin = bk;
+    if (arg_orthant) *arg_orthant = bj;
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Permutation test: every relabelling re-run through the definition          */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Z: pooled points (n x d).  labels: B rows of ceil(n/32) uint32 words; bit i
+ * of a row (word i/32, bit i%32) set means point i belongs to the first
+ * sample.  Every row must have exactly n_p set bits.  nums[b] receives the
+ * numerator of the statistic for row b (shared den = n_p*(n-n_p)).
+ */
+int ddks_oracle_permutation(const float *Z, int64_t n, int32_t d, int64_t n_p,
+                            const uint32_t *labels, int32_t B, int32_t n_threads,
+                            uint64_t *nums)
+{
+    if (!Z || !labels || !nums || n < 2 || n_p < 1 || n_p >= n || d < 1 || d > 16 || B < 0)
+        return ORACLE_EINVAL;
+    const int64_t words = (n + 31) / 32;
+    float *A = (float *)malloc((size_t)n_p * d * sizeof(float));
+    float *Bs = (float *)malloc((size_t)(n - n_p) * d * sizeof(float));
+    if (!A || !Bs) {
+        free(A);
+        free(Bs);
+        return ORACLE_ENOMEM;
+    }
+    int status = ORACLE_OK;
+    for (int32_t b = 0; b < B && status == ORACLE_OK; ++b) {
+        const uint32_t *row = labels + (size_t)b * words;
+        int64_t ia = 0, ib = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            int in_first = (row[i / 32] >> (i % 32)) & 1u;
+            if (in_first) {
+                if (ia >= n_p) { status = ORACLE_EINVAL; break; }
+                memcpy(A + ia * d, Z + i * d, (size_t)d * sizeof(float));
+                ++ia;
+            } else {
+                if (ib >= n - n_p) { status = ORACLE_EINVAL; break; }
+                memcpy(Bs + ib * d, Z + i * d, (size_t)d * sizeof(float));
+                ++ib;
+            }
+        }
+        if (status != ORACLE_OK) break;
+        if (ia != n_p) { status = ORACLE_EINVAL; break; }
+        status = ddks_oracle_distance(A, n_p, Bs, n - n_p, d, n_threads, NULL, NULL, NULL,
+                                      &nums[b], NULL, NULL);
+    }
+    free(A);
+    free(Bs);
+    return status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Analytic significance (Sec. 3)                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Binomial pmf p(n : m, lambda) = C(m,n) lambda^n (1-lambda)^(m-n)
+   (Eq. binomial_probability), evaluated in log space. */
+static double binom_pmf(int64_t k, int64_t m, double lam)
+{
+    if (k < 0 || k > m) return 0.0;
+    if (lam <= 0.0) return k == 0 ? 1.0 : 0.0;
+    if (lam >= 1.0) return k == m ? 1.0 : 0.0;
+    double lc = lgamma((double)m + 1.0) - lgamma((double)k + 1.0) - lgamma((double)(m - k) + 1.0);
+    return exp(lc + (double)k * log(lam) + (double)(m - k) * log1p(-lam));
+}
+
+static int64_t floor_div(int64_t a, int64_t b) /* b > 0 */
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) q -= 1;
+    return q;
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) /* b > 0 */
+{
+    return -floor_div(-a, b);
+}
+
+/*
+ * Probability, under H0 with common rate lambda, that
+ * |a/n_p - b/n_q| > num/(n_p*n_q), a ~ Bi(n_p, lambda), b ~ Bi(n_q, lambda):
+ * the complement of Sec. 3's p(d <= delta), summed directly over the
+ * excluded (a, b) so that no cancellation occurs.
+ * |a/n_p - b/n_q| <= num/(n_p n_q)  <=>  |a*n_q - b*n_p| <= num.
+ */
+double ddks_oracle_tail(int64_t n_p, int64_t n_q, double lam, uint64_t num)
+{
+    double *pb = (double *)malloc((size_t)(n_q + 1) * sizeof(double));
+    double *below = (double *)malloc((size_t)(n_q + 2) * sizeof(double)); /* below[t] = sum_{b<t} */
+    double *above = (double *)malloc((size_t)(n_q + 2) * sizeof(double)); /* above[t] = sum_{b>=t} */
+    if (!pb || !below || !above) {
+        free(pb);
+        free(below);
+        free(above);
+        return NAN;
+    }
+    for (int64_t b = 0; b <= n_q; ++b) pb[b] = binom_pmf(b, n_q, lam);
+    below[0] = 0.0;
+    for (int64_t t = 1; t <= n_q + 1; ++t) below[t] = below[t - 1] + pb[t - 1];
+    above[n_q + 1] = 0.0;
+    for (int64_t t = n_q; t >= 0; --t) above[t] = above[t + 1] + pb[t];
+
+    double tail = 0.0;
+    for (int64_t a = 0; a <= n_p; ++a) {
+        int64_t lo = ceil_div(a * n_q - (int64_t)num, n_p);
+        int64_t hi = floor_div(a * n_q + (int64_t)num, n_p);
+        if (lo < 0) lo = 0;
+        if (hi > n_q) hi = n_q;
+        double excluded;
+        if (lo > hi) {
+            excluded = 1.0; /* no b is close enough */
+        } else {
+            excluded = below[lo] + above[hi + 1];
+        }
+        tail += binom_pmf(a, n_p, lam) * excluded;
+    }
+    free(pb);
+    free(below);
+    free(above);
+    if (tail < 0.0) tail = 0.0;
+    if (tail > 1.0) tail = 1.0;
+    return tail;
+}
+
+/*
+ * Analytic significance S of a statistic num/(n_p*n_q) from the membership
+ * counts [N][2^d][2] (sample 0 = P, sample 1 = T/Q) over all N = n_p + n_q
+ * origins (Eq. ddks_significance):
+ *   S = 1 - prod_{j,k} P(delta <= D | lambda_jk),
+ *   lambda_jk = (c_Q[k][j] + 1) / (n_q + 2).
+ * Computed as S = -expm1(sum log1p(-tail_jk)); tails are cached by the
+ * value of c_Q (the only thing lambda depends on).
+ */
+int ddks_oracle_significance(const uint32_t *counts, int64_t n_p, int64_t n_q, int32_t d,
+                             uint64_t num, double *S_out)
+{
+    if (!counts || !S_out || n_p < 1 || n_q < 1 || d < 1 || d > 16) return ORACLE_EINVAL;
+    const int64_t N = n_p + n_q;
+    const uint32_t bins = (uint32_t)1 << d;
+    double *cache = (double *)malloc((size_t)(n_q + 1) * sizeof(double));
+    char *have = (char *)calloc((size_t)(n_q + 1), 1);
+    if (!cache || !have) {
+        free(cache);
+        free(have);
+        return ORACLE_ENOMEM;
+    }
+    double log_keep = 0.0;
+    int status = ORACLE_OK;
+    for (int64_t k = 0; k < N && status == ORACLE_OK; ++k) {
+        for (uint32_t j = 0; j < bins; ++j) {
+            uint32_t t = counts[((size_t)k * bins + j) * 2 + 1];
+            if ((int64_t)t > n_q) { status = ORACLE_EINVAL; break; }
+            if (!have[t]) {
+                double lam = ((double)t + 1.0) / ((double)n_q + 2.0);
+                cache[t] = ddks_oracle_tail(n_p, n_q, lam, num);
+                have[t] = 1;
+            }
+            log_keep += log1p(-cache[t]);
+        }
+    }
+    free(cache);
+    free(have);
+    if (status != ORACLE_OK) return status;
+    *S_out = -expm1(log_keep);
+    return ORACLE_OK;
+}
