@@ -1,0 +1,193 @@
+/*
+ * ddks.h -- C ABI of libddks, an MI355X (gfx950) implementation of the exact
+ * d-dimensional two-sample Kolmogorov-Smirnov statistic (ddKS) of Hagen et
+ * al., "Accelerated Computation of a High Dimensional Kolmogorov-Smirnov
+ * Distance" (arXiv:2106.13706).
+ *
+ * The statistic (Sec. 2.1, Eq. ddks_tensor_definition): every point of both
+ * samples P and Q (the paper's T) is an origin, taken in the order P then Q.
+ * Relative to an origin o, a point x lies in the orthant with code
+ *     code = sum_{m<d} [x_m >= o_m] * 2^m
+ * (Eq. g: IEEE '>=', so -0 == +0 and a tied coordinate goes to the upper
+ * side; the origin counts itself).  c_P[o][code] and c_Q[o][code] count the
+ * points of each sample per orthant (Eq. membership).  D is the maximum over
+ * origins and orthants of |c_P/n_P - c_Q/n_Q| (Eq. d1, normalised by the
+ * sample sizes).  The library evaluates it exactly in integers:
+ *     num = max |c_P*n_Q - c_Q*n_P|,  den = n_P*n_Q,  D = num/den
+ * and reports the first maximiser (lowest origin index, then lowest code).
+ *
+ * Conventions for every call:
+ *   - Return value: DDKS_OK (0) or a negative ddks_status.  On error the
+ *     outputs are left unspecified and ddks_last_error() describes it.
+ *   - Points are fp32, row-major, n rows of d contiguous values, 1 <= d <= 8.
+ *     Values must be finite (the samples live in R^d); -0 is accepted and
+ *     compares equal to +0; subnormals are compared exactly.
+ *   - Without DDKS_DEVICE_PTRS, point/label/count pointers are host memory;
+ *     with it they are device memory on the context's device (for example
+ *     a torch tensor's data_ptr()).  Inputs are only borrowed for the call.
+ *   - Calls on one context are serialised internally; a context may be used
+ *     from several threads.  Different contexts are independent.
+ *   - A HIP error poisons the context: every later call returns
+ *     DDKS_E_DEVICE.  Destroy it and create another.
+ */
+#ifndef DDKS_H
+#define DDKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ddks_status {
+    DDKS_OK = 0,
+    DDKS_E_INVALID_ARG = -1,   /* null pointer, d outside [1,8], n < 1, bad label row, ... */
+    DDKS_E_NO_DEVICE = -2,     /* no usable gfx950 device with that ordinal */
+    DDKS_E_DEVICE = -3,        /* a HIP call failed; the context is poisoned */
+    DDKS_E_NOMEM = -4,         /* the request cannot fit the context's device-memory budget */
+    DDKS_E_NONFINITE = -5,     /* an input value is NaN or +-inf */
+    DDKS_E_AGAIN = -6,         /* serving queue full; retry later */
+    DDKS_E_PENDING = -7,       /* serving result not ready within the timeout */
+    DDKS_E_UNKNOWN_TICKET = -8,/* ticket never issued, or already collected */
+    DDKS_E_NOT_SUPPORTED = -9  /* request outside what this build supports */
+} ddks_status;
+
+/* ddks_options.flags and per-call flags */
+#define DDKS_DEVICE_PTRS 0x1u   /* pointer arguments are device memory */
+#define DDKS_FORCE_F32 0x2u     /* per call: skip the 16-bit rank encoding, compare raw fp32 */
+#define DDKS_NO_AUTOTUNE 0x4u   /* ctx option: use the built-in launch heuristics only */
+
+typedef struct ddks_ctx ddks_ctx;
+
+typedef struct ddks_options {
+    int32_t device;            /* HIP device ordinal */
+    void *stream;              /* hipStream_t to run on; NULL = a library-owned stream */
+    uint64_t mem_budget;       /* device bytes this context may hold; 0 = 90% of free memory */
+    uint32_t flags;            /* DDKS_NO_AUTOTUNE */
+    int32_t serve_streams;     /* serving: concurrent launch streams (0 = 4) */
+    int32_t serve_queue_depth; /* serving: max requests held (admitted or waiting); 0 = 65536 */
+    const char *tune_cache;    /* autotuner cache file; NULL = none (in-memory only) */
+} ddks_options;
+
+typedef struct ddks_result {
+    uint64_t num;             /* max |c_P*n_Q - c_Q*n_P| */
+    uint64_t den;             /* n_P*n_Q */
+    double D;                 /* (double)num / (double)den, correctly rounded */
+    int64_t argmax_origin;    /* index into P then Q of the first maximising origin */
+    int32_t argmax_orthant;   /* its lowest maximising orthant code */
+    int32_t d;
+    int64_t n_p, n_q;
+} ddks_result;
+
+/* Fills *opt with defaults (device 0, library stream, budget 0, no flags). */
+void ddks_default_options(ddks_options *opt);
+
+/* Creates a context on opt->device (opt may be NULL for defaults).
+ * Caller owns *out and releases it with ddks_destroy.
+ * Errors: DDKS_E_INVALID_ARG, DDKS_E_NO_DEVICE, DDKS_E_DEVICE, DDKS_E_NOMEM. */
+int ddks_create(const ddks_options *opt, ddks_ctx **out);
+
+/* Drains serving work, frees every device buffer and the context. NULL is a no-op. */
+int ddks_destroy(ddks_ctx *ctx);
+
+/*
+ * Exact ddKS of P (n_p x d) and Q (n_q x d); Sec. 2.1 Eq. ddks_tensor_definition.
+ * counts (nullable): caller-allocated uint32 [n_p+n_q][2^d][2], origin-major
+ * in P-then-Q order, sample 0 = P -- the membership matrices M of
+ * Eq. membership for both origin sets.  Host memory unless DDKS_DEVICE_PTRS.
+ * Synchronous: returns after the result (and counts) are available.
+ * Limits: 1 <= n_p, n_q; n_p + n_q <= 2^31 - 1; 1 <= d <= 8.
+ * Errors: DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOMEM, DDKS_E_DEVICE.
+ */
+int ddks_distance(ddks_ctx *ctx, const float *P, int64_t n_p, const float *Q, int64_t n_q,
+                  int32_t d, uint32_t flags, ddks_result *out, uint32_t *counts);
+
+/*
+ * Permutation test (Sec. 3 and Sec. 4.2): the statistic for B relabellings
+ * of the pooled sample Z (n x d).
+ * labels: B rows of ceil(n/32) uint32 words; bit (i % 32) of word (i / 32)
+ * set means point i is in the first sample.  Every row must hold exactly
+ * n_p set bits (and none beyond n).  nums_out[B] receives each row's
+ * numerator; all rows share den = n_p*(n - n_p).
+ * observed (nullable): the statistic of the split "first n_p rows of Z are
+ * the first sample", with its argmax, computed in the same launch.
+ * Errors: as ddks_distance, plus DDKS_E_INVALID_ARG for a malformed row.
+ */
+int ddks_permutation_batch(ddks_ctx *ctx, const float *Z, int64_t n, int32_t d, int64_t n_p,
+                           const uint32_t *labels, int32_t B, uint32_t flags, uint64_t *nums_out,
+                           ddks_result *observed);
+
+/*
+ * Analytic significance S of a statistic num/(n_p*n_q) from its membership
+ * counts (Sec. 3, Eq. ddks_significance):
+ *   S = 1 - prod over origins k and orthants j of P(delta <= D | lambda_kj),
+ *   lambda_kj = (c_Q[k][j] + 1) / (n_q + 2)   (Bayes estimator, uniform prior),
+ * delta = |a/n_p - b/n_q| with a ~ Bi(n_p, lambda), b ~ Bi(n_q, lambda)
+ * (Eq. abs_difference, Eq. binomial_probability).  Computed on the device
+ * in fp64.  counts: [n_p+n_q][2^d][2] as written by ddks_distance (host
+ * memory unless DDKS_DEVICE_PTRS).
+ * Errors: DDKS_E_INVALID_ARG, DDKS_E_NOMEM, DDKS_E_DEVICE.
+ */
+int ddks_significance(ddks_ctx *ctx, const uint32_t *counts, int64_t n_p, int64_t n_q, int32_t d,
+                      uint64_t num, uint32_t flags, double *S_out);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct ddks_request {
+    const float *P; /* host, n_p x d */
+    int64_t n_p;
+    const float *Q; /* host, n_q x d */
+    int64_t n_q;
+    int32_t d;
+    uint32_t flags; /* reserved, 0 */
+} ddks_request;
+
+typedef struct ddks_serve_stats {
+    uint64_t submitted, completed, rejected_again, rejected_nomem;
+    uint64_t launches;         /* packed launches issued */
+    double p50_latency_us;     /* submit -> result ready, over completed requests */
+    double p99_latency_us;
+    double mean_batch;         /* tests per packed launch */
+    uint64_t resident_bytes;   /* device bytes currently held by admitted requests */
+} ddks_serve_stats;
+
+/*
+ * Submits one test to the context's serving loop (continuous batching:
+ * requests that arrive while others run are admitted as device memory and
+ * queue slots free up, and packed into shared launches).  The library
+ * copies P and Q before returning; the caller may free them at once.
+ * Thread-safe.  *ticket identifies the request for ddks_serve_poll.
+ * Errors: DDKS_E_AGAIN (queue full), DDKS_E_NOMEM (can never fit the
+ * budget), DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_DEVICE.
+ */
+int ddks_serve_submit(ddks_ctx *ctx, const ddks_request *req, uint64_t *ticket);
+
+/*
+ * Waits up to timeout_us (0 = just check, < 0 = wait forever) for a
+ * submitted test.  On DDKS_OK fills *out (identical to what ddks_distance
+ * returns for the same inputs) and releases the ticket.  Thread-safe.
+ * Errors: DDKS_E_PENDING, DDKS_E_UNKNOWN_TICKET, DDKS_E_DEVICE.
+ */
+int ddks_serve_poll(ddks_ctx *ctx, uint64_t ticket, int32_t timeout_us, ddks_result *out);
+
+/* Counters and latency percentiles of the serving loop since the context was created
+ * (or since the last reset when reset != 0). */
+int ddks_serve_stats_get(ddks_ctx *ctx, ddks_serve_stats *out, int32_t reset);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Static description of a status code. */
+const char *ddks_status_string(int status);
+
+/* Description of the last error on this context (empty string if none). */
+const char *ddks_last_error(const ddks_ctx *ctx);
+
+/* Library version string. */
+const char *ddks_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDKS_H */

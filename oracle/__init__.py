@@ -50,6 +50,8 @@ def _load():
     lib.ddks_oracle_significance.argtypes = [vp, i64, i64, i32, ctypes.c_uint64,
                                              ctypes.POINTER(ctypes.c_double)]
     lib.ddks_oracle_significance.restype = ctypes.c_int
+    lib.ddks_oracle_origin_counts.argtypes = [vp, i64, vp, i64, i32, vp, i64, vp]
+    lib.ddks_oracle_origin_counts.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -99,6 +101,20 @@ def distance(P, Q, *, threads: int = 1, counts: bool = False,
         raise ValueError(f"oracle distance failed with status {st}")
     den = n_p * n_q
     return OracleResult(num.value, den, num.value / den, ko.value, jo.value, c, on, oc)
+
+
+def origin_counts(P, Q, idx) -> np.ndarray:
+    """[len(idx), 2^d, 2] counts of the chosen origins (P-then-Q indices)."""
+    lib = _load()
+    P, Q = _f32(P), _f32(Q)
+    d = P.shape[1]
+    ix = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros((ix.size, 1 << d, 2), dtype=np.uint32)
+    st = lib.ddks_oracle_origin_counts(P.ctypes.data, P.shape[0], Q.ctypes.data, Q.shape[0], d,
+                                       ix.ctypes.data, ix.size, out.ctypes.data)
+    if st != 0:
+        raise ValueError(f"oracle origin_counts failed with status {st}")
+    return out
 
 
 def labels_to_words(mask_rows) -> np.ndarray:

@@ -385,3 +385,37 @@ int ddks_oracle_significance(const uint32_t *counts, int64_t n_p, int64_t n_q, i
     *S_out = -expm1(log_keep);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Counts for a chosen subset of origins (same definition, one origin at a    */
+/* time), for checking large inputs at sampled origins.                        */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * idx[n_idx]: origin indices in P-then-Q order.  counts_out: [n_idx][2^d][2]
+ * uint32 (sample 0 = P).
+ */
+int ddks_oracle_origin_counts(const float *P, int64_t n_p, const float *Q, int64_t n_q, int32_t d,
+                              const int64_t *idx, int64_t n_idx, uint32_t *counts_out)
+{
+    if (!P || !Q || !idx || !counts_out || n_p < 1 || n_q < 1 || d < 1 || d > 16)
+        return ORACLE_EINVAL;
+    const uint32_t bins = (uint32_t)1 << d;
+    chunk_job job;
+    memset(&job, 0, sizeof(job));
+    job.P = P;
+    job.Q = Q;
+    job.n_p = n_p;
+    job.n_q = n_q;
+    job.d = d;
+    for (int64_t t = 0; t < n_idx; ++t) {
+        int64_t k = idx[t];
+        if (k < 0 || k >= n_p + n_q) return ORACLE_EINVAL;
+        const float *o = origin_at(&job, k);
+        uint32_t *c = counts_out + (size_t)t * bins * 2;
+        memset(c, 0, (size_t)bins * 2 * sizeof(uint32_t));
+        for (int64_t i = 0; i < n_p; ++i) c[orthant_code(P + i * d, o, d) * 2 + 0] += 1;
+        for (int64_t i = 0; i < n_q; ++i) c[orthant_code(Q + i * d, o, d) * 2 + 1] += 1;
+    }
+    return ORACLE_OK;
+}

@@ -1,0 +1,82 @@
+// Internal interface between the host runtime and the gfx950 kernels of libddks.
+// Not part of the public ABI (include/ddks.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddks {
+
+// Per-block best (origin group) and the final result, as the device writes them.
+struct BlockBest {
+    uint64_t num;     // max |c_P*n_Q - c_Q*n_P| within the block
+    uint32_t origin;  // lowest maximising origin (P-then-Q index); 0xffffffff if none
+    int32_t code;     // lowest maximising orthant code of that origin
+};
+
+struct ResultDev {
+    uint64_t num;
+    int64_t origin;
+    int32_t code;
+    uint32_t flags;  // bit 0: a non-finite input value was seen
+};
+
+enum Path : int { PATH_F32 = 0, PATH_R16 = 1 };
+
+// Launch shape of one sweep.
+struct SweepPlan {
+    int path = PATH_F32;
+    int d = 1;
+    int waves = 4;          // waves per block; each wave owns one LDS histogram
+    int64_t groups = 0;     // ceil(N / 64) origin groups
+    int64_t chunks = 1;     // point-range chunks (grid.y)
+    int64_t chunk_len = 0;  // points per chunk (<= waves * 65535)
+};
+
+// Words (4-byte) per point in the device point buffer.
+int point_words(int path, int d);
+
+// Bytes of dynamic LDS a sweep block of this plan uses.
+size_t sweep_lds_bytes(const SweepPlan &p);
+
+// Largest waves-per-block the LDS allows for this d (1..8).
+int max_waves_for_d(int d);
+
+// ---------------------------------------------------------------- launches
+// All return the HIP error of the launch (hipSuccess on success).
+
+// Copies P then Q into Z (N x d fp32), mapping -0 to +0 and setting bit 0 of
+// *flags if any value is not finite.  P/Q may alias Z (in-place).
+hipError_t launch_ingest_f32(const float *P, int64_t n_p, const float *Q, int64_t n_q, int d,
+                             float *Z, uint32_t *flags, hipStream_t s);
+
+// Dense per-dimension ranks of Z (N x d fp32), biased to int16 and packed two
+// dimensions per word (point_words(PATH_R16, d) words per point) into R.
+// keys/idx/tmp are scratch of N*d elements each.  *distinct_max receives the
+// largest per-dimension distinct-value count (the encoding is valid only when
+// it is <= 65536).
+hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, uint64_t *keys,
+                         uint64_t *keys_tmp, uint32_t *ranks_tmp, uint32_t *distinct_max,
+                         hipStream_t s);
+size_t rank16_scratch_bytes(int64_t N, int d);
+
+// The O(2^d N^2) sweep.  With plan.chunks == 1 the epilogue scores in place and
+// writes block_best[group]; otherwise it writes per-chunk partial counts
+// (uint2 [chunks][groups][2^d][64]) for launch_score.
+// counts (nullable, device): [N][2^d][2] uint32, written when chunks == 1.
+hipError_t launch_sweep(const SweepPlan &plan, const void *Z, int64_t N, int64_t n_p,
+                        int64_t n_q, uint2 *partial, BlockBest *block_best, uint32_t *counts,
+                        hipStream_t s);
+
+// Sums the partial counts of a multi-chunk sweep, scores, writes block_best
+// (and counts if non-null).
+hipError_t launch_score(const SweepPlan &plan, int64_t N, int64_t n_p, int64_t n_q,
+                        const uint2 *partial, BlockBest *block_best, uint32_t *counts,
+                        hipStream_t s);
+
+// Reduces block_best[0..nblocks) with the tie rule (num desc, origin asc,
+// code asc) into *out, copies *flags into out->flags and clears *flags.
+hipError_t launch_reduce(const BlockBest *block_best, int64_t nblocks, uint32_t *flags,
+                         ResultDev *out, hipStream_t s);
+
+}  // namespace ddks

@@ -1,0 +1,320 @@
+// libddks host runtime: context, device buffers under a budget, and the
+// single-test entry point ddks_distance (arXiv:2106.13706, Sec. 2.1
+// Eq. ddks_tensor_definition).
+#include "ddks_runtime.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <new>
+
+using namespace ddks;
+
+namespace ddks {
+
+int fail(ddks_ctx *c, int status, const std::string &msg)
+{
+    if (c) c->last_error = msg;
+    return status;
+}
+
+int hip_check(ddks_ctx *c, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return DDKS_OK;
+    if (c) {
+        c->poisoned = true;
+        c->last_error = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return DDKS_E_DEVICE;
+}
+
+int ensure(ddks_ctx *c, DevBuf &b, size_t bytes, const char *what)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return DDKS_OK;
+    // grow geometrically to limit reallocations across calls of rising size
+    size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+    want = (want + 4095) & ~(size_t)4095;
+    uint64_t others = c->used.load() - b.bytes;
+    if (others + want > c->budget) {
+        want = (bytes + 4095) & ~(size_t)4095;
+        if (others + want > c->budget)
+            return fail(c, DDKS_E_NOMEM,
+                        std::string("device memory budget exceeded allocating ") + what);
+    }
+    if (b.ptr) {
+        hipError_t e = hipFree(b.ptr);
+        c->used -= b.bytes;
+        b.ptr = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess) return hip_check(c, e, "hipFree");
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return fail(c, DDKS_E_NOMEM, std::string("hipMalloc out of memory for ") + what);
+    }
+    if (e != hipSuccess) return hip_check(c, e, "hipMalloc");
+    b.ptr = p;
+    b.bytes = want;
+    c->used += want;
+    return DDKS_OK;
+}
+
+void release(ddks_ctx *c, DevBuf &b)
+{
+    if (b.ptr) {
+        (void)hipFree(b.ptr);
+        c->used -= b.bytes;
+    }
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool /*want_counts*/)
+{
+    SweepPlan p;
+    p.path = path;
+    p.d = d;
+    if (c && c->tuner && !(c->opt_flags & DDKS_NO_AUTOTUNE) && tuner_lookup(c->tuner, path, d, N, &p)) {
+        p.path = path;
+        p.d = d;
+        p.groups = cdiv(N, 64);
+        p.chunk_len = cdiv(N, p.chunks);
+        if (p.chunk_len <= (int64_t)p.waves * 65535) return p;
+    }
+    p.waves = d <= 7 ? 4 : 2;
+    if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 || c->force_waves == 8) &&
+        c->force_waves <= max_waves_for_d(d))
+        p.waves = c->force_waves;
+    p.groups = cdiv(N, 64);
+    // about 8 waves per SIMD over the 1024 SIMDs, each sweeping >= 256 points
+    const int64_t target_waves = 8192;
+    int64_t chunks = cdiv(target_waves, p.groups * p.waves);
+    int64_t max_chunks = std::max<int64_t>(1, N / ((int64_t)p.waves * 256));
+    chunks = std::min(chunks, max_chunks);
+    chunks = std::max<int64_t>(chunks, cdiv(N, (int64_t)p.waves * 65535));
+    if (c && c->force_chunks > 0) chunks = std::min(c->force_chunks, N);
+    chunks = std::max<int64_t>(chunks, cdiv(N, (int64_t)p.waves * 65535));
+    chunks = std::min<int64_t>(chunks, 65535);
+    p.chunks = chunks;
+    p.chunk_len = cdiv(N, chunks);
+    return p;
+}
+
+int choose_path(ddks_ctx * /*c*/, int /*d*/, int64_t /*N*/, uint32_t /*flags*/)
+{
+    return PATH_F32;
+}
+
+int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
+              int64_t n_q, uint32_t *counts_dev, hipStream_t s)
+{
+    int st = ensure(c, c->block_best, (size_t)plan.groups * sizeof(BlockBest), "block results");
+    if (st) return st;
+    uint2 *partial = nullptr;
+    if (plan.chunks > 1) {
+        size_t pb = (size_t)plan.chunks * plan.groups * ((size_t)1 << plan.d) * 64 * sizeof(uint2);
+        st = ensure(c, c->partial, pb, "partial counts");
+        if (st) return st;
+        partial = (uint2 *)c->partial.ptr;
+    }
+    BlockBest *bb = (BlockBest *)c->block_best.ptr;
+    st = hip_check(c, launch_sweep(plan, zdata, N, n_p, n_q, partial, bb, counts_dev, s), "sweep launch");
+    if (st) return st;
+    if (plan.chunks > 1) {
+        st = hip_check(c, launch_score(plan, N, n_p, n_q, partial, bb, counts_dev, s), "score launch");
+        if (st) return st;
+    }
+    return hip_check(c, launch_reduce(bb, plan.groups, c->flags_dev, c->result_dev, s), "reduce launch");
+}
+
+}  // namespace ddks
+
+// ==================================================================== C ABI
+
+extern "C" {
+
+const char *ddks_version(void) { return "libddks 0.1 (gfx950)"; }
+
+const char *ddks_status_string(int s)
+{
+    switch (s) {
+    case DDKS_OK: return "ok";
+    case DDKS_E_INVALID_ARG: return "invalid argument";
+    case DDKS_E_NO_DEVICE: return "no usable device";
+    case DDKS_E_DEVICE: return "device error";
+    case DDKS_E_NOMEM: return "out of device memory budget";
+    case DDKS_E_NONFINITE: return "non-finite input value";
+    case DDKS_E_AGAIN: return "queue full, try again";
+    case DDKS_E_PENDING: return "result pending";
+    case DDKS_E_UNKNOWN_TICKET: return "unknown ticket";
+    case DDKS_E_NOT_SUPPORTED: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+const char *ddks_last_error(const ddks_ctx *c) { return c ? c->last_error.c_str() : ""; }
+
+void ddks_default_options(ddks_options *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+}
+
+int ddks_create(const ddks_options *opt, ddks_ctx **out)
+{
+    if (!out) return DDKS_E_INVALID_ARG;
+    *out = nullptr;
+    ddks_options o;
+    ddks_default_options(&o);
+    if (opt) o = *opt;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return DDKS_E_NO_DEVICE;
+    }
+    if (o.device < 0 || o.device >= ndev) return DDKS_E_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, o.device) != hipSuccess) return DDKS_E_NO_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return DDKS_E_NO_DEVICE;
+    if (hipSetDevice(o.device) != hipSuccess) return DDKS_E_DEVICE;
+
+    ddks_ctx *c = new (std::nothrow) ddks_ctx();
+    if (!c) return DDKS_E_NOMEM;
+    c->device = o.device;
+    c->opt_flags = o.flags;
+    c->serve_streams = o.serve_streams > 0 ? o.serve_streams : 4;
+    c->serve_queue_depth = o.serve_queue_depth > 0 ? o.serve_queue_depth : 65536;
+    if (o.tune_cache) c->tune_cache = o.tune_cache;
+    if (const char *e = getenv("DDKS_FORCE_WAVES")) c->force_waves = atoi(e);
+    if (const char *e = getenv("DDKS_FORCE_CHUNKS")) c->force_chunks = atoll(e);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        delete c;
+        return DDKS_E_DEVICE;
+    }
+    c->budget = o.mem_budget ? o.mem_budget : (uint64_t)(free_b * 0.9);
+    int st = DDKS_OK;
+    if (o.stream) {
+        c->stream = (hipStream_t)o.stream;
+    } else {
+        st = hip_check(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream");
+        c->own_stream = (st == DDKS_OK);
+    }
+    if (!st) st = hip_check(c, hipMalloc((void **)&c->result_dev, sizeof(ResultDev)), "hipMalloc");
+    if (!st) st = hip_check(c, hipMalloc((void **)&c->flags_dev, 2 * sizeof(uint32_t)), "hipMalloc");
+    if (!st) st = hip_check(c, hipMemset(c->flags_dev, 0, 2 * sizeof(uint32_t)), "hipMemset");
+    if (!st) st = hip_check(c, hipMalloc((void **)&c->rank_distinct_dev, 16 * sizeof(uint32_t)), "hipMalloc");
+    if (!st) st = hip_check(c, hipHostMalloc((void **)&c->result_host, sizeof(ResultDev), 0), "hipHostMalloc");
+    if (!st) st = hip_check(c, hipHostMalloc((void **)&c->rank_distinct_host, 16 * sizeof(uint32_t), 0), "hipHostMalloc");
+    if (!st) c->used += sizeof(ResultDev) + 2 * sizeof(uint32_t) + 16 * sizeof(uint32_t);
+    if (!st) c->tuner = tuner_create(c->tune_cache.empty() ? nullptr : c->tune_cache.c_str());
+    if (st) {
+        ddks_destroy(c);
+        return st;
+    }
+    *out = c;
+    return DDKS_OK;
+}
+
+int ddks_destroy(ddks_ctx *c)
+{
+    if (!c) return DDKS_OK;
+    (void)hipSetDevice(c->device);
+    serve_stop(c);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    DevBuf *bufs[] = {&c->z, &c->zr, &c->partial, &c->block_best, &c->counts, &c->rank_scratch,
+                      &c->labels, &c->nums, &c->sig};
+    for (DevBuf *b : bufs) release(c, *b);
+    if (c->result_dev) (void)hipFree(c->result_dev);
+    if (c->flags_dev) (void)hipFree(c->flags_dev);
+    if (c->rank_distinct_dev) (void)hipFree(c->rank_distinct_dev);
+    if (c->result_host) (void)hipHostFree(c->result_host);
+    if (c->rank_distinct_host) (void)hipHostFree(c->rank_distinct_host);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    tuner_destroy(c->tuner);
+    delete c;
+    return DDKS_OK;
+}
+
+int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int64_t n_q,
+                  int32_t d, uint32_t flags, ddks_result *out, uint32_t *counts)
+{
+    if (!c) return DDKS_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->poisoned) return fail(c, DDKS_E_DEVICE, "context poisoned by an earlier device error");
+    if (!P || !Q || !out) return fail(c, DDKS_E_INVALID_ARG, "null pointer argument");
+    if (d < 1 || d > 8) return fail(c, DDKS_E_INVALID_ARG, "d must be in [1, 8]");
+    if (n_p < 1 || n_q < 1) return fail(c, DDKS_E_INVALID_ARG, "each sample needs at least one point");
+    const int64_t N = n_p + n_q;
+    if (N > 0x7fffffffLL) return fail(c, DDKS_E_INVALID_ARG, "n_p + n_q exceeds 2^31 - 1");
+    if (hipSetDevice(c->device) != hipSuccess) return hip_check(c, hipGetLastError(), "hipSetDevice");
+    const bool dev = (flags & DDKS_DEVICE_PTRS) != 0;
+    hipStream_t s = c->stream;
+    const size_t bins = (size_t)1 << d;
+
+    int st = ensure(c, c->z, (size_t)N * d * sizeof(float), "points");
+    if (st) return st;
+    float *Z = (float *)c->z.ptr;
+    const float *srcP = P, *srcQ = Q;
+    if (!dev) {
+        st = hip_check(c, hipMemcpyAsync(Z, P, (size_t)n_p * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D P");
+        if (!st) st = hip_check(c, hipMemcpyAsync(Z + n_p * d, Q, (size_t)n_q * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D Q");
+        if (st) return st;
+        srcP = Z;
+        srcQ = Z + n_p * d;
+    }
+    st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
+    if (st) return st;
+
+    uint32_t *counts_dev = nullptr;
+    if (counts) {
+        if (dev) {
+            counts_dev = counts;
+        } else {
+            st = ensure(c, c->counts, (size_t)N * bins * 2 * sizeof(uint32_t), "counts");
+            if (st) return st;
+            counts_dev = (uint32_t *)c->counts.ptr;
+        }
+    }
+
+    int path = choose_path(c, d, N, flags);
+    const void *zdata = Z;
+    if (path == PATH_R16) {
+        bool ok = false;
+        st = encode_rank16(c, N, d, &ok);
+        if (st) return st;
+        if (ok) zdata = c->zr.ptr;
+        else path = PATH_F32;
+    }
+    SweepPlan plan = plan_for(c, path, d, N, counts != nullptr);
+    st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, s);
+    if (st) return st;
+    st = hip_check(c, hipMemcpyAsync(c->result_host, c->result_dev, sizeof(ResultDev), hipMemcpyDeviceToHost, s), "D2H result");
+    if (st) return st;
+    if (counts && !dev) {
+        st = hip_check(c, hipMemcpyAsync(counts, counts_dev, (size_t)N * bins * 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "D2H counts");
+        if (st) return st;
+    }
+    st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (st) return st;
+    const ResultDev r = *c->result_host;
+    if (r.flags & 1u) return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
+    out->num = r.num;
+    out->den = (uint64_t)n_p * (uint64_t)n_q;
+    out->D = (double)r.num / (double)out->den;
+    out->argmax_origin = r.origin;
+    out->argmax_orthant = r.code;
+    out->d = d;
+    out->n_p = n_p;
+    out->n_q = n_q;
+    return DDKS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Host-side context of libddks: device buffers under a memory budget, the
+// context stream, launch planning, and the helpers shared by the single-test,
+// permutation and serving paths.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ddks.h"
+#include "ddks_internal.h"
+
+namespace ddks {
+
+struct Serve;  // serving loop (ddks_serve.cpp)
+
+// A device allocation that grows on demand and is charged to its context's budget.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Tuner;  // launch-shape autotuner (ddks_tune.cpp)
+
+}  // namespace ddks
+
+struct ddks_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    uint32_t opt_flags = 0;
+    int serve_streams = 4;
+    int serve_queue_depth = 65536;
+    std::string tune_cache;
+    int force_waves = 0;   // test override (DDKS_FORCE_WAVES)
+    int64_t force_chunks = 0;  // test override (DDKS_FORCE_CHUNKS)
+    bool poisoned = false;
+    std::string last_error;
+    std::mutex mu;  // serialises the synchronous calls on `stream`
+
+    // buffers of the synchronous path
+    ddks::DevBuf z, zr, partial, block_best, counts, rank_scratch, labels, nums, sig;
+    ddks::ResultDev *result_dev = nullptr;  // device
+    ddks::ResultDev *result_host = nullptr; // pinned
+    uint32_t *flags_dev = nullptr;          // device, cleared by the reduction
+    uint32_t *rank_distinct_host = nullptr; // pinned
+    uint32_t *rank_distinct_dev = nullptr;
+
+    ddks::Tuner *tuner = nullptr;
+    ddks::Serve *serve = nullptr;
+    std::mutex serve_mu;
+};
+
+namespace ddks {
+
+// Records an error on the context and returns status.
+int fail(ddks_ctx *c, int status, const std::string &msg);
+// Checks a HIP return code; on failure poisons the context.
+int hip_check(ddks_ctx *c, hipError_t e, const char *what);
+
+// Grows b to at least bytes (contents not preserved), charging the budget.
+int ensure(ddks_ctx *c, DevBuf &b, size_t bytes, const char *what);
+void release(ddks_ctx *c, DevBuf &b);
+
+// Launch shape for one test of N points in dimension d on the given path.
+SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool want_counts);
+
+// Runs the sweep + score + reduce of one test whose points are already in a
+// device buffer (fp32 N x d at zf, and when path == PATH_R16 the rank
+// encoding at zr).  Leaves the result in c->result_dev; does not synchronise.
+int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
+              int64_t n_q, uint32_t *counts_dev, hipStream_t s);
+
+// Chooses the path for a test (fp32 or rank-16) given the caller's flags.
+int choose_path(ddks_ctx *c, int d, int64_t N, uint32_t flags);
+
+// Encodes the fp32 points in c->z (N x d) as int16 ranks into c->zr.  Returns
+// DDKS_OK and sets *ok = false when some dimension has more than 65536 distinct
+// values (the caller then falls back to the fp32 path).
+int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok);
+
+// Serving lifecycle (ddks_serve.cpp).
+int serve_start(ddks_ctx *c);
+void serve_stop(ddks_ctx *c);
+
+// Autotuner (ddks_tune.cpp).
+Tuner *tuner_create(const char *cache_path);
+void tuner_destroy(Tuner *t);
+// Returns true and fills plan if a tuned shape exists for (path, d, N bucket).
+bool tuner_lookup(Tuner *t, int path, int d, int64_t N, SweepPlan *plan);
+
+}  // namespace ddks

@@ -1,0 +1,588 @@
+// gfx950 kernels for the exact ddKS orthant-counting sweep (arXiv:2106.13706,
+// Sec. 2.1 Eq. ddks_tensor_definition, Eq. g, Eq. membership, Eq. d1).
+//
+// Work decomposition: one origin per lane, 64 origins per wave; every wave of
+// a block holds the same 64 origins and sweeps its own share of the points,
+// so the block's waves are reduced in LDS and only the block's result leaves
+// the CU.  Points are read with wave-uniform (scalar) loads straight into
+// SGPRs, so a point costs no VGPR traffic; each lane compares it with its own
+// origin:
+//
+//   fp32 path: v_fma_mix{lo,hi}_f16(x, 1.0, -o) gives sign(x - o) in bit 15 or
+//              31 of a register; x - o is exact in sign (zero only when
+//              x == o, which rounds to +0 since -0 was mapped to +0 on ingest;
+//              subnormals are kept: the kernels run with fp32/fp16 denormals
+//              preserved).
+//   rank path: coordinates replaced by per-dimension dense ranks biased to
+//              int16, two dimensions per word; v_pk_sub_i16 with saturation
+//              gives both signs in one instruction.
+//
+// v_perm_b32 gathers four sign bits into sign-filled bytes (0xff where
+// x_m < o_m), v_dot4_i32_i8 against per-dimension weights turns them into
+// -(sum of 2^m over the dimensions where x_m < o_m), and one v_lshl_add forms
+// the LDS address of the orthant bin.  Histograms are lane-minor
+// (bin * 64 + lane), so a ds_add_u32 from a wave touches 64 distinct banks
+// slots whatever the codes are.  Counts of both samples share one 32-bit
+// counter: +1 for a point of P, +65536 for a point of Q (a wave never sweeps
+// more than 65535 points of either sample).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ddks_internal.h"
+
+namespace ddks {
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+template <int D>
+struct Geo {
+    static constexpr int BINS = 1 << D;
+    static constexpr int NREG = (D + 1) / 2;   // sign registers, two dimensions each
+    static constexpr int NPERM = (D + 3) / 4;  // v_perm/v_dot4 groups, four dimensions each
+    // Dimension 7's weight does not fit a signed byte; it is given weight -128,
+    // which flips that bit of the bin index relative to the orthant code.
+    static constexpr int FLIP = (D == 8) ? 0x80 : 0;
+    static constexpr int KOFF = (D == 8) ? 127 : (BINS - 1);  // bin = dot-sum + KOFF
+};
+
+// v_perm_b32 selector for group q: byte i takes the sign of dimension 4q+i
+// (8/9: bit 15/31 of src1 = register 2q; 10/11: bit 15/31 of src0 = register
+// 2q+1) and 0x00 (selector 12) for dimensions beyond D.
+__host__ __device__ constexpr uint32_t perm_sel(int D, int q)
+{
+    uint32_t sel = 0;
+    for (int i = 0; i < 4; ++i) {
+        int m = 4 * q + i;
+        uint32_t b = (m < D) ? (uint32_t)(8 + i) : 12u;
+        sel |= b << (8 * i);
+    }
+    return sel;
+}
+
+// Signed-byte weights for group q: 2^m, and -128 for m = 7.
+__host__ __device__ constexpr uint32_t dot_wts(int D, int q)
+{
+    uint32_t w = 0;
+    for (int i = 0; i < 4; ++i) {
+        int m = 4 * q + i;
+        uint32_t b = 0;
+        if (m < D) b = (m == 7) ? 0x80u : (uint32_t)(1u << m);
+        w |= (b & 0xffu) << (8 * i);
+    }
+    return w;
+}
+
+// sign(x - o) of two fp32 dimensions into bits 15 and 31.
+__device__ __forceinline__ uint32_t sgn2_f32(float x0, float o0, float x1, float o1)
+{
+    uint32_t r;
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,0]" : "=v"(r) : "s"(x0), "v"(o0));
+    asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,0]" : "+v"(r) : "s"(x1), "v"(o1));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t sgn1_f32(float x0, float o0)
+{
+    uint32_t r;
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,0]" : "=v"(r) : "s"(x0), "v"(o0));
+    return r;
+}
+
+// sign(x - o) of two rank-encoded dimensions (int16, saturating) into bits 15 and 31.
+__device__ __forceinline__ uint32_t sgn2_r16(uint32_t x, uint32_t o)
+{
+    short2_t t = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2_t, x),
+                                               __builtin_bit_cast(short2_t, o));
+    return __builtin_bit_cast(uint32_t, t);
+}
+
+// -(sum over dimensions with x_m < o_m of their weights), from the sign registers.
+template <int D>
+__device__ __forceinline__ int dot_code(const uint32_t (&r)[Geo<D>::NREG])
+{
+    constexpr int NR = Geo<D>::NREG;
+    uint32_t R0 = __builtin_amdgcn_perm(NR > 1 ? r[NR > 1 ? 1 : 0] : 0u, r[0], perm_sel(D, 0));
+    int acc;
+    asm("v_dot4_i32_i8 %0, %1, %2, 0" : "=v"(acc) : "v"(R0), "s"(dot_wts(D, 0)));
+    if constexpr (Geo<D>::NPERM > 1) {
+        uint32_t R1 = __builtin_amdgcn_perm(NR > 3 ? r[NR > 3 ? 3 : 2] : 0u, r[2], perm_sel(D, 1));
+        asm("v_dot4_i32_i8 %0, %1, %2, %3" : "=v"(acc) : "v"(R1), "s"(dot_wts(D, 1)), "v"(acc));
+    }
+    return acc;
+}
+
+// Point element type and words per point for each path.
+template <int PATH, int D>
+struct Layout;
+template <int D>
+struct Layout<PATH_F32, D> {
+    typedef float T;
+    static constexpr int PW = D;  // floats per point
+};
+template <int D>
+struct Layout<PATH_R16, D> {
+    typedef uint32_t T;
+    static constexpr int PW = (D <= 2) ? 1 : (D <= 4 ? 2 : 4);  // padded to a power of two
+};
+
+// Points per unrolled block: about 32 scalar registers of point data.
+template <int PATH, int D>
+struct Unroll {
+    static constexpr int PW = Layout<PATH, D>::PW;
+    static constexpr int U = (32 / PW) < 1 ? 1 : (32 / PW);
+};
+
+// The origin held by a lane.
+template <int PATH, int D>
+struct Origin;
+template <int D>
+struct Origin<PATH_F32, D> {
+    float o[D];
+    __device__ void load(const float *Z, int64_t k)
+    {
+#pragma unroll
+        for (int m = 0; m < D; ++m) o[m] = Z[k * D + m];
+    }
+};
+template <int D>
+struct Origin<PATH_R16, D> {
+    static constexpr int PW = Layout<PATH_R16, D>::PW;
+    uint32_t o[PW];
+    __device__ void load(const uint32_t *Z, int64_t k)
+    {
+#pragma unroll
+        for (int m = 0; m < PW; ++m) o[m] = Z[k * PW + m];
+    }
+};
+
+// Sign registers of point x (PW words at xs) against the lane's origin.
+template <int PATH, int D>
+__device__ __forceinline__ void signs(const typename Layout<PATH, D>::T *xs,
+                                      const Origin<PATH, D> &org, uint32_t (&r)[Geo<D>::NREG])
+{
+    if constexpr (PATH == PATH_F32) {
+#pragma unroll
+        for (int p = 0; p < Geo<D>::NREG; ++p) {
+            if (2 * p + 1 < D)
+                r[p] = sgn2_f32(xs[2 * p], org.o[2 * p], xs[2 * p + 1], org.o[2 * p + 1]);
+            else
+                r[p] = sgn1_f32(xs[2 * p], org.o[2 * p]);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < Geo<D>::NREG; ++p) r[p] = sgn2_r16(xs[p], org.o[p]);
+    }
+}
+
+// Sweeps points [lo, hi) of Z against the lane's origin, adding inc to the
+// lane's bin of each point.  hw points at bin KOFF of this lane's column.
+template <int PATH, int D>
+__device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *__restrict__ Z,
+                                            int64_t lo, int64_t hi, const Origin<PATH, D> &org,
+                                            uint32_t *hw, uint32_t inc)
+{
+    typedef typename Layout<PATH, D>::T T;
+    constexpr int PW = Layout<PATH, D>::PW;
+    constexpr int U = Unroll<PATH, D>::U;
+    int64_t i = lo;
+    for (; i + U <= hi; i += U) {
+        const T *blk = Z + i * PW;
+        T buf[U * PW];
+#pragma unroll
+        for (int e = 0; e < U * PW; ++e) buf[e] = blk[e];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint32_t r[Geo<D>::NREG];
+            signs<PATH, D>(buf + u * PW, org, r);
+            int acc = dot_code<D>(r);
+            atomicAdd(hw + acc * 64, inc);
+        }
+    }
+    for (; i < hi; ++i) {
+        const T *xs = Z + i * PW;
+        T buf[PW];
+#pragma unroll
+        for (int e = 0; e < PW; ++e) buf[e] = xs[e];
+        uint32_t r[Geo<D>::NREG];
+        signs<PATH, D>(buf, org, r);
+        int acc = dot_code<D>(r);
+        atomicAdd(hw + acc * 64, inc);
+    }
+}
+
+// Key order of the maximum: larger num first, then lower origin, then lower code.
+__device__ __forceinline__ bool better(uint64_t an, uint32_t ao, int32_t ac, uint64_t bn,
+                                       uint32_t bo, int32_t bc)
+{
+    if (an != bn) return an > bn;
+    if (ao != bo) return ao < bo;
+    return ac < bc;
+}
+
+__device__ __forceinline__ uint64_t score(uint32_t cp, uint32_t cq, int64_t n_p, int64_t n_q)
+{
+    int64_t a = (int64_t)cp * n_q - (int64_t)cq * n_p;
+    return (uint64_t)(a < 0 ? -a : a);
+}
+
+// Wave-wide arg-max of (num, origin, code) with the key order above.
+__device__ __forceinline__ void wave_best(uint64_t &n, uint32_t &o, int32_t &c)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t n2 = __shfl_xor(n, off, 64);
+        uint32_t o2 = __shfl_xor(o, off, 64);
+        int32_t c2 = __shfl_xor(c, off, 64);
+        if (better(n2, o2, c2, n, o, c)) {
+            n = n2;
+            o = o2;
+            c = c2;
+        }
+    }
+}
+
+// Block finish: thread (wave w, lane) owns bins j = w, w+W, ... of origin
+// group*64+lane; get(j) returns its (c_P, c_Q).  Scores every bin, writes the
+// counts if requested, reduces to the block's best.  scratch: >= W*64*16 bytes.
+template <int D, int W, typename Get>
+__device__ __forceinline__ void finish_block(Get get, int64_t group, int64_t N, int64_t n_p,
+                                             int64_t n_q, BlockBest *block_best,
+                                             uint32_t *counts, uint32_t *scratch)
+{
+    constexpr int BINS = Geo<D>::BINS;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t k = group * 64 + lane;
+    const bool valid = k < N;
+    uint64_t best = 0;
+    int32_t bcode = 0x7fffffff;
+    for (int j = w; j < BINS; j += W) {
+        uint2 c = get(j);
+        const int code = j ^ Geo<D>::FLIP;
+        uint64_t s = score(c.x, c.y, n_p, n_q);
+        if (s > best || (s == best && code < bcode)) {
+            best = s;
+            bcode = code;
+        }
+        if (counts && valid) {
+            *reinterpret_cast<uint2 *>(counts + ((size_t)k * BINS + code) * 2) = c;
+        }
+    }
+    __syncthreads();  // every read of the histograms is done; scratch may alias them
+    uint64_t *sn = reinterpret_cast<uint64_t *>(scratch);
+    int32_t *sc = reinterpret_cast<int32_t *>(scratch + 2 * W * 64);
+    sn[w * 64 + lane] = best;
+    sc[w * 64 + lane] = bcode;
+    __syncthreads();
+    if (w == 0) {
+        for (int v = 1; v < W; ++v) {
+            uint64_t n2 = sn[v * 64 + lane];
+            int32_t c2 = sc[v * 64 + lane];
+            if (n2 > best || (n2 == best && c2 < bcode)) {
+                best = n2;
+                bcode = c2;
+            }
+        }
+        uint32_t org = valid ? (uint32_t)k : 0xffffffffu;
+        if (!valid) {
+            best = 0;
+            bcode = 0x7fffffff;
+        }
+        wave_best(best, org, bcode);
+        if (lane == 0) {
+            BlockBest bb;
+            bb.num = best;
+            bb.origin = org;
+            bb.code = bcode;
+            block_best[group] = bb;
+        }
+    }
+}
+
+template <int D, int PATH, int W>
+__global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, int64_t N,
+                                                  int64_t n_p, int64_t n_q, int64_t chunk_len,
+                                                  int64_t groups, uint2 *__restrict__ partial,
+                                                  BlockBest *__restrict__ block_best,
+                                                  uint32_t *__restrict__ counts)
+{
+    typedef typename Layout<PATH, D>::T T;
+    constexpr int BINS = Geo<D>::BINS;
+    extern __shared__ uint32_t smem[];
+    const T *__restrict__ Z = static_cast<const T *>(Zv);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t group = blockIdx.x;
+    const int64_t chunk = blockIdx.y;
+
+    for (int i = threadIdx.x; i < W * BINS * 64; i += W * 64) smem[i] = 0;
+
+    int64_t k = group * 64 + lane;
+    Origin<PATH, D> org;
+    org.load(Z, k < N ? k : N - 1);
+    __syncthreads();
+
+    // This wave's share of the chunk's points.
+    const int64_t c0 = chunk * chunk_len;
+    const int64_t c1 = (c0 + chunk_len < N) ? c0 + chunk_len : N;
+    const int64_t per = (c1 - c0 + W - 1) / W;
+    int64_t a = c0 + (int64_t)w * per;
+    int64_t b = a + per;
+    if (a > c1) a = c1;
+    if (b > c1) b = c1;
+    a = __builtin_amdgcn_readfirstlane((int)(a - c0)) + c0;  // keep the range in SGPRs
+    b = __builtin_amdgcn_readfirstlane((int)(b - c0)) + c0;
+
+    uint32_t *hw = smem + (w * BINS + Geo<D>::KOFF) * 64 + lane;
+    sweep_range<PATH, D>(Z, a, b < n_p ? b : n_p, org, hw, 1u);
+    sweep_range<PATH, D>(Z, a > n_p ? a : n_p, b, org, hw, 0x10000u);
+    __syncthreads();
+
+    if (gridDim.y == 1) {
+        auto get = [&](int j) {
+            uint32_t cp = 0, cq = 0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) {
+                uint32_t h = smem[(v * BINS + j) * 64 + lane];
+                cp += h & 0xffffu;
+                cq += h >> 16;
+            }
+            return make_uint2(cp, cq);
+        };
+        finish_block<D, W>(get, group, N, n_p, n_q, block_best, counts, smem);
+    } else {
+        for (int j = w; j < BINS; j += W) {
+            uint32_t cp = 0, cq = 0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) {
+                uint32_t h = smem[(v * BINS + j) * 64 + lane];
+                cp += h & 0xffffu;
+                cq += h >> 16;
+            }
+            partial[((chunk * groups + group) * BINS + j) * 64 + lane] = make_uint2(cp, cq);
+        }
+    }
+}
+
+template <int D, int W>
+__global__ __launch_bounds__(W * 64) void k_score(int64_t N, int64_t n_p, int64_t n_q,
+                                                  int64_t chunks, int64_t groups,
+                                                  const uint2 *__restrict__ partial,
+                                                  BlockBest *__restrict__ block_best,
+                                                  uint32_t *__restrict__ counts)
+{
+    constexpr int BINS = Geo<D>::BINS;
+    __shared__ uint32_t scratch[W * 64 * 4];
+    const int lane = threadIdx.x & 63;
+    const int64_t group = blockIdx.x;
+    auto get = [&](int j) {
+        uint32_t cp = 0, cq = 0;
+        for (int64_t s = 0; s < chunks; ++s) {
+            uint2 c = partial[((s * groups + group) * BINS + j) * 64 + lane];
+            cp += c.x;
+            cq += c.y;
+        }
+        return make_uint2(cp, cq);
+    };
+    finish_block<D, W>(get, group, N, n_p, n_q, block_best, counts, scratch);
+}
+
+__global__ __launch_bounds__(1024) void k_reduce(const BlockBest *__restrict__ bb, int64_t n,
+                                                 uint32_t *__restrict__ flags,
+                                                 ResultDev *__restrict__ out)
+{
+    __shared__ uint64_t sn[16];
+    __shared__ uint32_t so[16];
+    __shared__ int32_t sc[16];
+    uint64_t best = 0;
+    uint32_t org = 0xffffffffu;
+    int32_t code = 0x7fffffff;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        BlockBest b = bb[i];
+        if (better(b.num, b.origin, b.code, best, org, code)) {
+            best = b.num;
+            org = b.origin;
+            code = b.code;
+        }
+    }
+    wave_best(best, org, code);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sn[w] = best;
+        so[w] = org;
+        sc[w] = code;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x >> 6); ++v) {
+            if (better(sn[v], so[v], sc[v], best, org, code)) {
+                best = sn[v];
+                org = so[v];
+                code = sc[v];
+            }
+        }
+        out->num = best;
+        out->origin = (int64_t)org;
+        out->code = code;
+        out->flags = *flags;
+        *flags = 0u;
+    }
+}
+
+__global__ void k_ingest_f32(const float *P, int64_t np_elems, const float *Q, int64_t total,
+                             float *Z, uint32_t *flags)
+{
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v = i < np_elems ? P[i] : Q[i - np_elems];
+        if (!__builtin_isfinite(v)) bad = 1u;
+        Z[i] = v + 0.0f;  // maps -0 to +0, leaves every other value (subnormals included) as is
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, 1u);
+}
+
+// ---------------------------------------------------------------- host side
+
+int point_words(int path, int d)
+{
+    if (path == PATH_F32) return d;
+    return d <= 2 ? 1 : (d <= 4 ? 2 : 4);
+}
+
+size_t sweep_lds_bytes(const SweepPlan &p)
+{
+    size_t hist = (size_t)p.waves * ((size_t)1 << p.d) * 64 * 4;
+    size_t fin = (size_t)p.waves * 64 * 16;
+    return hist > fin ? hist : fin;
+}
+
+int max_waves_for_d(int d)
+{
+    // 160 KB of LDS per CU; keep at least one block of histograms per CU.
+    size_t per_wave = ((size_t)1 << d) * 64 * 4;
+    int w = (int)((160 * 1024) / per_wave);
+    if (w > 16) w = 16;
+    if (w < 1) w = 1;
+    return w;
+}
+
+hipError_t launch_ingest_f32(const float *P, int64_t n_p, const float *Q, int64_t n_q, int d,
+                             float *Z, uint32_t *flags, hipStream_t s)
+{
+    int64_t total = (n_p + n_q) * d;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_ingest_f32, dim3((unsigned)blocks), dim3(256), 0, s, P, n_p * d, Q,
+                       total, Z, flags);
+    return hipGetLastError();
+}
+
+template <int D, int PATH, int W>
+static hipError_t launch_sweep_t(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p,
+                                 int64_t n_q, uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 hipStream_t s)
+{
+    size_t lds = sweep_lds_bytes(p);
+    static bool attr_set = false;
+    if (!attr_set && lds > 64 * 1024) {
+        // Raise the dynamic-LDS cap once; if the runtime refuses, the launch
+        // below reports the real error.
+        if (hipFuncSetAttribute((const void *)k_sweep<D, PATH, W>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            (void)hipGetLastError();
+        attr_set = true;
+    }
+    dim3 grid((unsigned)p.groups, (unsigned)p.chunks);
+    hipLaunchKernelGGL((k_sweep<D, PATH, W>), grid, dim3(W * 64), lds, s, Z, N, n_p, n_q,
+                       p.chunk_len, p.groups, partial, bb, counts);
+    return hipGetLastError();
+}
+
+template <int D, int PATH>
+static hipError_t launch_sweep_w(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p,
+                                 int64_t n_q, uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 hipStream_t s)
+{
+    switch (p.waves) {
+    case 1: return launch_sweep_t<D, PATH, 1>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 2: return launch_sweep_t<D, PATH, 2>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 4:
+        if constexpr (D <= 7)
+            return launch_sweep_t<D, PATH, 4>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+        else
+            return hipErrorInvalidValue;
+    case 8:
+        if constexpr (D <= 6)
+            return launch_sweep_t<D, PATH, 8>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+        else
+            return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PATH>
+static hipError_t launch_sweep_p(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p,
+                                 int64_t n_q, uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 hipStream_t s)
+{
+    switch (p.d) {
+    case 1: return launch_sweep_w<1, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 2: return launch_sweep_w<2, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 3: return launch_sweep_w<3, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 4: return launch_sweep_w<4, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 5: return launch_sweep_w<5, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 6: return launch_sweep_w<6, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 7: return launch_sweep_w<7, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 8: return launch_sweep_w<8, PATH>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p, int64_t n_q,
+                        uint2 *partial, BlockBest *bb, uint32_t *counts, hipStream_t s)
+{
+    if (p.groups < 1 || p.chunks < 1 || p.chunk_len < 1 ||
+        p.chunk_len > (int64_t)p.waves * 65535 || p.groups * 64 < N ||
+        p.chunks * p.chunk_len < N || p.groups > 0x7fffffff || p.chunks > 65535)
+        return hipErrorInvalidValue;
+    if (p.path == PATH_F32) return launch_sweep_p<PATH_F32>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    if (p.path == PATH_R16) return launch_sweep_p<PATH_R16>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    return hipErrorInvalidValue;
+}
+
+template <int D>
+static hipError_t launch_score_d(const SweepPlan &p, int64_t N, int64_t n_p, int64_t n_q,
+                                 const uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL((k_score<D, 4>), dim3((unsigned)p.groups), dim3(256), 0, s, N, n_p, n_q,
+                       p.chunks, p.groups, partial, bb, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(const SweepPlan &p, int64_t N, int64_t n_p, int64_t n_q,
+                        const uint2 *partial, BlockBest *bb, uint32_t *counts, hipStream_t s)
+{
+    switch (p.d) {
+    case 1: return launch_score_d<1>(p, N, n_p, n_q, partial, bb, counts, s);
+    case 2: return launch_score_d<2>(p, N, n_p, n_q, partial, bb, counts, s);
+    case 3: return launch_score_d<3>(p, N, n_p, n_q, partial, bb, counts, s);
+    case 4: return launch_score_d<4>(p, N, n_p, n_q, partial, bb, counts, s);
+    case 5: return launch_score_d<5>(p, N, n_p, n_q, partial, bb, counts, s);
+    case 6: return launch_score_d<6>(p, N, n_p, n_q, partial, bb, counts, s);
+    case 7: return launch_score_d<7>(p, N, n_p, n_q, partial, bb, counts, s);
+    case 8: return launch_score_d<8>(p, N, n_p, n_q, partial, bb, counts, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce(const BlockBest *bb, int64_t nblocks, uint32_t *flags, ResultDev *out,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bb, nblocks, flags, out);
+    return hipGetLastError();
+}
+
+}  // namespace ddks

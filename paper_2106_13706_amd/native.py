@@ -1,0 +1,301 @@
+"""ctypes binding of libddks.so (include/ddks.h): argument marshalling only.
+
+Every computation runs in the library's gfx950 kernels.  There is no CPU
+fallback: if libddks.so is missing or no gfx950 device is present the calls
+raise.  Inputs may be numpy arrays (host memory) or torch tensors on the
+context's device (passed as device pointers).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddks.so")
+
+DDKS_OK = 0
+DDKS_E_INVALID_ARG = -1
+DDKS_E_NO_DEVICE = -2
+DDKS_E_DEVICE = -3
+DDKS_E_NOMEM = -4
+DDKS_E_NONFINITE = -5
+DDKS_E_AGAIN = -6
+DDKS_E_PENDING = -7
+DDKS_E_UNKNOWN_TICKET = -8
+DDKS_E_NOT_SUPPORTED = -9
+
+DDKS_DEVICE_PTRS = 0x1
+DDKS_FORCE_F32 = 0x2
+DDKS_NO_AUTOTUNE = 0x4
+
+# Every symbol include/ddks.h declares.
+EXPORTS = (
+    "ddks_default_options", "ddks_create", "ddks_destroy", "ddks_distance",
+    "ddks_permutation_batch", "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
+    "ddks_serve_stats_get", "ddks_status_string", "ddks_last_error", "ddks_version",
+)
+
+
+class DDKSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("mem_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("serve_streams", ctypes.c_int32), ("serve_queue_depth", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("num", ctypes.c_uint64), ("den", ctypes.c_uint64), ("D", ctypes.c_double),
+                ("argmax_origin", ctypes.c_int64), ("argmax_orthant", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("n_p", ctypes.c_int64), ("n_q", ctypes.c_int64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_void_p), ("n_p", ctypes.c_int64), ("Q", ctypes.c_void_p),
+                ("n_q", ctypes.c_int64), ("d", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class _ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected_again", ctypes.c_uint64), ("rejected_nomem", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("p50_latency_us", ctypes.c_double),
+                ("p99_latency_us", ctypes.c_double), ("mean_batch", ctypes.c_double),
+                ("resident_bytes", ctypes.c_uint64)]
+
+
+@dataclass
+class Result:
+    num: int
+    den: int
+    D: float
+    argmax_origin: int
+    argmax_orthant: int
+    d: int
+    n_p: int
+    n_q: int
+
+    @classmethod
+    def _from(cls, r: _Result) -> "Result":
+        return cls(r.num, r.den, r.D, r.argmax_origin, r.argmax_orthant, r.d, r.n_p, r.n_q)
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libddks.so and declares its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libddks.so not found at {path}; build it with "
+                          "python -m paper_2106_13706_amd.build (or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, u32, u64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                              ctypes.c_uint64)
+    lib.ddks_default_options.argtypes = [ctypes.POINTER(_Options)]
+    lib.ddks_default_options.restype = None
+    lib.ddks_create.argtypes = [ctypes.POINTER(_Options), ctypes.POINTER(vp)]
+    lib.ddks_destroy.argtypes = [vp]
+    lib.ddks_distance.argtypes = [vp, vp, i64, vp, i64, i32, u32, ctypes.POINTER(_Result), vp]
+    lib.ddks_permutation_batch.argtypes = [vp, vp, i64, i32, i64, vp, i32, u32, vp,
+                                           ctypes.POINTER(_Result)]
+    lib.ddks_significance.argtypes = [vp, vp, i64, i64, i32, u64, u32,
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.ddks_serve_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(u64)]
+    lib.ddks_serve_poll.argtypes = [vp, u64, i32, ctypes.POINTER(_Result)]
+    lib.ddks_serve_stats_get.argtypes = [vp, ctypes.POINTER(_ServeStats), i32]
+    lib.ddks_status_string.argtypes = [ctypes.c_int]
+    lib.ddks_status_string.restype = ctypes.c_char_p
+    lib.ddks_last_error.argtypes = [vp]
+    lib.ddks_last_error.restype = ctypes.c_char_p
+    lib.ddks_version.restype = ctypes.c_char_p
+    for name in ("ddks_create", "ddks_destroy", "ddks_distance", "ddks_permutation_batch",
+                 "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
+                 "ddks_serve_stats_get"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _points(x, d=None):
+    """(pointer, rows, d, keepalive, is_device) for a numpy array or torch tensor."""
+    if _is_torch(x):
+        import torch
+        if x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError("torch inputs must be contiguous float32")
+        if not x.is_cuda:
+            return _points(x.numpy(), d)
+        t = x.reshape(x.shape[0], -1) if x.dim() > 1 else x.reshape(-1, 1)
+        return t.data_ptr(), t.shape[0], t.shape[1], t, True
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    return a.ctypes.data, a.shape[0], a.shape[1], a, False
+
+
+class Context:
+    """One libddks context (device, stream, buffers, serving loop)."""
+
+    def __init__(self, device: int = 0, stream=None, mem_budget: int = 0, flags: int = 0,
+                 serve_streams: int = 0, serve_queue_depth: int = 0, tune_cache: str | None = None):
+        self._lib = load()
+        o = _Options()
+        self._lib.ddks_default_options(ctypes.byref(o))
+        o.device = device
+        if stream is not None:
+            o.stream = stream if isinstance(stream, int) else stream.cuda_stream
+        o.mem_budget = mem_budget
+        o.flags = flags
+        o.serve_streams = serve_streams
+        o.serve_queue_depth = serve_queue_depth
+        self._cache = tune_cache.encode() if tune_cache else None
+        o.tune_cache = self._cache
+        h = ctypes.c_void_p()
+        st = self._lib.ddks_create(ctypes.byref(o), ctypes.byref(h))
+        if st != DDKS_OK:
+            raise DDKSError(st, "ddks_create failed: "
+                            + self._lib.ddks_status_string(st).decode())
+        self._h = h
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, st: int, what: str):
+        if st != DDKS_OK:
+            err = self._lib.ddks_last_error(self._h).decode()
+            raise DDKSError(st, f"{what}: {err or self._lib.ddks_status_string(st).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ddks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    # -------------------------------------------------------------- calls
+    def distance(self, P, Q, *, counts: bool = False, flags: int = 0):
+        """Exact ddKS of P and Q.  Returns Result, or (Result, counts[N, 2^d, 2])
+        when counts=True (a numpy array for host inputs, a torch int32 tensor
+        holding the uint32 bits for device inputs)."""
+        pp, n_p, d, kp, dev_p = _points(P)
+        qp, n_q, dq, kq, dev_q = _points(Q)
+        if d != dq:
+            raise ValueError("P and Q must have the same number of columns")
+        if dev_p != dev_q:
+            raise ValueError("P and Q must both be host arrays or both device tensors")
+        if dev_p:
+            flags |= DDKS_DEVICE_PTRS
+        cbuf = None
+        cptr = None
+        if counts:
+            N = n_p + n_q
+            if dev_p:
+                import torch
+                cbuf = torch.empty((N, 1 << d, 2), dtype=torch.int32, device=kp.device)
+                cptr = cbuf.data_ptr()
+            else:
+                cbuf = np.empty((N, 1 << d, 2), dtype=np.uint32)
+                cptr = cbuf.ctypes.data
+        r = _Result()
+        st = self._lib.ddks_distance(self._h, pp, n_p, qp, n_q, d, flags, ctypes.byref(r), cptr)
+        self._check(st, "ddks_distance")
+        res = Result._from(r)
+        return (res, cbuf) if counts else res
+
+    def permutation_batch(self, Z, n_p: int, labels, *, observed: bool = True, flags: int = 0):
+        """Numerators for every relabelling row (labels: [B, ceil(n/32)] uint32
+        words) and, if observed, the Result of the split 'first n_p rows'."""
+        zp, n, d, kz, dev = _points(Z)
+        if dev:
+            flags |= DDKS_DEVICE_PTRS
+            import torch
+            L = labels
+            if not (_is_torch(L) and L.is_cuda):
+                raise ValueError("with device points, labels must be a device tensor")
+            B = L.shape[0]
+            lp = L.data_ptr()
+            nums = torch.empty(B, dtype=torch.int64, device=kz.device)
+            nptr = nums.data_ptr()
+        else:
+            L = np.ascontiguousarray(labels, dtype=np.uint32)
+            B = L.shape[0]
+            lp = L.ctypes.data
+            nums = np.empty(B, dtype=np.uint64)
+            nptr = nums.ctypes.data
+        r = _Result()
+        st = self._lib.ddks_permutation_batch(self._h, zp, n, d, n_p, lp, B, flags, nptr,
+                                              ctypes.byref(r) if observed else None)
+        self._check(st, "ddks_permutation_batch")
+        return nums, (Result._from(r) if observed else None)
+
+    def significance(self, counts, n_p: int, n_q: int, d: int, num: int, *, flags: int = 0):
+        if _is_torch(counts) and counts.is_cuda:
+            flags |= DDKS_DEVICE_PTRS
+            cp = counts.data_ptr()
+            keep = counts
+        else:
+            keep = np.ascontiguousarray(counts, dtype=np.uint32)
+            cp = keep.ctypes.data
+        S = ctypes.c_double()
+        st = self._lib.ddks_significance(self._h, cp, n_p, n_q, d, num, flags, ctypes.byref(S))
+        self._check(st, "ddks_significance")
+        return S.value
+
+    def serve_submit(self, P, Q) -> int:
+        pp, n_p, d, kp, dev_p = _points(P)
+        qp, n_q, dq, kq, dev_q = _points(Q)
+        if dev_p or dev_q:
+            raise ValueError("serving takes host arrays")
+        if d != dq:
+            raise ValueError("P and Q must have the same number of columns")
+        req = _Request(pp, n_p, qp, n_q, d, 0)
+        t = ctypes.c_uint64()
+        st = self._lib.ddks_serve_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if st == DDKS_E_AGAIN:
+            return -1
+        self._check(st, "ddks_serve_submit")
+        return t.value
+
+    def serve_poll(self, ticket: int, timeout_us: int = -1):
+        """Result, or None if still pending after timeout_us."""
+        r = _Result()
+        st = self._lib.ddks_serve_poll(self._h, ticket, timeout_us, ctypes.byref(r))
+        if st == DDKS_E_PENDING:
+            return None
+        self._check(st, "ddks_serve_poll")
+        return Result._from(r)
+
+    def serve_stats(self, reset: bool = False) -> dict:
+        s = _ServeStats()
+        st = self._lib.ddks_serve_stats_get(self._h, ctypes.byref(s), 1 if reset else 0)
+        self._check(st, "ddks_serve_stats_get")
+        return {k: getattr(s, k) for k, _ in _ServeStats._fields_}
+
+
+def version() -> str:
+    return load().ddks_version().decode()

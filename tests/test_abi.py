@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI: the library builds, loads and exports every
+symbol include/ddks.h declares; calls that need a device fail cleanly
+without one.  CPU only (no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddks.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddks_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2106_13706_amd import native
+    if not os.path.exists(native.LIB_PATH):
+        from paper_2106_13706_amd import build
+        build.build(force=False)
+    return native.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_2106_13706_amd import native
+    names = _declared()
+    assert len(names) >= 12
+    assert set(names) == set(native.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ddks_[a-z0-9_]+)$", out, flags=re.M))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_status_strings_and_version(lib):
+    from paper_2106_13706_amd import native
+    assert lib.ddks_status_string(0) == b"ok"
+    assert lib.ddks_status_string(native.DDKS_E_NONFINITE) == b"non-finite input value"
+    assert lib.ddks_status_string(12345) == b"unknown status"
+    assert b"gfx950" in lib.ddks_version()
+
+
+def test_null_arguments_rejected(lib):
+    from paper_2106_13706_amd import native
+    assert lib.ddks_create(None, None) == native.DDKS_E_INVALID_ARG
+    assert lib.ddks_destroy(None) == 0
+    r = native._Result()
+    assert lib.ddks_distance(None, None, 1, None, 1, 2, 0, ctypes.byref(r), None) == \
+        native.DDKS_E_INVALID_ARG
+    assert lib.ddks_last_error(None) == b""
+
+
+def test_create_without_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2106_13706_amd import native
+    h = ctypes.c_void_p()
+    assert lib.ddks_create(None, ctypes.byref(h)) == native.DDKS_E_NO_DEVICE
+    with pytest.raises(native.DDKSError):
+        native.Context()

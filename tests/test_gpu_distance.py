@@ -1,0 +1,195 @@
+"""GPU parity of ddks_distance against the CPU oracle: counts, num, den, D
+and argmax bit-for-bit (integer results; tolerance 0).  Needs an MI355X."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _ctx(**env):
+    from paper_2106_13706_amd import native
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return native.Context()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _ctx()
+    yield c
+    c.close()
+
+
+def check(ctx, oracle_mod, P, Q, counts=True, flags=0):
+    print(f"  case n_p={len(P)} n_q={len(Q)} d={P.shape[1]}", flush=True)
+    if counts:
+        r, c = ctx.distance(P, Q, counts=True, flags=flags)
+    else:
+        r = ctx.distance(P, Q, flags=flags)
+    o = oracle_mod.distance(P, Q, counts=counts, threads=THREADS)
+    assert (r.num, r.den, r.argmax_origin, r.argmax_orthant) == (
+        o.num, o.den, o.argmax_origin, o.argmax_orthant)
+    assert r.D == o.D
+    if counts:
+        np.testing.assert_array_equal(c, o.counts)
+    return r
+
+
+@pytest.mark.parametrize("name", ["example_a.json", "example_b.json", "example_c.json"])
+def test_worked_examples(ctx, oracle_mod, name):
+    g = json.load(open(os.path.join(GOLDEN, name)))
+    P = np.array(g["P"], np.float32)
+    Q = np.array(g["Q"], np.float32)
+    r = check(ctx, oracle_mod, P, Q)
+    assert (r.num, r.den) == (g["num"], g["den"])
+
+
+SIZES = [(1, 1), (1, 2), (3, 5), (63, 1), (64, 64), (65, 63), (100, 37), (300, 211),
+         (1000, 1), (777, 1234)]
+
+
+@pytest.mark.parametrize("d", range(1, 9))
+def test_random_sizes_all_d(ctx, oracle_mod, d):
+    g = np.random.default_rng(1000 + d)
+    for n_p, n_q in SIZES:
+        P = g.standard_normal((n_p, d)).astype(np.float32)
+        Q = (g.standard_normal((n_q, d)) * 1.1 + 0.2).astype(np.float32)
+        check(ctx, oracle_mod, P, Q)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8])
+def test_ties_and_signed_zero(ctx, oracle_mod, d):
+    g = np.random.default_rng(77 + d)
+    P = g.integers(-2, 3, size=(301, d)).astype(np.float32)
+    Q = g.integers(-1, 3, size=(257, d)).astype(np.float32)
+    P[g.random(P.shape) < 0.3] = -0.0
+    Q[g.random(Q.shape) < 0.2] = -0.0
+    assert np.signbit(P).any() and np.signbit(Q).any()
+    check(ctx, oracle_mod, P, Q)
+
+
+def test_subnormals_and_extremes(ctx, oracle_mod):
+    tiny = np.float32(1e-45)
+    vals = np.array([0.0, -0.0, tiny, -tiny, 2 * tiny, 1e-40, -1e-40, 1.1754942e-38,
+                     1.1754944e-38, 3.4028235e38, -3.4028235e38, 1.0, -1.0], np.float32)
+    g = np.random.default_rng(5)
+    for d in (1, 2, 4, 7):
+        P = g.choice(vals, size=(150, d)).astype(np.float32)
+        Q = g.choice(vals, size=(170, d)).astype(np.float32)
+        check(ctx, oracle_mod, P, Q)
+
+
+@pytest.mark.parametrize("waves,chunks", [(1, 1), (2, 3), (4, 1), (4, 7), (8, 2), (8, 1)])
+def test_launch_shapes(oracle_mod, waves, chunks):
+    c = _ctx(DDKS_FORCE_WAVES=waves, DDKS_FORCE_CHUNKS=chunks)
+    try:
+        g = np.random.default_rng(waves * 10 + chunks)
+        for d in (2, 4, 6):
+            P = np.rint(g.standard_normal((2345, d)) * 4).astype(np.float32)
+            Q = np.rint(g.standard_normal((1999, d)) * 4 + 0.5).astype(np.float32)
+            check(c, oracle_mod, P, Q)
+    finally:
+        c.close()
+
+
+def test_nonfinite_rejected(ctx):
+    from paper_2106_13706_amd import native
+    P = np.zeros((10, 3), np.float32)
+    Q = np.ones((10, 3), np.float32)
+    for bad in (np.nan, np.inf, -np.inf):
+        P2 = P.copy()
+        P2[4, 1] = bad
+        with pytest.raises(native.DDKSError) as e:
+            ctx.distance(P2, Q)
+        assert e.value.status == native.DDKS_E_NONFINITE
+    # the context keeps working after a rejected call
+    assert ctx.distance(P, Q).num == 100
+
+
+def test_invalid_arguments(ctx):
+    from paper_2106_13706_amd import native
+    with pytest.raises(native.DDKSError) as e:
+        ctx.distance(np.zeros((3, 9), np.float32), np.zeros((3, 9), np.float32))
+    assert e.value.status == native.DDKS_E_INVALID_ARG
+    with pytest.raises(native.DDKSError) as e:
+        ctx.distance(np.zeros((0, 2), np.float32), np.zeros((3, 2), np.float32))
+    assert e.value.status == native.DDKS_E_INVALID_ARG
+
+
+def test_device_pointers(oracle_mod):
+    import torch
+    from paper_2106_13706_amd import native
+    s = torch.cuda.current_stream()
+    c = native.Context(stream=s)
+    try:
+        g = np.random.default_rng(3)
+        P = g.standard_normal((1500, 4)).astype(np.float32)
+        Q = g.standard_normal((1700, 4)).astype(np.float32)
+        Pt = torch.from_numpy(P).cuda()
+        Qt = torch.from_numpy(Q).cuda()
+        r, cnt = c.distance(Pt, Qt, counts=True)
+        o = oracle_mod.distance(P, Q, counts=True, threads=THREADS)
+        assert (r.num, r.argmax_origin, r.argmax_orthant) == (o.num, o.argmax_origin,
+                                                              o.argmax_orthant)
+        np.testing.assert_array_equal(cnt.cpu().numpy().view(np.uint32), o.counts)
+    finally:
+        c.close()
+
+
+# ------------------------------------------------------------- the workloads
+
+def test_workload_gaussian_shift_d3_500(ctx, oracle_mod):
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.gaussian_shift()
+    check(ctx, oracle_mod, P, Q)
+
+
+def test_workload_gaussian_scale_d4_20000(ctx, oracle_mod):
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.gaussian_scale()
+    check(ctx, oracle_mod, P, Q)
+
+
+def test_workload_mixture_grid_d6_scaled(ctx, oracle_mod):
+    """Same recipe as the 100000-point workload at 1/10 the size: full parity."""
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.mixture_grid(n_p=10000, n_q=10000)
+    assert np.signbit(P).any()
+    check(ctx, oracle_mod, P, Q)
+
+
+def test_workload_mixture_grid_d6_100000_sampled(ctx, oracle_mod):
+    """Full size: counts at sampled origins against the oracle, and properties
+    that hold at any size for the rest (count partition, self-count, the
+    reported maximum is the maximum of the returned counts, symmetry)."""
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.mixture_grid()
+    n_p, n_q = len(P), len(Q)
+    N = n_p + n_q
+    r, c = ctx.distance(P, Q, counts=True)
+    g = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([g.integers(0, N, 48), [0, n_p - 1, n_p, N - 1,
+                                                            r.argmax_origin]]))
+    np.testing.assert_array_equal(c[idx], oracle_mod.origin_counts(P, Q, idx))
+    assert (c[:, :, 0].sum(axis=1, dtype=np.int64) == n_p).all()
+    assert (c[:, :, 1].sum(axis=1, dtype=np.int64) == n_q).all()
+    assert (c[:n_p, -1, 0] >= 1).all() and (c[n_p:, -1, 1] >= 1).all()
+    s = np.abs(c[:, :, 0].astype(np.int64) * n_q - c[:, :, 1].astype(np.int64) * n_p)
+    flat = int(np.argmax(s.reshape(-1)))
+    assert int(s.reshape(-1)[flat]) == r.num
+    assert divmod(flat, s.shape[1]) == (r.argmax_origin, r.argmax_orthant)
+    r2 = ctx.distance(Q, P)
+    assert r2.num == r.num and r2.den == r.den

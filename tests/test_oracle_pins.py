@@ -271,3 +271,14 @@ def test_argmax_is_first_maximiser(oracle_mod):
     flat = int(np.argmax(s.reshape(-1)))  # numpy argmax returns the first maximiser
     assert (r.argmax_origin, r.argmax_orthant) == divmod(flat, s.shape[1])
     np.testing.assert_array_equal(r.origin_num, s.max(axis=1).astype(np.uint64))
+
+
+def test_origin_counts_subset_matches_full(oracle_mod):
+    g = np.random.default_rng(21)
+    P = np.rint(g.standard_normal((40, 3)) * 3).astype(np.float32)
+    Q = np.rint(g.standard_normal((31, 3)) * 3).astype(np.float32)
+    full = oracle_mod.distance(P, Q, counts=True).counts
+    idx = np.array([0, 5, 39, 40, 70, 12])
+    np.testing.assert_array_equal(oracle_mod.origin_counts(P, Q, idx), full[idx])
+    num, _, MP, MQ = ddks_tensor(P, Q)
+    np.testing.assert_array_equal(oracle_mod.origin_counts(P, Q, idx)[:, :, 1], MQ[idx])
