@@ -72,20 +72,93 @@ __host__ __device__ constexpr uint32_t dot_wts(int D, int q)
     return w;
 }
 
-// sign(x - o) of two fp32 dimensions into bits 15 and 31.
-__device__ __forceinline__ uint32_t sgn2_f32(float x0, float o0, float x1, float o1)
-{
-    uint32_t r;
-    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,0]" : "=v"(r) : "s"(x0), "v"(o0));
-    asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,0]" : "+v"(r) : "s"(x1), "v"(o1));
-    return r;
-}
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-__device__ __forceinline__ uint32_t sgn1_f32(float x0, float o0)
+// ---------------------------------------------------------------------------
+// Inline-asm building blocks.  Two gfx950 pipeline hazards are invisible to
+// the compiler inside asm, so each asm block carries a whole dependent chain
+// with the spacing built in:
+//  * v_fma_mix{lo,hi}_f16 write half a VGPR; a read of that VGPR needs one
+//    intervening instruction (the compiler already pads after any asm block
+//    before its own VALU reads).
+//  * a v_dot4 result needs three intervening instructions before a VALU reads
+//    it; the dots of four points are issued back to back, then their address
+//    computations, so every read is at least three instructions later.
+// ---------------------------------------------------------------------------
+
+#define MIXLO(d, x, o) "v_fma_mixlo_f16 " d ", " x ", 1.0, -" o " op_sel_hi:[0,0,0]\n\t"
+#define MIXHI(d, x, o) "v_fma_mixhi_f16 " d ", " x ", 1.0, -" o " op_sel_hi:[0,0,0]\n\t"
+
+// Sign registers of one fp32 point: register p holds sign(x_{2p} - o_{2p}) in
+// bit 15 and sign(x_{2p+1} - o_{2p+1}) in bit 31 (bit 31 undefined when 2p+1 = D).
+template <int D>
+__device__ __forceinline__ void signs_f32(const float *x, const float *o, uint32_t (&r)[Geo<D>::NREG]);
+
+template <>
+__device__ __forceinline__ void signs_f32<1>(const float *x, const float *o, uint32_t (&r)[1])
 {
-    uint32_t r;
-    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,0]" : "=v"(r) : "s"(x0), "v"(o0));
-    return r;
+    asm(MIXLO("%0", "%1", "%2") : "=v"(r[0]) : "s"(x[0]), "v"(o[0]));
+}
+template <>
+__device__ __forceinline__ void signs_f32<2>(const float *x, const float *o, uint32_t (&r)[1])
+{
+    asm(MIXLO("%0", "%1", "%2") "s_nop 0\n\t" MIXHI("%0", "%3", "%4")
+        : "=&v"(r[0]) : "s"(x[0]), "v"(o[0]), "s"(x[1]), "v"(o[1]));
+}
+template <>
+__device__ __forceinline__ void signs_f32<3>(const float *x, const float *o, uint32_t (&r)[2])
+{
+    asm(MIXLO("%0", "%2", "%3") MIXLO("%1", "%4", "%5") MIXHI("%0", "%6", "%7")
+        : "=&v"(r[0]), "=&v"(r[1])
+        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[1]), "v"(o[1]));
+}
+template <>
+__device__ __forceinline__ void signs_f32<4>(const float *x, const float *o, uint32_t (&r)[2])
+{
+    asm(MIXLO("%0", "%2", "%3") MIXLO("%1", "%4", "%5") MIXHI("%0", "%6", "%7")
+            MIXHI("%1", "%8", "%9")
+        : "=&v"(r[0]), "=&v"(r[1])
+        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[1]), "v"(o[1]), "s"(x[3]),
+          "v"(o[3]));
+}
+template <>
+__device__ __forceinline__ void signs_f32<5>(const float *x, const float *o, uint32_t (&r)[3])
+{
+    asm(MIXLO("%0", "%3", "%4") MIXLO("%1", "%5", "%6") MIXLO("%2", "%7", "%8")
+            MIXHI("%0", "%9", "%10") MIXHI("%1", "%11", "%12")
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
+        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[1]),
+          "v"(o[1]), "s"(x[3]), "v"(o[3]));
+}
+template <>
+__device__ __forceinline__ void signs_f32<6>(const float *x, const float *o, uint32_t (&r)[3])
+{
+    asm(MIXLO("%0", "%3", "%4") MIXLO("%1", "%5", "%6") MIXLO("%2", "%7", "%8")
+            MIXHI("%0", "%9", "%10") MIXHI("%1", "%11", "%12") MIXHI("%2", "%13", "%14")
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
+        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[1]),
+          "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]));
+}
+template <>
+__device__ __forceinline__ void signs_f32<7>(const float *x, const float *o, uint32_t (&r)[4])
+{
+    asm(MIXLO("%0", "%4", "%5") MIXLO("%1", "%6", "%7") MIXLO("%2", "%8", "%9")
+            MIXLO("%3", "%10", "%11") MIXHI("%0", "%12", "%13") MIXHI("%1", "%14", "%15")
+                MIXHI("%2", "%16", "%17")
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
+        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[6]),
+          "v"(o[6]), "s"(x[1]), "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]));
+}
+template <>
+__device__ __forceinline__ void signs_f32<8>(const float *x, const float *o, uint32_t (&r)[4])
+{
+    asm(MIXLO("%0", "%4", "%5") MIXLO("%1", "%6", "%7") MIXLO("%2", "%8", "%9")
+            MIXLO("%3", "%10", "%11") MIXHI("%0", "%12", "%13") MIXHI("%1", "%14", "%15")
+                MIXHI("%2", "%16", "%17") MIXHI("%3", "%18", "%19")
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
+        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[6]),
+          "v"(o[6]), "s"(x[1]), "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]),
+          "s"(x[7]), "v"(o[7]));
 }
 
 // sign(x - o) of two rank-encoded dimensions (int16, saturating) into bits 15 and 31.
@@ -96,19 +169,61 @@ __device__ __forceinline__ uint32_t sgn2_r16(uint32_t x, uint32_t o)
     return __builtin_bit_cast(uint32_t, t);
 }
 
-// -(sum over dimensions with x_m < o_m of their weights), from the sign registers.
+// Sign-filled bytes of perm group q (v_perm_b32 sign selectors).
 template <int D>
-__device__ __forceinline__ int dot_code(const uint32_t (&r)[Geo<D>::NREG])
+__device__ __forceinline__ uint32_t group_bytes(const uint32_t (&r)[Geo<D>::NREG], int q)
 {
     constexpr int NR = Geo<D>::NREG;
-    uint32_t R0 = __builtin_amdgcn_perm(NR > 1 ? r[NR > 1 ? 1 : 0] : 0u, r[0], perm_sel(D, 0));
-    int acc;
-    asm("v_dot4_i32_i8 %0, %1, %2, 0" : "=v"(acc) : "v"(R0), "s"(dot_wts(D, 0)));
-    if constexpr (Geo<D>::NPERM > 1) {
-        uint32_t R1 = __builtin_amdgcn_perm(NR > 3 ? r[NR > 3 ? 3 : 2] : 0u, r[2], perm_sel(D, 1));
-        asm("v_dot4_i32_i8 %0, %1, %2, %3" : "=v"(acc) : "v"(R1), "s"(dot_wts(D, 1)), "v"(acc));
+    if (q == 0) return __builtin_amdgcn_perm(NR > 1 ? r[NR > 1 ? 1 : 0] : 0u, r[0], perm_sel(D, 0));
+    return __builtin_amdgcn_perm(NR > 3 ? r[NR > 3 ? 3 : 2] : 0u, r[NR > 2 ? 2 : 0], perm_sel(D, 1));
+}
+
+#define DOT0(d, r, w) "v_dot4_i32_i8 " d ", " r ", " w ", 0\n\t"
+#define DOTC(d, r, w) "v_dot4_i32_i8 " d ", " r ", " w ", " d "\n\t"
+#define ADDR(d, b) "v_lshl_add_u32 " d ", " d ", 8, " b "\n\t"
+
+// LDS byte addresses of the bins of four points: base + 256 * (dot-sum).
+template <int NPERM>
+__device__ __forceinline__ void addr4(const uint32_t (&R)[2][4], uint32_t base, uint32_t (&a)[4],
+                                      uint32_t w0, uint32_t w1)
+{
+    if constexpr (NPERM == 1) {
+        asm(DOT0("%0", "%4", "%8") DOT0("%1", "%5", "%8") DOT0("%2", "%6", "%8")
+                DOT0("%3", "%7", "%8") ADDR("%0", "%9") ADDR("%1", "%9") ADDR("%2", "%9")
+                    ADDR("%3", "%9")
+            : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3])
+            : "v"(R[0][0]), "v"(R[0][1]), "v"(R[0][2]), "v"(R[0][3]), "s"(w0), "v"(base));
+    } else {
+        asm(DOT0("%0", "%4", "%12") DOT0("%1", "%5", "%12") DOT0("%2", "%6", "%12")
+                DOT0("%3", "%7", "%12") DOTC("%0", "%8", "%13") DOTC("%1", "%9", "%13")
+                    DOTC("%2", "%10", "%13") DOTC("%3", "%11", "%13") ADDR("%0", "%14")
+                        ADDR("%1", "%14") ADDR("%2", "%14") ADDR("%3", "%14")
+            : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3])
+            : "v"(R[0][0]), "v"(R[0][1]), "v"(R[0][2]), "v"(R[0][3]), "v"(R[1][0]),
+              "v"(R[1][1]), "v"(R[1][2]), "v"(R[1][3]), "s"(w0), "s"(w1), "v"(base));
     }
-    return acc;
+}
+
+// The same for a single point, with the wait states written out.
+template <int NPERM>
+__device__ __forceinline__ uint32_t addr1(uint32_t R0, uint32_t R1, uint32_t base, uint32_t w0,
+                                          uint32_t w1)
+{
+    uint32_t a;
+    if constexpr (NPERM == 1) {
+        asm(DOT0("%0", "%1", "%2") "s_nop 2\n\t" ADDR("%0", "%3")
+            : "=&v"(a) : "v"(R0), "s"(w0), "v"(base));
+    } else {
+        asm(DOT0("%0", "%1", "%3") "s_nop 2\n\t" DOTC("%0", "%2", "%4") "s_nop 2\n\t" ADDR("%0", "%5")
+            : "=&v"(a) : "v"(R0), "v"(R1), "s"(w0), "s"(w1), "v"(base));
+    }
+    return a;
+}
+
+__device__ __forceinline__ void lds_add(uint32_t byte_addr, uint32_t v)
+{
+    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)byte_addr, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Point element type and words per point for each path.
@@ -125,11 +240,12 @@ struct Layout<PATH_R16, D> {
     static constexpr int PW = (D <= 2) ? 1 : (D <= 4 ? 2 : 4);  // padded to a power of two
 };
 
-// Points per unrolled block: about 32 scalar registers of point data.
+// Points per unrolled block: a multiple of four, about 32 scalar registers of point data.
 template <int PATH, int D>
 struct Unroll {
     static constexpr int PW = Layout<PATH, D>::PW;
-    static constexpr int U = (32 / PW) < 1 ? 1 : (32 / PW);
+    static constexpr int U0 = ((32 / PW) / 4) * 4;
+    static constexpr int U = U0 < 4 ? 4 : U0;
 };
 
 // The origin held by a lane.
@@ -161,13 +277,7 @@ __device__ __forceinline__ void signs(const typename Layout<PATH, D>::T *xs,
                                       const Origin<PATH, D> &org, uint32_t (&r)[Geo<D>::NREG])
 {
     if constexpr (PATH == PATH_F32) {
-#pragma unroll
-        for (int p = 0; p < Geo<D>::NREG; ++p) {
-            if (2 * p + 1 < D)
-                r[p] = sgn2_f32(xs[2 * p], org.o[2 * p], xs[2 * p + 1], org.o[2 * p + 1]);
-            else
-                r[p] = sgn1_f32(xs[2 * p], org.o[2 * p]);
-        }
+        signs_f32<D>(xs, org.o, r);
     } else {
 #pragma unroll
         for (int p = 0; p < Geo<D>::NREG; ++p) r[p] = sgn2_r16(xs[p], org.o[p]);
@@ -175,15 +285,17 @@ __device__ __forceinline__ void signs(const typename Layout<PATH, D>::T *xs,
 }
 
 // Sweeps points [lo, hi) of Z against the lane's origin, adding inc to the
-// lane's bin of each point.  hw points at bin KOFF of this lane's column.
+// lane's bin of each point.  base: LDS byte address of bin KOFF of this lane.
 template <int PATH, int D>
 __device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *__restrict__ Z,
                                             int64_t lo, int64_t hi, const Origin<PATH, D> &org,
-                                            uint32_t *hw, uint32_t inc)
+                                            uint32_t base, uint32_t inc)
 {
     typedef typename Layout<PATH, D>::T T;
     constexpr int PW = Layout<PATH, D>::PW;
     constexpr int U = Unroll<PATH, D>::U;
+    constexpr int NP = Geo<D>::NPERM;
+    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
     int64_t i = lo;
     for (; i + U <= hi; i += U) {
         const T *blk = Z + i * PW;
@@ -191,11 +303,19 @@ __device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *_
 #pragma unroll
         for (int e = 0; e < U * PW; ++e) buf[e] = blk[e];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            uint32_t r[Geo<D>::NREG];
-            signs<PATH, D>(buf + u * PW, org, r);
-            int acc = dot_code<D>(r);
-            atomicAdd(hw + acc * 64, inc);
+        for (int g = 0; g < U; g += 4) {
+            uint32_t R[2][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint32_t r[Geo<D>::NREG];
+                signs<PATH, D>(buf + (g + u) * PW, org, r);
+                R[0][u] = group_bytes<D>(r, 0);
+                R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+            }
+            uint32_t a[4];
+            addr4<NP>(R, base, a, w0, w1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) lds_add(a[u], inc);
         }
     }
     for (; i < hi; ++i) {
@@ -205,8 +325,9 @@ __device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *_
         for (int e = 0; e < PW; ++e) buf[e] = xs[e];
         uint32_t r[Geo<D>::NREG];
         signs<PATH, D>(buf, org, r);
-        int acc = dot_code<D>(r);
-        atomicAdd(hw + acc * 64, inc);
+        uint32_t R0 = group_bytes<D>(r, 0);
+        uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+        lds_add(addr1<NP>(R0, R1, base, w0, w1), inc);
     }
 }
 
@@ -333,9 +454,10 @@ __global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, i
     a = __builtin_amdgcn_readfirstlane((int)(a - c0)) + c0;  // keep the range in SGPRs
     b = __builtin_amdgcn_readfirstlane((int)(b - c0)) + c0;
 
-    uint32_t *hw = smem + (w * BINS + Geo<D>::KOFF) * 64 + lane;
-    sweep_range<PATH, D>(Z, a, b < n_p ? b : n_p, org, hw, 1u);
-    sweep_range<PATH, D>(Z, a > n_p ? a : n_p, b, org, hw, 0x10000u);
+    const uint32_t base =
+        (uint32_t)(uintptr_t)(lds_u32 *)(smem + (w * BINS + Geo<D>::KOFF) * 64 + lane);
+    sweep_range<PATH, D>(Z, a, b < n_p ? b : n_p, org, base, 1u);
+    sweep_range<PATH, D>(Z, a > n_p ? a : n_p, b, org, base, 0x10000u);
     __syncthreads();
 
     if (gridDim.y == 1) {

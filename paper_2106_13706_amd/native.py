@@ -98,6 +98,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libddks.so not found at {path}; build it with "
                           "python -m paper_2106_13706_amd.build (or __graft_entry__.build())")
+    # torch ships its own HIP runtime (same sonames as /opt/rocm's).  Loading it
+    # first makes libddks bind to that one copy, so torch and libddks share a
+    # single HIP runtime in the process; two runtimes cannot both open the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i64, i32, u32, u64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                               ctypes.c_uint64)
