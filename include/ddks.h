@@ -56,7 +56,9 @@ typedef enum ddks_status {
 /* ddks_options.flags and per-call flags */
 #define DDKS_DEVICE_PTRS 0x1u   /* pointer arguments are device memory */
 #define DDKS_FORCE_F32 0x2u     /* per call: skip the 16-bit rank encoding, compare raw fp32 */
+#define DDKS_FORCE_RANK16 0x10u /* per call: use the rank encoding even for small inputs */
 #define DDKS_NO_AUTOTUNE 0x4u   /* ctx option: use the built-in launch heuristics only */
+#define DDKS_PROFILE_KERNELS 0x8u /* ctx option: time the sweep kernels with HIP events */
 
 typedef struct ddks_ctx ddks_ctx;
 
@@ -174,6 +176,24 @@ int ddks_serve_poll(ddks_ctx *ctx, uint64_t ticket, int32_t timeout_us, ddks_res
 /* Counters and latency percentiles of the serving loop since the context was created
  * (or since the last reset when reset != 0). */
 int ddks_serve_stats_get(ddks_ctx *ctx, ddks_serve_stats *out, int32_t reset);
+
+/* ---------------------------------------------------------------- profiling */
+
+typedef struct ddks_profile {
+    uint64_t sweeps;      /* sweep launches timed */
+    double sweep_ms;      /* summed device time of the orthant-counting sweep kernel */
+    double score_ms;      /* summed device time of the partial-count scoring kernel */
+    double batch_ms;      /* summed device time of the permutation kernel */
+    uint64_t compares;    /* origin*point*dim compares those sweeps evaluated */
+} ddks_profile;
+
+/*
+ * Device-time counters, recorded with HIP events on the context's stream
+ * around each kernel launch when the context was created with
+ * DDKS_PROFILE_KERNELS (all zero otherwise).  reset != 0 clears them after
+ * reading.  Errors: DDKS_E_INVALID_ARG.
+ */
+int ddks_profile_get(ddks_ctx *ctx, ddks_profile *out, int32_t reset);
 
 /* ---------------------------------------------------------------- misc */
 

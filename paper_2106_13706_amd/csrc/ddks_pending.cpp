@@ -8,7 +8,6 @@ struct Tuner {};
 Tuner *tuner_create(const char *) { return nullptr; }
 void tuner_destroy(Tuner *) {}
 bool tuner_lookup(Tuner *, int, int, int64_t, SweepPlan *) { return false; }
-int encode_rank16(ddks_ctx *, int64_t, int, bool *ok) { *ok = false; return DDKS_OK; }
 int serve_start(ddks_ctx *) { return DDKS_E_NOT_SUPPORTED; }
 void serve_stop(ddks_ctx *) {}
 }  // namespace ddks

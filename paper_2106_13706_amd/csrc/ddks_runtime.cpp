@@ -107,9 +107,37 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool /*want_counts*/
     return p;
 }
 
-int choose_path(ddks_ctx * /*c*/, int /*d*/, int64_t /*N*/, uint32_t /*flags*/)
+int choose_path(ddks_ctx * /*c*/, int /*d*/, int64_t N, uint32_t flags)
 {
-    return PATH_F32;
+    if (flags & DDKS_FORCE_F32) return PATH_F32;
+    if (flags & DDKS_FORCE_RANK16) return PATH_R16;
+    // The encoding costs a few small launches; it pays once the O(N^2) sweep
+    // dominates.
+    return N >= 8192 ? PATH_R16 : PATH_F32;
+}
+
+int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok)
+{
+    *ok = false;
+    const int pw = point_words(PATH_R16, d);
+    int st = ensure(c, c->zr, (size_t)N * pw * sizeof(uint32_t), "rank encoding");
+    if (st) return st;
+    st = ensure(c, c->rank_scratch, rank16_scratch_bytes(N, d), "rank scratch");
+    if (st) return st;
+    st = hip_check(c, launch_rank16((const float *)c->z.ptr, N, d, (uint32_t *)c->zr.ptr,
+                                    c->rank_scratch.ptr, c->rank_distinct_dev, c->stream),
+                   "rank launch");
+    if (st) return st;
+    if (N <= 65536) {
+        *ok = true;  // at most N distinct values per dimension
+        return DDKS_OK;
+    }
+    st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, c->rank_distinct_dev, sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, c->stream), "D2H distinct count");
+    if (!st) st = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (st) return st;
+    *ok = *c->rank_distinct_host <= 65536u;
+    return DDKS_OK;
 }
 
 int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
@@ -125,13 +153,34 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
         partial = (uint2 *)c->partial.ptr;
     }
     BlockBest *bb = (BlockBest *)c->block_best.ptr;
+    const bool prof = c->profile && s == c->stream;
+    if (prof) (void)hipEventRecord(c->ev[0], s);
     st = hip_check(c, launch_sweep(plan, zdata, N, n_p, n_q, partial, bb, counts_dev, s), "sweep launch");
     if (st) return st;
+    if (prof) (void)hipEventRecord(c->ev[1], s);
     if (plan.chunks > 1) {
         st = hip_check(c, launch_score(plan, N, n_p, n_q, partial, bb, counts_dev, s), "score launch");
         if (st) return st;
+        if (prof) (void)hipEventRecord(c->ev[2], s);
+    }
+    if (prof) {
+        c->ev_pending = true;
+        c->ev_score = plan.chunks > 1;
+        c->ev_compares = N * N * plan.d;
     }
     return hip_check(c, launch_reduce(bb, plan.groups, c->flags_dev, c->result_dev, s), "reduce launch");
+}
+
+void profile_collect(ddks_ctx *c)
+{
+    if (!c->ev_pending) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->prof.sweep_ms += ms;
+    if (c->ev_score && hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess)
+        c->prof.score_ms += ms;
+    c->prof.sweeps += 1;
+    c->prof.compares += (uint64_t)c->ev_compares;
+    c->ev_pending = false;
 }
 
 }  // namespace ddks
@@ -214,6 +263,9 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->result_host, sizeof(ResultDev), 0), "hipHostMalloc");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->rank_distinct_host, 16 * sizeof(uint32_t), 0), "hipHostMalloc");
     if (!st) c->used += sizeof(ResultDev) + 2 * sizeof(uint32_t) + 16 * sizeof(uint32_t);
+    c->profile = (o.flags & DDKS_PROFILE_KERNELS) != 0;
+    for (int i = 0; i < 4 && !st && c->profile; ++i)
+        st = hip_check(c, hipEventCreate(&c->ev[i]), "hipEventCreate");
     if (!st) c->tuner = tuner_create(c->tune_cache.empty() ? nullptr : c->tune_cache.c_str());
     if (st) {
         ddks_destroy(c);
@@ -237,6 +289,8 @@ int ddks_destroy(ddks_ctx *c)
     if (c->rank_distinct_dev) (void)hipFree(c->rank_distinct_dev);
     if (c->result_host) (void)hipHostFree(c->result_host);
     if (c->rank_distinct_host) (void)hipHostFree(c->rank_distinct_host);
+    for (int i = 0; i < 4; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     tuner_destroy(c->tuner);
     delete c;
@@ -304,6 +358,7 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     }
     st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
     if (st) return st;
+    profile_collect(c);
     const ResultDev r = *c->result_host;
     if (r.flags & 1u) return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
     out->num = r.num;
@@ -314,6 +369,15 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     out->d = d;
     out->n_p = n_p;
     out->n_q = n_q;
+    return DDKS_OK;
+}
+
+int ddks_profile_get(ddks_ctx *c, ddks_profile *out, int32_t reset)
+{
+    if (!c || !out) return DDKS_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    *out = c->prof;
+    if (reset) c->prof = ddks_profile{};
     return DDKS_OK;
 }
 

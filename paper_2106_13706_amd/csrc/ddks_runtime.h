@@ -52,6 +52,14 @@ struct ddks_ctx {
     uint32_t *rank_distinct_host = nullptr; // pinned
     uint32_t *rank_distinct_dev = nullptr;
 
+    // kernel timing (DDKS_PROFILE_KERNELS)
+    bool profile = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ev_pending = false;
+    bool ev_score = false;
+    int64_t ev_compares = 0;
+    ddks_profile prof{};
+
     ddks::Tuner *tuner = nullptr;
     ddks::Serve *serve = nullptr;
     std::mutex serve_mu;
@@ -76,6 +84,10 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool want_counts);
 // encoding at zr).  Leaves the result in c->result_dev; does not synchronise.
 int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
               int64_t n_q, uint32_t *counts_dev, hipStream_t s);
+
+// Folds the events recorded by the last run_sweep into c->prof (after the
+// stream has been synchronised).
+void profile_collect(ddks_ctx *c);
 
 // Chooses the path for a test (fp32 or rank-16) given the caller's flags.
 int choose_path(ddks_ctx *c, int d, int64_t N, uint32_t flags);

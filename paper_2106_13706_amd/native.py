@@ -30,12 +30,15 @@ DDKS_E_NOT_SUPPORTED = -9
 DDKS_DEVICE_PTRS = 0x1
 DDKS_FORCE_F32 = 0x2
 DDKS_NO_AUTOTUNE = 0x4
+DDKS_PROFILE_KERNELS = 0x8
+DDKS_FORCE_RANK16 = 0x10
 
 # Every symbol include/ddks.h declares.
 EXPORTS = (
     "ddks_default_options", "ddks_create", "ddks_destroy", "ddks_distance",
     "ddks_permutation_batch", "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
-    "ddks_serve_stats_get", "ddks_status_string", "ddks_last_error", "ddks_version",
+    "ddks_serve_stats_get", "ddks_profile_get", "ddks_status_string", "ddks_last_error",
+    "ddks_version",
 )
 
 
@@ -69,6 +72,12 @@ class _ServeStats(ctypes.Structure):
                 ("launches", ctypes.c_uint64), ("p50_latency_us", ctypes.c_double),
                 ("p99_latency_us", ctypes.c_double), ("mean_batch", ctypes.c_double),
                 ("resident_bytes", ctypes.c_uint64)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_uint64), ("sweep_ms", ctypes.c_double),
+                ("score_ms", ctypes.c_double), ("batch_ms", ctypes.c_double),
+                ("compares", ctypes.c_uint64)]
 
 
 @dataclass
@@ -120,6 +129,7 @@ def load(path: str = LIB_PATH):
     lib.ddks_serve_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(u64)]
     lib.ddks_serve_poll.argtypes = [vp, u64, i32, ctypes.POINTER(_Result)]
     lib.ddks_serve_stats_get.argtypes = [vp, ctypes.POINTER(_ServeStats), i32]
+    lib.ddks_profile_get.argtypes = [vp, ctypes.POINTER(_Profile), i32]
     lib.ddks_status_string.argtypes = [ctypes.c_int]
     lib.ddks_status_string.restype = ctypes.c_char_p
     lib.ddks_last_error.argtypes = [vp]
@@ -127,7 +137,7 @@ def load(path: str = LIB_PATH):
     lib.ddks_version.restype = ctypes.c_char_p
     for name in ("ddks_create", "ddks_destroy", "ddks_distance", "ddks_permutation_batch",
                  "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
-                 "ddks_serve_stats_get"):
+                 "ddks_serve_stats_get", "ddks_profile_get"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -296,6 +306,13 @@ class Context:
             return None
         self._check(st, "ddks_serve_poll")
         return Result._from(r)
+
+    def profile(self, reset: bool = False) -> dict:
+        """Device-time counters (needs flags=DDKS_PROFILE_KERNELS at creation)."""
+        p = _Profile()
+        self._check(self._lib.ddks_profile_get(self._h, ctypes.byref(p), 1 if reset else 0),
+                    "ddks_profile_get")
+        return {k: getattr(p, k) for k, _ in _Profile._fields_}
 
     def serve_stats(self, reset: bool = False) -> dict:
         s = _ServeStats()

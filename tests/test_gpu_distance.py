@@ -61,27 +61,33 @@ SIZES = [(1, 1), (1, 2), (3, 5), (63, 1), (64, 64), (65, 63), (100, 37), (300, 2
          (1000, 1), (777, 1234)]
 
 
+PATHS = {"f32": 0x2, "rank16": 0x10}  # DDKS_FORCE_F32, DDKS_FORCE_RANK16
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("d", range(1, 9))
-def test_random_sizes_all_d(ctx, oracle_mod, d):
+def test_random_sizes_all_d(ctx, oracle_mod, d, path):
     g = np.random.default_rng(1000 + d)
     for n_p, n_q in SIZES:
         P = g.standard_normal((n_p, d)).astype(np.float32)
         Q = (g.standard_normal((n_q, d)) * 1.1 + 0.2).astype(np.float32)
-        check(ctx, oracle_mod, P, Q)
+        check(ctx, oracle_mod, P, Q, flags=PATHS[path])
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("d", [1, 2, 3, 5, 8])
-def test_ties_and_signed_zero(ctx, oracle_mod, d):
+def test_ties_and_signed_zero(ctx, oracle_mod, d, path):
     g = np.random.default_rng(77 + d)
     P = g.integers(-2, 3, size=(301, d)).astype(np.float32)
     Q = g.integers(-1, 3, size=(257, d)).astype(np.float32)
     P[g.random(P.shape) < 0.3] = -0.0
     Q[g.random(Q.shape) < 0.2] = -0.0
     assert np.signbit(P).any() and np.signbit(Q).any()
-    check(ctx, oracle_mod, P, Q)
+    check(ctx, oracle_mod, P, Q, flags=PATHS[path])
 
 
-def test_subnormals_and_extremes(ctx, oracle_mod):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_subnormals_and_extremes(ctx, oracle_mod, path):
     tiny = np.float32(1e-45)
     vals = np.array([0.0, -0.0, tiny, -tiny, 2 * tiny, 1e-40, -1e-40, 1.1754942e-38,
                      1.1754944e-38, 3.4028235e38, -3.4028235e38, 1.0, -1.0], np.float32)
@@ -89,7 +95,7 @@ def test_subnormals_and_extremes(ctx, oracle_mod):
     for d in (1, 2, 4, 7):
         P = g.choice(vals, size=(150, d)).astype(np.float32)
         Q = g.choice(vals, size=(170, d)).astype(np.float32)
-        check(ctx, oracle_mod, P, Q)
+        check(ctx, oracle_mod, P, Q, flags=PATHS[path])
 
 
 @pytest.mark.parametrize("waves,chunks", [(1, 1), (2, 3), (4, 1), (4, 7), (8, 2), (8, 1)])
@@ -100,7 +106,8 @@ def test_launch_shapes(oracle_mod, waves, chunks):
         for d in (2, 4, 6):
             P = np.rint(g.standard_normal((2345, d)) * 4).astype(np.float32)
             Q = np.rint(g.standard_normal((1999, d)) * 4 + 0.5).astype(np.float32)
-            check(c, oracle_mod, P, Q)
+            for flags in PATHS.values():
+                check(c, oracle_mod, P, Q, flags=flags)
     finally:
         c.close()
 
@@ -163,12 +170,34 @@ def test_workload_gaussian_scale_d4_20000(ctx, oracle_mod):
     check(ctx, oracle_mod, P, Q)
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_workload_gaussian_scale_d4_20000_paths(ctx, oracle_mod, path):
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.gaussian_scale()
+    check(ctx, oracle_mod, P, Q, counts=False, flags=PATHS[path])
+
+
 def test_workload_mixture_grid_d6_scaled(ctx, oracle_mod):
     """Same recipe as the 100000-point workload at 1/10 the size: full parity."""
     from paper_2106_13706_amd import workloads
     P, Q = workloads.mixture_grid(n_p=10000, n_q=10000)
     assert np.signbit(P).any()
     check(ctx, oracle_mod, P, Q)
+    check(ctx, oracle_mod, P, Q, counts=False, flags=PATHS["f32"])
+
+
+def test_rank16_dense_path_and_fallback(ctx, oracle_mod):
+    """More than 65536 points: with few distinct values the dense ranks fit
+    16 bits; with more than 65536 distinct values in a dimension the library
+    falls back to fp32 compares.  Both must match the oracle."""
+    g = np.random.default_rng(44)
+    P = np.rint(g.standard_normal((40000, 2)) * 30).astype(np.float32)
+    Q = np.rint(g.standard_normal((30001, 2)) * 30 + 3).astype(np.float32)
+    check(ctx, oracle_mod, P, Q, counts=False, flags=PATHS["rank16"])
+    P = g.standard_normal((36000, 2)).astype(np.float32)
+    Q = g.standard_normal((34000, 2)).astype(np.float32)
+    assert len(np.unique(np.concatenate([P, Q])[:, 0])) > 65536
+    check(ctx, oracle_mod, P, Q, counts=False, flags=PATHS["rank16"])
 
 
 def test_workload_mixture_grid_d6_100000_sampled(ctx, oracle_mod):
