@@ -105,20 +105,33 @@ int ddks_destroy(ddks_ctx *ctx);
 int ddks_distance(ddks_ctx *ctx, const float *P, int64_t n_p, const float *Q, int64_t n_q,
                   int32_t d, uint32_t flags, ddks_result *out, uint32_t *counts);
 
+typedef struct ddks_perm_summary {
+    int64_t B;          /* relabellings evaluated */
+    uint64_t n_ge;      /* relabellings whose numerator is >= the observed one */
+    double p_value;     /* (1 + n_ge) / (1 + B) */
+    double fraction;    /* n_ge / B (0 when B == 0) */
+} ddks_perm_summary;
+
 /*
  * Permutation test (Sec. 3 and Sec. 4.2): the statistic for B relabellings
  * of the pooled sample Z (n x d).
  * labels: B rows of ceil(n/32) uint32 words; bit (i % 32) of word (i / 32)
  * set means point i is in the first sample.  Every row must hold exactly
- * n_p set bits (and none beyond n).  nums_out[B] receives each row's
+ * n_p set bits (and none at or beyond n).  nums_out[B] receives each row's
  * numerator; all rows share den = n_p*(n - n_p).
  * observed (nullable): the statistic of the split "first n_p rows of Z are
- * the first sample", with its argmax, computed in the same launch.
- * Errors: as ddks_distance, plus DDKS_E_INVALID_ARG for a malformed row.
+ * the first sample", with its argmax, computed in the same launch sequence.
+ * summary (nullable): the permutation p-value of the observed statistic;
+ * ties count as at least as extreme (the paper gives no formula; this is
+ * the add-one estimator).
+ * Repeated calls with the same shapes replay one captured hipGraph.
+ * Limits: 2 <= n <= 2^31 - 1, 1 <= n_p < n, n_p <= 65535, B >= 0.
+ * Errors: as ddks_distance, plus DDKS_E_INVALID_ARG for a malformed row and
+ * DDKS_E_NOT_SUPPORTED for n_p > 65535.
  */
 int ddks_permutation_batch(ddks_ctx *ctx, const float *Z, int64_t n, int32_t d, int64_t n_p,
                            const uint32_t *labels, int32_t B, uint32_t flags, uint64_t *nums_out,
-                           ddks_result *observed);
+                           ddks_result *observed, ddks_perm_summary *summary);
 
 /*
  * Analytic significance S of a statistic num/(n_p*n_q) from its membership
@@ -183,8 +196,9 @@ typedef struct ddks_profile {
     uint64_t sweeps;      /* sweep launches timed */
     double sweep_ms;      /* summed device time of the orthant-counting sweep kernel */
     double score_ms;      /* summed device time of the partial-count scoring kernel */
-    double batch_ms;      /* summed device time of the permutation kernel */
+    double batch_ms;      /* summed device time of whole permutation batches (graph launches) */
     uint64_t compares;    /* origin*point*dim compares those sweeps evaluated */
+    uint64_t batches;     /* permutation batches timed */
 } ddks_profile;
 
 /*

@@ -18,7 +18,8 @@ struct ResultDev {
     uint64_t num;
     int64_t origin;
     int32_t code;
-    uint32_t flags;  // bit 0: a non-finite input value was seen
+    uint32_t flags;  // bit 0: a non-finite input value was seen; bit 1: malformed label row
+    uint64_t ge;     // permutation batch: relabellings with numerator >= num
 };
 
 enum Path : int { PATH_F32 = 0, PATH_R16 = 1 };
@@ -78,5 +79,28 @@ hipError_t launch_score(const SweepPlan &plan, int64_t N, int64_t n_p, int64_t n
 // code asc) into *out, copies *flags into out->flags and clears *flags.
 hipError_t launch_reduce(const BlockBest *block_best, int64_t nblocks, uint32_t *flags,
                          ResultDev *out, hipStream_t s);
+
+// ---------------------------------------------------------------- permutation test
+
+// LDS bytes of one permutation-kernel wave (pb relabellings per wave).
+size_t perm_lds_bytes(int d, int pb);
+// Largest relabellings-per-wave group for dimension d (8 for d <= 6, else 4).
+int perm_max_group(int d);
+
+// Checks every label row (bit 1 of *flags when a row is malformed), builds the
+// per-point increments inc [ceil(B/pb)][n][pb/4] and clears nums[B].
+hipError_t launch_perm_prepare(const uint32_t *labels, int64_t n, int B, int64_t n_p, int pb,
+                               uint64_t *inc, uint32_t *flags, unsigned long long *nums,
+                               hipStream_t s);
+
+// nums[b] = max over origins and orthants of |c_P*n_Q - c_Q*n_P| for relabelling b
+// (atomic max; nums must start at zero).  obs_counts: [N][2^d][2] counts of any
+// one split of the same pooled points (only c_P + c_Q is used).  n_p <= 65535.
+hipError_t launch_perm(int path, int d, int pb, const void *Z, int64_t N, int64_t n_p,
+                       const uint64_t *inc, int B, const uint32_t *obs_counts,
+                       unsigned long long *nums, hipStream_t s);
+
+// res->ge = #{b : nums[b] >= res->num}.
+hipError_t launch_count_ge(const unsigned long long *nums, int B, ResultDev *res, hipStream_t s);
 
 }  // namespace ddks

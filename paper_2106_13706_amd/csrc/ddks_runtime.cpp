@@ -61,6 +61,7 @@ int ensure(ddks_ctx *c, DevBuf &b, size_t bytes, const char *what)
     b.ptr = p;
     b.bytes = want;
     c->used += want;
+    c->buf_gen += 1;
     return DDKS_OK;
 }
 
@@ -153,7 +154,7 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
         partial = (uint2 *)c->partial.ptr;
     }
     BlockBest *bb = (BlockBest *)c->block_best.ptr;
-    const bool prof = c->profile && s == c->stream;
+    const bool prof = c->profile && s == c->stream && !c->batch_capturing;
     if (prof) (void)hipEventRecord(c->ev[0], s);
     st = hip_check(c, launch_sweep(plan, zdata, N, n_p, n_q, partial, bb, counts_dev, s), "sweep launch");
     if (st) return st;
@@ -281,8 +282,9 @@ int ddks_destroy(ddks_ctx *c)
     (void)hipSetDevice(c->device);
     serve_stop(c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     DevBuf *bufs[] = {&c->z, &c->zr, &c->partial, &c->block_best, &c->counts, &c->rank_scratch,
-                      &c->labels, &c->nums, &c->sig};
+                      &c->labels, &c->nums, &c->sig, &c->inc, &c->obs};
     for (DevBuf *b : bufs) release(c, *b);
     if (c->result_dev) (void)hipFree(c->result_dev);
     if (c->flags_dev) (void)hipFree(c->flags_dev);

@@ -45,7 +45,12 @@ struct ddks_ctx {
     std::mutex mu;  // serialises the synchronous calls on `stream`
 
     // buffers of the synchronous path
-    ddks::DevBuf z, zr, partial, block_best, counts, rank_scratch, labels, nums, sig;
+    ddks::DevBuf z, zr, partial, block_best, counts, rank_scratch, labels, nums, sig, inc, obs;
+    uint64_t buf_gen = 0;  // bumped whenever a buffer is reallocated
+
+    // captured permutation-batch graph, replayed while its key matches
+    hipGraphExec_t batch_exec = nullptr;
+    std::vector<uint64_t> batch_key;
     ddks::ResultDev *result_dev = nullptr;  // device
     ddks::ResultDev *result_host = nullptr; // pinned
     uint32_t *flags_dev = nullptr;          // device, cleared by the reduction
@@ -57,6 +62,8 @@ struct ddks_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool ev_pending = false;
     bool ev_score = false;
+    bool batch_capturing = false;  // no event records while a graph is being captured
+    bool graph_pending = false;
     int64_t ev_compares = 0;
     ddks_profile prof{};
 

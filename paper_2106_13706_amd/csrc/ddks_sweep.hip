@@ -28,339 +28,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "ddks_internal.h"
+#include "ddks_device.h"
 
 namespace ddks {
-
-typedef short short2_t __attribute__((ext_vector_type(2)));
-
-template <int D>
-struct Geo {
-    static constexpr int BINS = 1 << D;
-    static constexpr int NREG = (D + 1) / 2;   // sign registers, two dimensions each
-    static constexpr int NPERM = (D + 3) / 4;  // v_perm/v_dot4 groups, four dimensions each
-    // Dimension 7's weight does not fit a signed byte; it is given weight -128,
-    // which flips that bit of the bin index relative to the orthant code.
-    static constexpr int FLIP = (D == 8) ? 0x80 : 0;
-    static constexpr int KOFF = (D == 8) ? 127 : (BINS - 1);  // bin = dot-sum + KOFF
-};
-
-// v_perm_b32 selector for group q: byte i takes the sign of dimension 4q+i
-// (8/9: bit 15/31 of src1 = register 2q; 10/11: bit 15/31 of src0 = register
-// 2q+1) and 0x00 (selector 12) for dimensions beyond D.
-__host__ __device__ constexpr uint32_t perm_sel(int D, int q)
-{
-    uint32_t sel = 0;
-    for (int i = 0; i < 4; ++i) {
-        int m = 4 * q + i;
-        uint32_t b = (m < D) ? (uint32_t)(8 + i) : 12u;
-        sel |= b << (8 * i);
-    }
-    return sel;
-}
-
-// Signed-byte weights for group q: 2^m, and -128 for m = 7.
-__host__ __device__ constexpr uint32_t dot_wts(int D, int q)
-{
-    uint32_t w = 0;
-    for (int i = 0; i < 4; ++i) {
-        int m = 4 * q + i;
-        uint32_t b = 0;
-        if (m < D) b = (m == 7) ? 0x80u : (uint32_t)(1u << m);
-        w |= (b & 0xffu) << (8 * i);
-    }
-    return w;
-}
-
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-
-// ---------------------------------------------------------------------------
-// Inline-asm building blocks.  Two gfx950 pipeline hazards are invisible to
-// the compiler inside asm, so each asm block carries a whole dependent chain
-// with the spacing built in:
-//  * v_fma_mix{lo,hi}_f16 write half a VGPR; a read of that VGPR needs one
-//    intervening instruction (the compiler already pads after any asm block
-//    before its own VALU reads).
-//  * a v_dot4 result needs three intervening instructions before a VALU reads
-//    it; the dots of four points are issued back to back, then their address
-//    computations, so every read is at least three instructions later.
-// ---------------------------------------------------------------------------
-
-#define MIXLO(d, x, o) "v_fma_mixlo_f16 " d ", " x ", 1.0, -" o " op_sel_hi:[0,0,0]\n\t"
-#define MIXHI(d, x, o) "v_fma_mixhi_f16 " d ", " x ", 1.0, -" o " op_sel_hi:[0,0,0]\n\t"
-
-// Sign registers of one fp32 point: register p holds sign(x_{2p} - o_{2p}) in
-// bit 15 and sign(x_{2p+1} - o_{2p+1}) in bit 31 (bit 31 undefined when 2p+1 = D).
-template <int D>
-__device__ __forceinline__ void signs_f32(const float *x, const float *o, uint32_t (&r)[Geo<D>::NREG]);
-
-template <>
-__device__ __forceinline__ void signs_f32<1>(const float *x, const float *o, uint32_t (&r)[1])
-{
-    asm(MIXLO("%0", "%1", "%2") : "=v"(r[0]) : "s"(x[0]), "v"(o[0]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<2>(const float *x, const float *o, uint32_t (&r)[1])
-{
-    asm(MIXLO("%0", "%1", "%2") "s_nop 0\n\t" MIXHI("%0", "%3", "%4")
-        : "=&v"(r[0]) : "s"(x[0]), "v"(o[0]), "s"(x[1]), "v"(o[1]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<3>(const float *x, const float *o, uint32_t (&r)[2])
-{
-    asm(MIXLO("%0", "%2", "%3") MIXLO("%1", "%4", "%5") MIXHI("%0", "%6", "%7")
-        : "=&v"(r[0]), "=&v"(r[1])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[1]), "v"(o[1]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<4>(const float *x, const float *o, uint32_t (&r)[2])
-{
-    asm(MIXLO("%0", "%2", "%3") MIXLO("%1", "%4", "%5") MIXHI("%0", "%6", "%7")
-            MIXHI("%1", "%8", "%9")
-        : "=&v"(r[0]), "=&v"(r[1])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[1]), "v"(o[1]), "s"(x[3]),
-          "v"(o[3]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<5>(const float *x, const float *o, uint32_t (&r)[3])
-{
-    asm(MIXLO("%0", "%3", "%4") MIXLO("%1", "%5", "%6") MIXLO("%2", "%7", "%8")
-            MIXHI("%0", "%9", "%10") MIXHI("%1", "%11", "%12")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[1]),
-          "v"(o[1]), "s"(x[3]), "v"(o[3]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<6>(const float *x, const float *o, uint32_t (&r)[3])
-{
-    asm(MIXLO("%0", "%3", "%4") MIXLO("%1", "%5", "%6") MIXLO("%2", "%7", "%8")
-            MIXHI("%0", "%9", "%10") MIXHI("%1", "%11", "%12") MIXHI("%2", "%13", "%14")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[1]),
-          "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<7>(const float *x, const float *o, uint32_t (&r)[4])
-{
-    asm(MIXLO("%0", "%4", "%5") MIXLO("%1", "%6", "%7") MIXLO("%2", "%8", "%9")
-            MIXLO("%3", "%10", "%11") MIXHI("%0", "%12", "%13") MIXHI("%1", "%14", "%15")
-                MIXHI("%2", "%16", "%17")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[6]),
-          "v"(o[6]), "s"(x[1]), "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<8>(const float *x, const float *o, uint32_t (&r)[4])
-{
-    asm(MIXLO("%0", "%4", "%5") MIXLO("%1", "%6", "%7") MIXLO("%2", "%8", "%9")
-            MIXLO("%3", "%10", "%11") MIXHI("%0", "%12", "%13") MIXHI("%1", "%14", "%15")
-                MIXHI("%2", "%16", "%17") MIXHI("%3", "%18", "%19")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[6]),
-          "v"(o[6]), "s"(x[1]), "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]),
-          "s"(x[7]), "v"(o[7]));
-}
-
-// sign(x - o) of two rank-encoded dimensions (int16, saturating) into bits 15 and 31.
-__device__ __forceinline__ uint32_t sgn2_r16(uint32_t x, uint32_t o)
-{
-    short2_t t = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2_t, x),
-                                               __builtin_bit_cast(short2_t, o));
-    return __builtin_bit_cast(uint32_t, t);
-}
-
-// Sign-filled bytes of perm group q (v_perm_b32 sign selectors).
-template <int D>
-__device__ __forceinline__ uint32_t group_bytes(const uint32_t (&r)[Geo<D>::NREG], int q)
-{
-    constexpr int NR = Geo<D>::NREG;
-    if (q == 0) return __builtin_amdgcn_perm(NR > 1 ? r[NR > 1 ? 1 : 0] : 0u, r[0], perm_sel(D, 0));
-    return __builtin_amdgcn_perm(NR > 3 ? r[NR > 3 ? 3 : 2] : 0u, r[NR > 2 ? 2 : 0], perm_sel(D, 1));
-}
-
-#define DOT0(d, r, w) "v_dot4_i32_i8 " d ", " r ", " w ", 0\n\t"
-#define DOTC(d, r, w) "v_dot4_i32_i8 " d ", " r ", " w ", " d "\n\t"
-#define ADDR(d, b) "v_lshl_add_u32 " d ", " d ", 8, " b "\n\t"
-
-// LDS byte addresses of the bins of four points: base + 256 * (dot-sum).
-template <int NPERM>
-__device__ __forceinline__ void addr4(const uint32_t (&R)[2][4], uint32_t base, uint32_t (&a)[4],
-                                      uint32_t w0, uint32_t w1)
-{
-    if constexpr (NPERM == 1) {
-        asm(DOT0("%0", "%4", "%8") DOT0("%1", "%5", "%8") DOT0("%2", "%6", "%8")
-                DOT0("%3", "%7", "%8") ADDR("%0", "%9") ADDR("%1", "%9") ADDR("%2", "%9")
-                    ADDR("%3", "%9")
-            : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3])
-            : "v"(R[0][0]), "v"(R[0][1]), "v"(R[0][2]), "v"(R[0][3]), "s"(w0), "v"(base));
-    } else {
-        asm(DOT0("%0", "%4", "%12") DOT0("%1", "%5", "%12") DOT0("%2", "%6", "%12")
-                DOT0("%3", "%7", "%12") DOTC("%0", "%8", "%13") DOTC("%1", "%9", "%13")
-                    DOTC("%2", "%10", "%13") DOTC("%3", "%11", "%13") ADDR("%0", "%14")
-                        ADDR("%1", "%14") ADDR("%2", "%14") ADDR("%3", "%14")
-            : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3])
-            : "v"(R[0][0]), "v"(R[0][1]), "v"(R[0][2]), "v"(R[0][3]), "v"(R[1][0]),
-              "v"(R[1][1]), "v"(R[1][2]), "v"(R[1][3]), "s"(w0), "s"(w1), "v"(base));
-    }
-}
-
-// The same for a single point, with the wait states written out.
-template <int NPERM>
-__device__ __forceinline__ uint32_t addr1(uint32_t R0, uint32_t R1, uint32_t base, uint32_t w0,
-                                          uint32_t w1)
-{
-    uint32_t a;
-    if constexpr (NPERM == 1) {
-        asm(DOT0("%0", "%1", "%2") "s_nop 2\n\t" ADDR("%0", "%3")
-            : "=&v"(a) : "v"(R0), "s"(w0), "v"(base));
-    } else {
-        asm(DOT0("%0", "%1", "%3") "s_nop 2\n\t" DOTC("%0", "%2", "%4") "s_nop 2\n\t" ADDR("%0", "%5")
-            : "=&v"(a) : "v"(R0), "v"(R1), "s"(w0), "s"(w1), "v"(base));
-    }
-    return a;
-}
-
-__device__ __forceinline__ void lds_add(uint32_t byte_addr, uint32_t v)
-{
-    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)byte_addr, v, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Point element type and words per point for each path.
-template <int PATH, int D>
-struct Layout;
-template <int D>
-struct Layout<PATH_F32, D> {
-    typedef float T;
-    static constexpr int PW = D;  // floats per point
-};
-template <int D>
-struct Layout<PATH_R16, D> {
-    typedef uint32_t T;
-    static constexpr int PW = (D <= 2) ? 1 : (D <= 4 ? 2 : 4);  // padded to a power of two
-};
-
-// Points per unrolled block: a multiple of four, about 32 scalar registers of point data.
-template <int PATH, int D>
-struct Unroll {
-    static constexpr int PW = Layout<PATH, D>::PW;
-    static constexpr int U0 = ((32 / PW) / 4) * 4;
-    static constexpr int U = U0 < 4 ? 4 : U0;
-};
-
-// The origin held by a lane.
-template <int PATH, int D>
-struct Origin;
-template <int D>
-struct Origin<PATH_F32, D> {
-    float o[D];
-    __device__ void load(const float *Z, int64_t k)
-    {
-#pragma unroll
-        for (int m = 0; m < D; ++m) o[m] = Z[k * D + m];
-    }
-};
-template <int D>
-struct Origin<PATH_R16, D> {
-    static constexpr int PW = Layout<PATH_R16, D>::PW;
-    uint32_t o[PW];
-    __device__ void load(const uint32_t *Z, int64_t k)
-    {
-#pragma unroll
-        for (int m = 0; m < PW; ++m) o[m] = Z[k * PW + m];
-    }
-};
-
-// Sign registers of point x (PW words at xs) against the lane's origin.
-template <int PATH, int D>
-__device__ __forceinline__ void signs(const typename Layout<PATH, D>::T *xs,
-                                      const Origin<PATH, D> &org, uint32_t (&r)[Geo<D>::NREG])
-{
-    if constexpr (PATH == PATH_F32) {
-        signs_f32<D>(xs, org.o, r);
-    } else {
-#pragma unroll
-        for (int p = 0; p < Geo<D>::NREG; ++p) r[p] = sgn2_r16(xs[p], org.o[p]);
-    }
-}
-
-// Sweeps points [lo, hi) of Z against the lane's origin, adding inc to the
-// lane's bin of each point.  base: LDS byte address of bin KOFF of this lane.
-template <int PATH, int D>
-__device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *__restrict__ Z,
-                                            int64_t lo, int64_t hi, const Origin<PATH, D> &org,
-                                            uint32_t base, uint32_t inc)
-{
-    typedef typename Layout<PATH, D>::T T;
-    constexpr int PW = Layout<PATH, D>::PW;
-    constexpr int U = Unroll<PATH, D>::U;
-    constexpr int NP = Geo<D>::NPERM;
-    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
-    int64_t i = lo;
-    for (; i + U <= hi; i += U) {
-        const T *blk = Z + i * PW;
-        T buf[U * PW];
-#pragma unroll
-        for (int e = 0; e < U * PW; ++e) buf[e] = blk[e];
-#pragma unroll
-        for (int g = 0; g < U; g += 4) {
-            uint32_t R[2][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint32_t r[Geo<D>::NREG];
-                signs<PATH, D>(buf + (g + u) * PW, org, r);
-                R[0][u] = group_bytes<D>(r, 0);
-                R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-            }
-            uint32_t a[4];
-            addr4<NP>(R, base, a, w0, w1);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) lds_add(a[u], inc);
-        }
-    }
-    for (; i < hi; ++i) {
-        const T *xs = Z + i * PW;
-        T buf[PW];
-#pragma unroll
-        for (int e = 0; e < PW; ++e) buf[e] = xs[e];
-        uint32_t r[Geo<D>::NREG];
-        signs<PATH, D>(buf, org, r);
-        uint32_t R0 = group_bytes<D>(r, 0);
-        uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-        lds_add(addr1<NP>(R0, R1, base, w0, w1), inc);
-    }
-}
-
-// Key order of the maximum: larger num first, then lower origin, then lower code.
-__device__ __forceinline__ bool better(uint64_t an, uint32_t ao, int32_t ac, uint64_t bn,
-                                       uint32_t bo, int32_t bc)
-{
-    if (an != bn) return an > bn;
-    if (ao != bo) return ao < bo;
-    return ac < bc;
-}
-
-__device__ __forceinline__ uint64_t score(uint32_t cp, uint32_t cq, int64_t n_p, int64_t n_q)
-{
-    int64_t a = (int64_t)cp * n_q - (int64_t)cq * n_p;
-    return (uint64_t)(a < 0 ? -a : a);
-}
-
-// Wave-wide arg-max of (num, origin, code) with the key order above.
-__device__ __forceinline__ void wave_best(uint64_t &n, uint32_t &o, int32_t &c)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        uint64_t n2 = __shfl_xor(n, off, 64);
-        uint32_t o2 = __shfl_xor(o, off, 64);
-        int32_t c2 = __shfl_xor(c, off, 64);
-        if (better(n2, o2, c2, n, o, c)) {
-            n = n2;
-            o = o2;
-            c = c2;
-        }
-    }
-}
 
 // Block finish: thread (wave w, lane) owns bins j = w, w+W, ... of origin
 // group*64+lane; get(j) returns its (c_P, c_Q).  Scores every bin, writes the

@@ -74,10 +74,15 @@ class _ServeStats(ctypes.Structure):
                 ("resident_bytes", ctypes.c_uint64)]
 
 
+class _PermSummary(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int64), ("n_ge", ctypes.c_uint64), ("p_value", ctypes.c_double),
+                ("fraction", ctypes.c_double)]
+
+
 class _Profile(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_uint64), ("sweep_ms", ctypes.c_double),
                 ("score_ms", ctypes.c_double), ("batch_ms", ctypes.c_double),
-                ("compares", ctypes.c_uint64)]
+                ("compares", ctypes.c_uint64), ("batches", ctypes.c_uint64)]
 
 
 @dataclass
@@ -123,7 +128,7 @@ def load(path: str = LIB_PATH):
     lib.ddks_destroy.argtypes = [vp]
     lib.ddks_distance.argtypes = [vp, vp, i64, vp, i64, i32, u32, ctypes.POINTER(_Result), vp]
     lib.ddks_permutation_batch.argtypes = [vp, vp, i64, i32, i64, vp, i32, u32, vp,
-                                           ctypes.POINTER(_Result)]
+                                           ctypes.POINTER(_Result), ctypes.POINTER(_PermSummary)]
     lib.ddks_significance.argtypes = [vp, vp, i64, i64, i32, u64, u32,
                                       ctypes.POINTER(ctypes.c_double)]
     lib.ddks_serve_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(u64)]
@@ -244,9 +249,10 @@ class Context:
         res = Result._from(r)
         return (res, cbuf) if counts else res
 
-    def permutation_batch(self, Z, n_p: int, labels, *, observed: bool = True, flags: int = 0):
+    def permutation_batch(self, Z, n_p: int, labels, *, flags: int = 0):
         """Numerators for every relabelling row (labels: [B, ceil(n/32)] uint32
-        words) and, if observed, the Result of the split 'first n_p rows'."""
+        words), the Result of the split 'first n_p rows' and the p-value summary
+        {B, n_ge, p_value, fraction}."""
         zp, n, d, kz, dev = _points(Z)
         if dev:
             flags |= DDKS_DEVICE_PTRS
@@ -261,14 +267,18 @@ class Context:
         else:
             L = np.ascontiguousarray(labels, dtype=np.uint32)
             B = L.shape[0]
+            if B and L.shape[1] != (n + 31) // 32:
+                raise ValueError("label rows must have ceil(n/32) words")
             lp = L.ctypes.data
             nums = np.empty(B, dtype=np.uint64)
             nptr = nums.ctypes.data
         r = _Result()
+        sm = _PermSummary()
         st = self._lib.ddks_permutation_batch(self._h, zp, n, d, n_p, lp, B, flags, nptr,
-                                              ctypes.byref(r) if observed else None)
+                                              ctypes.byref(r), ctypes.byref(sm))
         self._check(st, "ddks_permutation_batch")
-        return nums, (Result._from(r) if observed else None)
+        summary = {"B": sm.B, "n_ge": sm.n_ge, "p_value": sm.p_value, "fraction": sm.fraction}
+        return nums, Result._from(r), summary
 
     def significance(self, counts, n_p: int, n_q: int, d: int, num: int, *, flags: int = 0):
         if _is_torch(counts) and counts.is_cuda:
