@@ -100,6 +100,17 @@ hipError_t launch_perm(int path, int d, int pb, const void *Z, int64_t N, int64_
                        const uint64_t *inc, int B, const uint32_t *obs_counts,
                        unsigned long long *nums, hipStream_t s);
 
+// ---------------------------------------------------------------- significance
+
+// Scratch bytes for launch_significance with `rows` concurrent tail rows.
+size_t significance_scratch_bytes(int64_t n_p, int64_t n_q, int rows);
+
+// *S = analytic significance of num/(n_p n_q) from counts [N][2^d][2] (fp64).
+// Sets bit 2 of *flags if a second-sample count exceeds n_q.
+hipError_t launch_significance(const uint32_t *counts, int64_t N, int d, int64_t n_p, int64_t n_q,
+                               uint64_t num, void *scratch, int rows, uint32_t *flags, double *S,
+                               hipStream_t s);
+
 // res->ge = #{b : nums[b] >= res->num}.
 hipError_t launch_count_ge(const unsigned long long *nums, int B, ResultDev *res, hipStream_t s);
 

@@ -13,8 +13,6 @@ void serve_stop(ddks_ctx *) {}
 }  // namespace ddks
 
 extern "C" {
-int ddks_significance(ddks_ctx *c, const uint32_t *, int64_t, int64_t, int32_t, uint64_t, uint32_t, double *)
-{ return fail(c, DDKS_E_NOT_SUPPORTED, "significance not built"); }
 int ddks_serve_submit(ddks_ctx *c, const ddks_request *, uint64_t *)
 { return fail(c, DDKS_E_NOT_SUPPORTED, "serving not built"); }
 int ddks_serve_poll(ddks_ctx *c, uint64_t, int32_t, ddks_result *)

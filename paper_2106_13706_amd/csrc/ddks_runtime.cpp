@@ -263,6 +263,7 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     if (!st) st = hip_check(c, hipMalloc((void **)&c->rank_distinct_dev, 16 * sizeof(uint32_t)), "hipMalloc");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->result_host, sizeof(ResultDev), 0), "hipHostMalloc");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->rank_distinct_host, 16 * sizeof(uint32_t), 0), "hipHostMalloc");
+    if (!st) st = hip_check(c, hipHostMalloc((void **)&c->sig_host, 2 * sizeof(double), 0), "hipHostMalloc");
     if (!st) c->used += sizeof(ResultDev) + 2 * sizeof(uint32_t) + 16 * sizeof(uint32_t);
     c->profile = (o.flags & DDKS_PROFILE_KERNELS) != 0;
     for (int i = 0; i < 4 && !st && c->profile; ++i)
@@ -291,6 +292,7 @@ int ddks_destroy(ddks_ctx *c)
     if (c->rank_distinct_dev) (void)hipFree(c->rank_distinct_dev);
     if (c->result_host) (void)hipHostFree(c->result_host);
     if (c->rank_distinct_host) (void)hipHostFree(c->rank_distinct_host);
+    if (c->sig_host) (void)hipHostFree(c->sig_host);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

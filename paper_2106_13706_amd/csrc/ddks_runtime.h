@@ -55,6 +55,7 @@ struct ddks_ctx {
     ddks::ResultDev *result_host = nullptr; // pinned
     uint32_t *flags_dev = nullptr;          // device, cleared by the reduction
     uint32_t *rank_distinct_host = nullptr; // pinned
+    double *sig_host = nullptr;             // pinned, 2 doubles
     uint32_t *rank_distinct_dev = nullptr;
 
     // kernel timing (DDKS_PROFILE_KERNELS)
