@@ -24,6 +24,14 @@ struct ResultDev {
 
 enum Path : int { PATH_F32 = 0, PATH_R16 = 1 };
 
+// One test of a packed (serving) launch.
+struct PackedTest {
+    const void *Z;      // device points, P then Q, N x d fp32 (-0 already mapped to +0)
+    int64_t N, n_p, n_q;
+    int64_t groups;     // ceil(N / 64)
+    int64_t bb_offset;  // first BlockBest slot of this test
+};
+
 // Launch shape of one sweep.
 struct SweepPlan {
     int path = PATH_F32;
@@ -79,6 +87,17 @@ hipError_t launch_score(const SweepPlan &plan, int64_t N, int64_t n_p, int64_t n
 // code asc) into *out, copies *flags into out->flags and clears *flags.
 hipError_t launch_reduce(const BlockBest *block_best, int64_t nblocks, uint32_t *flags,
                          ResultDev *out, hipStream_t s);
+
+// ---------------------------------------------------------------- packed tests
+
+// One launch over work items (test, origin group) of tests of dimension d,
+// each test swept in a single chunk (N <= waves * 65535 points); block results
+// go to bb[test.bb_offset + group].  Waves per block: 4 (d <= 7) or 2 (d = 8).
+hipError_t launch_sweep_packed(int path, int d, const PackedTest *tests, const int2 *items,
+                               int64_t nitems, BlockBest *bb, hipStream_t s);
+// out[t] = the test's maximum with the tie rule, for t < ntests.
+hipError_t launch_reduce_packed(const PackedTest *tests, int64_t ntests, const BlockBest *bb,
+                                ResultDev *out, hipStream_t s);
 
 // ---------------------------------------------------------------- permutation test
 

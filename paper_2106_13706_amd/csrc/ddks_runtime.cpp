@@ -351,6 +351,8 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
         if (ok) zdata = c->zr.ptr;
         else path = PATH_F32;
     }
+    st = tune_sweep(c, path, d, N, n_p, n_q, zdata);
+    if (st) return st;
     SweepPlan plan = plan_for(c, path, d, N, counts != nullptr);
     st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, s);
     if (st) return st;

@@ -40,7 +40,7 @@ struct ddks_ctx {
     std::string tune_cache;
     int force_waves = 0;   // test override (DDKS_FORCE_WAVES)
     int64_t force_chunks = 0;  // test override (DDKS_FORCE_CHUNKS)
-    bool poisoned = false;
+    std::atomic<bool> poisoned{false};
     std::string last_error;
     std::mutex mu;  // serialises the synchronous calls on `stream`
 
@@ -112,7 +112,10 @@ void serve_stop(ddks_ctx *c);
 // Autotuner (ddks_tune.cpp).
 Tuner *tuner_create(const char *cache_path);
 void tuner_destroy(Tuner *t);
-// Returns true and fills plan if a tuned shape exists for (path, d, N bucket).
+// Returns true and fills plan (waves, chunks) if a tuned shape exists for (path, d, N bucket).
 bool tuner_lookup(Tuner *t, int path, int d, int64_t N, SweepPlan *plan);
+// Times the admissible launch shapes of a sweep on the given (already
+// ingested) input once per (path, d, N bucket) and records the fastest.
+int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q, const void *zdata);
 
 }  // namespace ddks

@@ -1,0 +1,545 @@
+// Serving loop of libddks: continuous batching of many exact ddKS tests
+// (arXiv:2106.13706, Sec. 2.1) of mixed dimension and size on one GPU.
+//
+//   submit  copies the request (mapping -0 to +0, rejecting non-finite
+//           values) and queues it;
+//   admit   a scheduler thread moves queued requests, oldest first, into a
+//           device arena while it has room (the arena is charged to the
+//           context's memory budget);
+//   launch  admitted tests are packed, per dimension, into one launch whose
+//           blocks are (test, origin group) work items, on one of several
+//           streams, so launches overlap on the device and requests that
+//           arrive while others run join the next launch;
+//   retire  finished launches (HIP events) hand their results to the
+//           tickets, free their arena space and wake pollers.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
+#include "ddks_runtime.h"
+
+namespace ddks {
+
+using Clock = std::chrono::steady_clock;
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// First-fit allocator over [0, size) with coalescing.
+struct Arena {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    void init(size_t n)
+    {
+        size = n;
+        free_.clear();
+        if (n) free_[0] = n;
+    }
+    int64_t alloc(size_t n)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > n) free_[off + n] = len - n;
+                return (int64_t)off;
+            }
+        }
+        return -1;
+    }
+    void release(size_t off, size_t n)
+    {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    int d = 0;
+    int64_t n_p = 0, n_q = 0, N = 0;
+    std::vector<float> data;  // P then Q
+    size_t pts_bytes = 0, bytes = 0;
+    int64_t off = -1;
+    bool done = false;
+    int status = DDKS_OK;
+    ddks_result result{};
+    Clock::time_point t_submit, t_done;
+};
+
+// One stream with the buffers of the launch in flight on it.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Req *> reqs;
+    // pinned staging and device copies of the launch's tables and results
+    PackedTest *tests_h = nullptr, *tests_d = nullptr;
+    int2 *items_h = nullptr, *items_d = nullptr;
+    ResultDev *res_h = nullptr, *res_d = nullptr;
+    size_t cap_tests = 0, cap_items = 0;
+};
+
+struct Serve {
+    ddks_ctx *c = nullptr;
+    std::mutex m;
+    std::condition_variable cv_sched, cv_done;
+    std::deque<Req *> pending;
+    std::deque<Req *> ready;  // admitted, not yet launched
+    std::unordered_map<uint64_t, Req *> table;
+    uint64_t next_ticket = 1;
+    size_t held = 0;  // requests submitted and not yet collected
+    Arena arena;
+    void *arena_base = nullptr;
+    std::vector<Slot> slots;
+    std::thread th;
+    bool stop = false;
+    bool failed = false;
+    std::string error;
+    // stats
+    uint64_t submitted = 0, completed = 0, rej_again = 0, rej_nomem = 0, launches = 0,
+             launched_tests = 0;
+    std::vector<double> lat_us;
+
+    int grow_slot(Slot &s, size_t tests, size_t items);
+    bool launch_batch(Slot &s, std::vector<Req *> &batch);
+    void retire(Slot &s);
+    void loop();
+};
+
+static int64_t packed_max_points(int d) { return (d <= 7 ? 4 : 2) * (int64_t)65535; }
+
+int Serve::grow_slot(Slot &s, size_t tests, size_t items)
+{
+    if (tests > s.cap_tests) {
+        size_t n = std::max(tests, s.cap_tests * 2);
+        if (s.tests_h) (void)hipHostFree(s.tests_h);
+        if (s.tests_d) (void)hipFree(s.tests_d);
+        if (s.res_h) (void)hipHostFree(s.res_h);
+        if (s.res_d) (void)hipFree(s.res_d);
+        s.tests_h = nullptr;
+        s.tests_d = nullptr;
+        s.res_h = nullptr;
+        s.res_d = nullptr;
+        if (hipHostMalloc((void **)&s.tests_h, n * sizeof(PackedTest), 0) != hipSuccess ||
+            hipMalloc((void **)&s.tests_d, n * sizeof(PackedTest)) != hipSuccess ||
+            hipHostMalloc((void **)&s.res_h, n * sizeof(ResultDev), 0) != hipSuccess ||
+            hipMalloc((void **)&s.res_d, n * sizeof(ResultDev)) != hipSuccess)
+            return DDKS_E_DEVICE;
+        s.cap_tests = n;
+    }
+    if (items > s.cap_items) {
+        size_t n = std::max(items, s.cap_items * 2);
+        if (s.items_h) (void)hipHostFree(s.items_h);
+        if (s.items_d) (void)hipFree(s.items_d);
+        s.items_h = nullptr;
+        s.items_d = nullptr;
+        if (hipHostMalloc((void **)&s.items_h, n * sizeof(int2), 0) != hipSuccess ||
+            hipMalloc((void **)&s.items_d, n * sizeof(int2)) != hipSuccess)
+            return DDKS_E_DEVICE;
+        s.cap_items = n;
+    }
+    return DDKS_OK;
+}
+
+// Uploads the batch's points and tables and enqueues one packed launch per
+// dimension present, then the per-test reductions and the result copy.
+bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
+{
+    std::stable_sort(batch.begin(), batch.end(), [](const Req *a, const Req *b) { return a->d < b->d; });
+    size_t nitems = 0;
+    for (Req *r : batch) nitems += (size_t)((r->N + 63) / 64);
+    if (grow_slot(s, batch.size(), nitems) != DDKS_OK) {
+        error = "serving buffer allocation failed";
+        return false;
+    }
+    char *base = (char *)arena_base;
+    BlockBest *bb = (BlockBest *)arena_base;
+    size_t it = 0;
+    for (size_t i = 0; i < batch.size(); ++i) {
+        Req *r = batch[i];
+        PackedTest &t = s.tests_h[i];
+        t.Z = base + r->off;
+        t.N = r->N;
+        t.n_p = r->n_p;
+        t.n_q = r->n_q;
+        t.groups = (r->N + 63) / 64;
+        t.bb_offset = (int64_t)((r->off + r->pts_bytes) / sizeof(BlockBest));
+        for (int64_t g = 0; g < t.groups; ++g) s.items_h[it++] = make_int2((int)i, (int)g);
+        if (hipMemcpyAsync(base + r->off, r->data.data(), r->data.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s.stream) != hipSuccess) {
+            error = "H2D request copy failed";
+            return false;
+        }
+    }
+    if (hipMemcpyAsync(s.tests_d, s.tests_h, batch.size() * sizeof(PackedTest),
+                       hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+        hipMemcpyAsync(s.items_d, s.items_h, nitems * sizeof(int2), hipMemcpyHostToDevice,
+                       s.stream) != hipSuccess) {
+        error = "H2D table copy failed";
+        return false;
+    }
+    // one launch per run of equal dimension (the batch is sorted by d)
+    size_t i0 = 0, item0 = 0;
+    while (i0 < batch.size()) {
+        size_t i1 = i0, items = 0;
+        while (i1 < batch.size() && batch[i1]->d == batch[i0]->d) {
+            items += (size_t)((batch[i1]->N + 63) / 64);
+            ++i1;
+        }
+        if (launch_sweep_packed(PATH_F32, batch[i0]->d, s.tests_d, s.items_d + item0, (int64_t)items,
+                                bb, s.stream) != hipSuccess) {
+            error = "packed sweep launch failed";
+            return false;
+        }
+        item0 += items;
+        i0 = i1;
+    }
+    if (launch_reduce_packed(s.tests_d, (int64_t)batch.size(), bb, s.res_d, s.stream) != hipSuccess ||
+        hipMemcpyAsync(s.res_h, s.res_d, batch.size() * sizeof(ResultDev), hipMemcpyDeviceToHost,
+                       s.stream) != hipSuccess ||
+        hipEventRecord(s.done, s.stream) != hipSuccess) {
+        error = "packed reduction launch failed";
+        return false;
+    }
+    s.reqs = batch;
+    s.busy = true;
+    launches += 1;
+    launched_tests += batch.size();
+    return true;
+}
+
+// Called with m held, after s.done completed.
+void Serve::retire(Slot &s)
+{
+    const auto now = Clock::now();
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+        Req *r = s.reqs[i];
+        const ResultDev &x = s.res_h[i];
+        r->result.num = x.num;
+        r->result.den = (uint64_t)r->n_p * (uint64_t)r->n_q;
+        r->result.D = (double)x.num / (double)r->result.den;
+        r->result.argmax_origin = x.origin;
+        r->result.argmax_orthant = x.code;
+        r->result.d = r->d;
+        r->result.n_p = r->n_p;
+        r->result.n_q = r->n_q;
+        r->status = DDKS_OK;
+        r->done = true;
+        r->t_done = now;
+        arena.release((size_t)r->off, r->bytes);
+        r->off = -1;
+        std::vector<float>().swap(r->data);
+        completed += 1;
+        lat_us.push_back(std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count());
+    }
+    s.reqs.clear();
+    s.busy = false;
+}
+
+void Serve::loop()
+{
+    (void)hipSetDevice(c->device);
+    // cap on work items per launch, so that a flood of requests still yields
+    // several launches that overlap instead of one long one
+    const size_t max_items = 1u << 16;
+    std::unique_lock<std::mutex> lk(m);
+    while (true) {
+        bool progress = false;
+        for (Slot &s : slots) {
+            if (!s.busy) continue;
+            hipError_t q = hipEventQuery(s.done);
+            if (q == hipSuccess) {
+                retire(s);
+                progress = true;
+            } else if (q != hipErrorNotReady) {
+                failed = true;
+                error = std::string("device error in serving: ") + hipGetErrorString(q);
+            }
+        }
+        if (progress) cv_done.notify_all();
+        while (!pending.empty() && !failed) {
+            Req *r = pending.front();
+            int64_t off = arena.alloc(r->bytes);
+            if (off < 0) break;
+            r->off = off;
+            ready.push_back(r);
+            pending.pop_front();
+        }
+        if (!ready.empty() && !failed) {
+            Slot *free_slot = nullptr;
+            for (Slot &s : slots)
+                if (!s.busy) {
+                    free_slot = &s;
+                    break;
+                }
+            if (free_slot) {
+                std::vector<Req *> batch;
+                size_t items = 0;
+                while (!ready.empty()) {
+                    Req *r = ready.front();
+                    size_t gi = (size_t)((r->N + 63) / 64);
+                    if (!batch.empty() && items + gi > max_items) break;
+                    batch.push_back(r);
+                    items += gi;
+                    ready.pop_front();
+                }
+                if (!launch_batch(*free_slot, batch)) failed = true;
+                progress = true;
+            }
+        }
+        if (failed) {
+            // fail every request still held and stop launching
+            auto fail_req = [&](Req *r) {
+                if (!r->done) {
+                    r->status = DDKS_E_DEVICE;
+                    r->done = true;
+                }
+            };
+            for (Req *r : pending) fail_req(r);
+            for (Req *r : ready) fail_req(r);
+            for (Slot &s : slots)
+                for (Req *r : s.reqs) fail_req(r);
+            pending.clear();
+            ready.clear();
+            c->poisoned = true;
+            cv_done.notify_all();
+        }
+        bool inflight = false;
+        for (Slot &s : slots) inflight |= s.busy;
+        if (stop && pending.empty() && ready.empty() && !inflight) break;
+        if (failed && !inflight) {
+            if (stop) break;
+            cv_sched.wait(lk);
+            continue;
+        }
+        if (progress) continue;
+        if (inflight)
+            cv_sched.wait_for(lk, std::chrono::microseconds(20));
+        else
+            cv_sched.wait(lk);
+    }
+}
+
+int serve_start(ddks_ctx *c)
+{
+    if (c->serve) return DDKS_OK;
+    Serve *sv = new (std::nothrow) Serve();
+    if (!sv) return DDKS_E_NOMEM;
+    sv->c = c;
+    // the arena takes what the budget leaves, up to 8 GB
+    uint64_t left = c->budget > c->used.load() ? c->budget - c->used.load() : 0;
+    uint64_t arena = std::min<uint64_t>(left, 8ull << 30);
+    arena &= ~(uint64_t)255;
+    if (arena < 4096) {
+        delete sv;
+        return fail(c, DDKS_E_NOMEM, "no device memory budget left for serving");
+    }
+    if (hipMalloc(&sv->arena_base, arena) != hipSuccess) {
+        (void)hipGetLastError();
+        delete sv;
+        return fail(c, DDKS_E_NOMEM, "serving arena allocation failed");
+    }
+    c->used += arena;
+    sv->arena.init(arena);
+    sv->slots.resize((size_t)std::max(1, c->serve_streams));
+    for (Slot &s : sv->slots) {
+        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+            c->serve = sv;
+            serve_stop(c);
+            return hip_check(c, hipErrorOutOfMemory, "serving stream creation");
+        }
+    }
+    c->serve = sv;
+    sv->th = std::thread([sv] { sv->loop(); });
+    return DDKS_OK;
+}
+
+void serve_stop(ddks_ctx *c)
+{
+    Serve *sv = c->serve;
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->m);
+        sv->stop = true;
+    }
+    sv->cv_sched.notify_all();
+    if (sv->th.joinable()) sv->th.join();
+    for (Slot &s : sv->slots) {
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.tests_h) (void)hipHostFree(s.tests_h);
+        if (s.tests_d) (void)hipFree(s.tests_d);
+        if (s.items_h) (void)hipHostFree(s.items_h);
+        if (s.items_d) (void)hipFree(s.items_d);
+        if (s.res_h) (void)hipHostFree(s.res_h);
+        if (s.res_d) (void)hipFree(s.res_d);
+    }
+    if (sv->arena_base) {
+        (void)hipFree(sv->arena_base);
+        c->used -= sv->arena.size;
+    }
+    for (auto &kv : sv->table) delete kv.second;
+    delete sv;
+    c->serve = nullptr;
+}
+
+}  // namespace ddks
+
+using namespace ddks;
+
+extern "C" {
+
+int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
+{
+    if (!c) return DDKS_E_INVALID_ARG;
+    if (!req || !ticket || !req->P || !req->Q) return fail(c, DDKS_E_INVALID_ARG, "null pointer argument");
+    if (req->d < 1 || req->d > 8) return fail(c, DDKS_E_INVALID_ARG, "d must be in [1, 8]");
+    if (req->n_p < 1 || req->n_q < 1) return fail(c, DDKS_E_INVALID_ARG, "each sample needs at least one point");
+    const int64_t N = req->n_p + req->n_q;
+    if (N > packed_max_points(req->d))
+        return fail(c, DDKS_E_NOT_SUPPORTED, "serving handles at most 262140 points (131070 at d = 8); use ddks_distance");
+    if (c->poisoned) return fail(c, DDKS_E_DEVICE, "context poisoned by an earlier device error");
+    {
+        std::lock_guard<std::mutex> lk(c->serve_mu);
+        if (!c->serve) {
+            std::lock_guard<std::mutex> lk2(c->mu);
+            if (hipSetDevice(c->device) != hipSuccess) return hip_check(c, hipGetLastError(), "hipSetDevice");
+            int st = serve_start(c);
+            if (st) return st;
+        }
+    }
+    Serve *sv = c->serve;
+    Req *r = new (std::nothrow) Req();
+    if (!r) return DDKS_E_NOMEM;
+    r->d = req->d;
+    r->n_p = req->n_p;
+    r->n_q = req->n_q;
+    r->N = N;
+    const size_t np_el = (size_t)req->n_p * req->d, nq_el = (size_t)req->n_q * req->d;
+    try {
+        r->data.resize(np_el + nq_el);
+    } catch (...) {
+        delete r;
+        return DDKS_E_NOMEM;
+    }
+    bool finite = true;
+    for (size_t i = 0; i < np_el; ++i) {
+        float v = req->P[i];
+        finite &= std::isfinite(v);
+        r->data[i] = v + 0.0f;  // -0 -> +0
+    }
+    for (size_t i = 0; i < nq_el; ++i) {
+        float v = req->Q[i];
+        finite &= std::isfinite(v);
+        r->data[np_el + i] = v + 0.0f;
+    }
+    if (!finite) {
+        delete r;
+        return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
+    }
+    r->pts_bytes = align256((np_el + nq_el) * sizeof(float));
+    r->bytes = r->pts_bytes + align256((size_t)((N + 63) / 64) * sizeof(BlockBest));
+    std::lock_guard<std::mutex> lk(sv->m);
+    if (sv->failed) {
+        delete r;
+        return fail(c, DDKS_E_DEVICE, sv->error);
+    }
+    if (r->bytes > sv->arena.size) {
+        sv->rej_nomem += 1;
+        delete r;
+        return fail(c, DDKS_E_NOMEM, "request can never fit the serving memory budget");
+    }
+    if (sv->held >= (size_t)c->serve_queue_depth) {
+        sv->rej_again += 1;
+        delete r;
+        return DDKS_E_AGAIN;
+    }
+    r->ticket = sv->next_ticket++;
+    r->t_submit = Clock::now();
+    sv->table[r->ticket] = r;
+    sv->pending.push_back(r);
+    sv->held += 1;
+    sv->submitted += 1;
+    *ticket = r->ticket;
+    sv->cv_sched.notify_one();
+    return DDKS_OK;
+}
+
+int ddks_serve_poll(ddks_ctx *c, uint64_t ticket, int32_t timeout_us, ddks_result *out)
+{
+    if (!c || !out) return DDKS_E_INVALID_ARG;
+    Serve *sv = c->serve;
+    if (!sv) return DDKS_E_UNKNOWN_TICKET;
+    std::unique_lock<std::mutex> lk(sv->m);
+    auto itr = sv->table.find(ticket);
+    if (itr == sv->table.end()) return DDKS_E_UNKNOWN_TICKET;
+    Req *r = itr->second;
+    if (!r->done) {
+        if (timeout_us < 0)
+            sv->cv_done.wait(lk, [&] { return r->done; });
+        else if (timeout_us > 0)
+            sv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return r->done; });
+    }
+    if (!r->done) return DDKS_E_PENDING;
+    const int st = r->status;
+    if (st == DDKS_OK) *out = r->result;
+    sv->table.erase(itr);
+    sv->held -= 1;
+    delete r;
+    return st;
+}
+
+int ddks_serve_stats_get(ddks_ctx *c, ddks_serve_stats *out, int32_t reset)
+{
+    if (!c || !out) return DDKS_E_INVALID_ARG;
+    memset(out, 0, sizeof(*out));
+    Serve *sv = c->serve;
+    if (!sv) return DDKS_OK;
+    std::lock_guard<std::mutex> lk(sv->m);
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->rejected_again = sv->rej_again;
+    out->rejected_nomem = sv->rej_nomem;
+    out->launches = sv->launches;
+    out->mean_batch = sv->launches ? (double)sv->launched_tests / (double)sv->launches : 0.0;
+    out->resident_bytes = sv->arena.size;
+    for (auto &kv : sv->arena.free_) out->resident_bytes -= kv.second;
+    if (!sv->lat_us.empty()) {
+        std::vector<double> v = sv->lat_us;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) {
+            size_t i = (size_t)std::min<double>((double)v.size() - 1, q * (double)(v.size() - 1) + 0.5);
+            return v[i];
+        };
+        out->p50_latency_us = pct(0.50);
+        out->p99_latency_us = pct(0.99);
+    }
+    if (reset) {
+        sv->submitted = sv->completed = sv->rej_again = sv->rej_nomem = 0;
+        sv->launches = sv->launched_tests = 0;
+        sv->lat_us.clear();
+    }
+    return DDKS_OK;
+}
+
+}  // extern "C"

@@ -90,21 +90,23 @@ __device__ __forceinline__ void finish_block(Get get, int64_t group, int64_t N, 
     }
 }
 
+// One block of the sweep: origins group*64 .. group*64+63 against the points
+// of chunk `chunk` (of nchunks), split across the W waves.  With nchunks == 1
+// the block scores in place and writes block_best[group] (and counts);
+// otherwise it writes its partial counts.
 template <int D, int PATH, int W>
-__global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, int64_t N,
-                                                  int64_t n_p, int64_t n_q, int64_t chunk_len,
-                                                  int64_t groups, uint2 *__restrict__ partial,
-                                                  BlockBest *__restrict__ block_best,
-                                                  uint32_t *__restrict__ counts)
+__device__ __forceinline__ void sweep_block(const void *__restrict__ Zv, int64_t N, int64_t n_p,
+                                            int64_t n_q, int64_t chunk_len, int64_t chunk,
+                                            int64_t nchunks, int64_t group, int64_t groups,
+                                            uint2 *__restrict__ partial,
+                                            BlockBest *__restrict__ block_best,
+                                            uint32_t *__restrict__ counts, uint32_t *smem)
 {
     typedef typename Layout<PATH, D>::T T;
     constexpr int BINS = Geo<D>::BINS;
-    extern __shared__ uint32_t smem[];
     const T *__restrict__ Z = static_cast<const T *>(Zv);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t group = blockIdx.x;
-    const int64_t chunk = blockIdx.y;
 
     for (int i = threadIdx.x; i < W * BINS * 64; i += W * 64) smem[i] = 0;
 
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, i
     sweep_range<PATH, D>(Z, a > n_p ? a : n_p, b, org, base, 0x10000u);
     __syncthreads();
 
-    if (gridDim.y == 1) {
+    if (nchunks == 1) {
         auto get = [&](int j) {
             uint32_t cp = 0, cq = 0;
 #pragma unroll
@@ -154,6 +156,32 @@ __global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, i
             partial[((chunk * groups + group) * BINS + j) * 64 + lane] = make_uint2(cp, cq);
         }
     }
+}
+
+template <int D, int PATH, int W>
+__global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, int64_t N,
+                                                  int64_t n_p, int64_t n_q, int64_t chunk_len,
+                                                  int64_t groups, uint2 *__restrict__ partial,
+                                                  BlockBest *__restrict__ block_best,
+                                                  uint32_t *__restrict__ counts)
+{
+    extern __shared__ uint32_t smem[];
+    sweep_block<D, PATH, W>(Zv, N, n_p, n_q, chunk_len, blockIdx.y, gridDim.y, blockIdx.x, groups,
+                            partial, block_best, counts, smem);
+}
+
+// Many tests of one dimension in one launch: block i sweeps work item
+// items[i] = (test, origin group), each test in a single chunk.
+template <int D, int PATH, int W>
+__global__ __launch_bounds__(W * 64) void k_sweep_packed(const PackedTest *__restrict__ tests,
+                                                         const int2 *__restrict__ items,
+                                                         BlockBest *__restrict__ block_best)
+{
+    extern __shared__ uint32_t smem[];
+    const int2 it = items[blockIdx.x];
+    const PackedTest t = tests[it.x];
+    sweep_block<D, PATH, W>(t.Z, t.N, t.n_p, t.n_q, t.N, 0, 1, it.y, t.groups, nullptr,
+                            block_best + t.bb_offset, nullptr, smem);
 }
 
 template <int D, int W>
@@ -218,6 +246,51 @@ __global__ __launch_bounds__(1024) void k_reduce(const BlockBest *__restrict__ b
         out->code = code;
         out->flags = *flags;
         *flags = 0u;
+    }
+}
+
+// One block per packed test: reduce its block results into out[test].
+__global__ __launch_bounds__(256) void k_reduce_packed(const PackedTest *__restrict__ tests,
+                                                       const BlockBest *__restrict__ bb,
+                                                       ResultDev *__restrict__ out)
+{
+    __shared__ uint64_t sn[4];
+    __shared__ uint32_t so[4];
+    __shared__ int32_t sc[4];
+    const PackedTest t = tests[blockIdx.x];
+    uint64_t best = 0;
+    uint32_t org = 0xffffffffu;
+    int32_t code = 0x7fffffff;
+    for (int64_t i = threadIdx.x; i < t.groups; i += blockDim.x) {
+        BlockBest b = bb[t.bb_offset + i];
+        if (better(b.num, b.origin, b.code, best, org, code)) {
+            best = b.num;
+            org = b.origin;
+            code = b.code;
+        }
+    }
+    wave_best(best, org, code);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sn[w] = best;
+        so[w] = org;
+        sc[w] = code;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; ++v)
+            if (better(sn[v], so[v], sc[v], best, org, code)) {
+                best = sn[v];
+                org = so[v];
+                code = sc[v];
+            }
+        ResultDev r;
+        r.num = best;
+        r.origin = (int64_t)org;
+        r.code = code;
+        r.flags = 0;
+        r.ge = 0;
+        out[blockIdx.x] = r;
     }
 }
 
@@ -342,6 +415,51 @@ hipError_t launch_sweep(const SweepPlan &p, const void *Z, int64_t N, int64_t n_
     if (p.path == PATH_F32) return launch_sweep_p<PATH_F32>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     if (p.path == PATH_R16) return launch_sweep_p<PATH_R16>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     return hipErrorInvalidValue;
+}
+
+template <int D, int PATH, int W>
+static hipError_t launch_packed_t(const PackedTest *tests, const int2 *items, int64_t nitems,
+                                  BlockBest *bb, hipStream_t s)
+{
+    SweepPlan p;
+    p.d = D;
+    p.waves = W;
+    const size_t lds = sweep_lds_bytes(p);
+    static bool attr_set = false;
+    if (!attr_set && lds > 64 * 1024) {
+        if (hipFuncSetAttribute((const void *)k_sweep_packed<D, PATH, W>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            (void)hipGetLastError();
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sweep_packed<D, PATH, W>), dim3((unsigned)nitems), dim3(W * 64), lds, s,
+                       tests, items, bb);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_packed(int path, int d, const PackedTest *tests, const int2 *items,
+                               int64_t nitems, BlockBest *bb, hipStream_t s)
+{
+    if (nitems < 1 || nitems > 0x7fffffff) return hipErrorInvalidValue;
+    if (path != PATH_F32) return hipErrorInvalidValue;
+    switch (d) {
+    case 1: return launch_packed_t<1, PATH_F32, 4>(tests, items, nitems, bb, s);
+    case 2: return launch_packed_t<2, PATH_F32, 4>(tests, items, nitems, bb, s);
+    case 3: return launch_packed_t<3, PATH_F32, 4>(tests, items, nitems, bb, s);
+    case 4: return launch_packed_t<4, PATH_F32, 4>(tests, items, nitems, bb, s);
+    case 5: return launch_packed_t<5, PATH_F32, 4>(tests, items, nitems, bb, s);
+    case 6: return launch_packed_t<6, PATH_F32, 4>(tests, items, nitems, bb, s);
+    case 7: return launch_packed_t<7, PATH_F32, 4>(tests, items, nitems, bb, s);
+    case 8: return launch_packed_t<8, PATH_F32, 2>(tests, items, nitems, bb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce_packed(const PackedTest *tests, int64_t ntests, const BlockBest *bb,
+                                ResultDev *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_packed, dim3((unsigned)ntests), dim3(256), 0, s, tests, bb, out);
+    return hipGetLastError();
 }
 
 template <int D>

@@ -1,0 +1,141 @@
+"""GPU serving loop (continuous batching): every result equals the oracle's
+and the single-test path's for the same inputs, alone or in a mix of
+dimensions and sizes; admission under a memory budget, queue limits and
+error paths.  Integer results, tolerance 0."""
+import os
+import threading
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _mix(seed, count, nmax=3000):
+    g = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        d = int(g.integers(1, 9))
+        n_p = int(np.rint(np.exp(g.uniform(np.log(1), np.log(nmax)))))
+        n_q = int(np.rint(np.exp(g.uniform(np.log(1), np.log(nmax)))))
+        P = g.standard_normal((n_p, d)).astype(np.float32)
+        Q = (g.standard_normal((n_q, d)) + g.uniform(0, 0.3)).astype(np.float32)
+        if g.random() < 0.3:
+            P = np.rint(P * 2) / 2
+            Q = np.rint(Q * 2) / 2
+            P[P == 0] = -0.0
+        reqs.append((P.astype(np.float32), Q.astype(np.float32)))
+    return reqs
+
+
+def _key(r):
+    return (r.num, r.den, r.argmax_origin, r.argmax_orthant)
+
+
+def test_mix_matches_oracle_and_single_path(oracle_mod):
+    from paper_2106_13706_amd import native
+    reqs = _mix(1, 120)
+    with native.Context() as ctx:
+        tickets = [ctx.serve_submit(P, Q) for P, Q in reqs]
+        assert all(t > 0 for t in tickets)
+        got = [ctx.serve_poll(t) for t in tickets]
+        alone = []
+        for P, Q in reqs:
+            t = ctx.serve_submit(P, Q)
+            alone.append(ctx.serve_poll(t))
+        single = [ctx.distance(P, Q) for P, Q in reqs]
+        st = ctx.serve_stats()
+    for (P, Q), a, b, s in zip(reqs, got, alone, single):
+        o = oracle_mod.distance(P, Q, threads=THREADS)
+        assert _key(a) == _key(b) == _key(s) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+        assert a.D == o.D
+    assert st["completed"] == 240 and st["submitted"] == 240
+    assert st["launches"] >= 2 and st["p99_latency_us"] >= st["p50_latency_us"] > 0
+
+
+def test_concurrent_submitters(oracle_mod):
+    from paper_2106_13706_amd import native
+    reqs = _mix(2, 64, nmax=5000)
+    out = {}
+    with native.Context(serve_streams=3) as ctx:
+        def worker(idx):
+            for i in idx:
+                P, Q = reqs[i]
+                out[i] = ctx.serve_poll(ctx.serve_submit(P, Q))
+        ts = [threading.Thread(target=worker, args=(range(k, len(reqs), 4),)) for k in range(4)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+    for i, (P, Q) in enumerate(reqs):
+        o = oracle_mod.distance(P, Q, threads=THREADS)
+        assert _key(out[i]) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+
+
+def test_memory_budget_admission(oracle_mod):
+    """A budget that holds only a few requests at once: all still complete
+    (admitted as memory frees up); one that can never fit is refused."""
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(3)
+    reqs = [(g.standard_normal((10000, 8)).astype(np.float32),
+             g.standard_normal((10000, 8)).astype(np.float32)) for _ in range(6)]
+    with native.Context() as ref:
+        expected = [_key(ref.distance(P, Q)) for P, Q in reqs]
+    # 2 MiB of budget: each request needs 0.64 MB, so at most three are resident
+    with native.Context(mem_budget=2 << 20) as ctx:
+        tickets = [ctx.serve_submit(P, Q) for P, Q in reqs]
+        res = [ctx.serve_poll(t) for t in tickets]
+        assert [_key(r) for r in res] == expected
+        big = g.standard_normal((130000, 8)).astype(np.float32)
+        with pytest.raises(native.DDKSError) as e:
+            ctx.serve_submit(big[:65000], big[65000:])
+        assert e.value.status == native.DDKS_E_NOMEM
+        assert ctx.serve_stats()["rejected_nomem"] == 1
+
+
+def test_queue_full_and_errors():
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(4)
+    with native.Context(serve_queue_depth=3) as ctx:
+        P = g.standard_normal((50, 3)).astype(np.float32)
+        tickets = [ctx.serve_submit(P, P + 1) for _ in range(3)]
+        assert ctx.serve_submit(P, P + 1) == -1  # DDKS_E_AGAIN
+        assert ctx.serve_stats()["rejected_again"] == 1
+        for t in tickets:
+            assert ctx.serve_poll(t) is not None
+        assert ctx.serve_submit(P, P + 1) > 0  # room again after collection
+        with pytest.raises(native.DDKSError) as e:
+            ctx.serve_poll(987654)
+        assert e.value.status == native.DDKS_E_UNKNOWN_TICKET
+        bad = P.copy()
+        bad[3, 1] = np.nan
+        with pytest.raises(native.DDKSError) as e:
+            ctx.serve_submit(bad, P)
+        assert e.value.status == native.DDKS_E_NONFINITE
+        with pytest.raises(native.DDKSError) as e:
+            ctx.serve_submit(np.zeros((3, 9), np.float32), np.zeros((3, 9), np.float32))
+        assert e.value.status == native.DDKS_E_INVALID_ARG
+
+
+def test_poll_timeout_reports_pending():
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(5)
+    with native.Context() as ctx:
+        P = g.standard_normal((60000, 8)).astype(np.float32)
+        Q = g.standard_normal((60000, 8)).astype(np.float32)
+        t = ctx.serve_submit(P, Q)
+        assert ctx.serve_poll(t, timeout_us=0) is None
+        r = ctx.serve_poll(t, timeout_us=-1)
+        assert r is not None and r.den == 60000 * 60000
+
+
+def test_destroy_with_outstanding_requests():
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(6)
+    ctx = native.Context()
+    for _ in range(20):
+        ctx.serve_submit(g.standard_normal((3000, 4)).astype(np.float32),
+                         g.standard_normal((2000, 4)).astype(np.float32))
+    ctx.close()  # drains the serving loop and frees everything
