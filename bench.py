@@ -31,11 +31,6 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
-
-
 def _traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, or None if
     the kernel source changed since the counters were taken."""
@@ -43,10 +38,17 @@ def _traffic(kernel, workload):
     if not os.path.exists(p):
         return None
     t = json.load(open(p))
-    src = os.path.join(ROOT, t["source"])
-    if not os.path.exists(src) or _sha(src) != t["source_sha256"]:
+    if _sources_sha(t["sources"]) != t["sources_sha256"]:
         return None
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+
+
+def _sources_sha(sources):
+    h = hashlib.sha256()
+    for s in sources:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _time_distance(ctx, P, Q, steps, warmup, torch):
@@ -84,6 +86,129 @@ def cpu_baseline(P, Q, compares):
                          f"{len(times)} run(s), {med:.2f} s each"}
 
 
+def bench_batch(ctx, torch, dev, reps=5):
+    """Permutation batch (d=5, pooled 2x4096, 1024 relabellings): one call =
+    observed split + all relabellings, replayed from a captured graph; against
+    sequential plain calls on device-resident relabelled samples."""
+    import numpy as np
+    from paper_2106_13706_amd import workloads
+    Z, n_p, labels = workloads.permutation()
+    n, d = Z.shape
+    B = labels.shape[0]
+    Zt = torch.from_numpy(Z).to(dev)
+    Lt = torch.from_numpy(labels.view(np.int32)).to(dev)
+    nums, obs, summ = ctx.permutation_batch(Zt, n_p, Lt)  # capture
+    torch.cuda.synchronize()
+    ctx.profile(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nums, obs, summ = ctx.permutation_batch(Zt, n_p, Lt)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    prof = ctx.profile(reset=True)
+    gpu_ms = prof["batch_ms"] / max(1, prof["batches"])
+    eff = B * n * n * d
+    # sequential plain calls: relabelled samples gathered on the device first
+    bits = np.unpackbits(labels.view(np.uint8), bitorder="little").reshape(B, -1)[:, :n].astype(bool)
+    nseq = 32
+    pairs = []
+    for b in range(nseq):
+        m = torch.from_numpy(bits[b]).to(dev)
+        pairs.append((Zt[m].contiguous(), Zt[~m].contiguous()))
+    for P_, Q_ in pairs[:4]:
+        ctx.distance(P_, Q_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_nums = [ctx.distance(P_, Q_).num for P_, Q_ in pairs]
+    torch.cuda.synchronize()
+    seq_sec = (time.perf_counter() - t0) / nseq
+    assert seq_nums == [int(x) for x in nums[:nseq].cpu().numpy().view(np.uint64)]
+    return {"workload": "permutation_d5_8192x1024", "ms_per_batch": sec * 1e3,
+            "gpu_ms_per_batch": gpu_ms, "tests_per_s": B / sec,
+            "effective_compares_per_s": eff / sec,
+            "effective_frac_of_valu_peak": (eff / sec) / VALU_COMPARE_PEAK,
+            "sequential_plain_calls_tests_per_s": 1.0 / seq_sec,
+            "speedup_vs_sequential": (B / sec) * seq_sec,
+            "p_value": summ["p_value"], "observed_D": obs.D}
+
+
+def bench_serving(ctx_factory, n_requests, seed_rate=None):
+    """Serving: Poisson-arrival stream of tests, d uniform in 2..8, n_P and n_Q
+    log-uniform in [64, 65536].  Runs: sequential plain calls (capacity
+    mu_seq), saturation (everything submitted at once) and open-loop arrivals
+    at rate mu_seq.  Inputs are slices of a seeded pool of N(0,1) draws (Q
+    shifted by delta), so the host does not generate gigabytes of normals."""
+    import threading
+    import numpy as np
+    from paper_2106_13706_amd import workloads
+    stream = workloads.serving_stream(n_requests=n_requests, materialize=False)
+    g = np.random.default_rng(workloads.SEED_BASE + 55)
+    pool = {d: g.standard_normal((2 * 65536 + 1024, d)).astype(np.float32) for d in range(2, 9)}
+    offs = g.integers(0, 65536, size=(len(stream.requests), 2))
+
+    def data(i):
+        r = stream.requests[i]
+        n_p, n_q = r.P.shape[0], r.Q.shape[0]
+        P = pool[r.d][offs[i, 0]:offs[i, 0] + n_p]
+        Q = pool[r.d][65536 + offs[i, 1]:65536 + offs[i, 1] + n_q] + np.float32(r.delta)
+        return P, Q
+
+    total_compares = sum((r.P.shape[0] + r.Q.shape[0]) ** 2 * r.d for r in stream.requests)
+    out = {"workload": f"serving_{n_requests}", "requests": n_requests,
+           "total_compares": total_compares}
+    inputs = [data(i) for i in range(len(stream.requests))]
+
+    with ctx_factory() as ctx:
+        # sequential plain calls
+        t0 = time.perf_counter()
+        seq = [ctx.distance(P, Q).num for P, Q in inputs]
+        seq_s = time.perf_counter() - t0
+    mu_seq = n_requests / seq_s
+    out["sequential_plain_calls_tests_per_s"] = mu_seq
+
+    def run(rate):
+        with ctx_factory() as ctx:
+            tickets = [None] * n_requests
+            got = [None] * n_requests
+            done = threading.Event()
+
+            def poller():
+                for i in range(n_requests):
+                    while tickets[i] is None:
+                        time.sleep(0.0002)
+                    got[i] = ctx.serve_poll(tickets[i]).num
+                done.set()
+
+            th = threading.Thread(target=poller)
+            th.start()
+            t0 = time.perf_counter()
+            for i, (P, Q) in enumerate(inputs):
+                if rate:
+                    wait = stream.requests[i].t_arrival * (1000.0 / rate) - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                t = -1
+                while t < 0:
+                    t = ctx.serve_submit(P, Q)
+                    if t < 0:
+                        time.sleep(0.0005)
+                tickets[i] = t
+            th.join()
+            wall = time.perf_counter() - t0
+            st = ctx.serve_stats()
+            assert got == seq, "served results differ from the plain calls"
+            return {"tests_per_s": n_requests / wall, "wall_s": wall,
+                    "p50_latency_ms": st["p50_latency_us"] / 1e3,
+                    "p99_latency_ms": st["p99_latency_us"] / 1e3,
+                    "launches": st["launches"], "mean_tests_per_launch": st["mean_batch"],
+                    "compares_per_s": total_compares / wall}
+
+    out["saturation"] = run(None)
+    out["open_loop_at_mu_seq"] = run(mu_seq)
+    out["open_loop_at_mu_seq"]["arrival_rate_per_s"] = mu_seq
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +216,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (lets profiled runs skip tuning launches)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (PMC calibration)")
     args = ap.parse_args()
@@ -104,7 +232,8 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    ctx = native.Context(stream=stream, flags=native.DDKS_PROFILE_KERNELS)
+    ctx = native.Context(stream=stream, flags=native.DDKS_PROFILE_KERNELS,
+                         tune_cache=args.tune_cache)
 
     workload = "gaussian_scale_d4_20000"
     P, Q = workloads.gaussian_scale()
@@ -166,6 +295,11 @@ def main():
             "kernel_avg_ms": k3 * 1e3, "frac": (c3 / k3) / VALU_COMPARE_PEAK,
             "num": r3.num, "den": r3.den}
         del P3t, Q3t
+        _log("[bench] extra: permutation batch")
+        extras["permutation_batch"] = bench_batch(ctx, torch, dev)
+        _log(f"[bench] extra: serving ({args.serve_requests} requests)")
+        extras["serving"] = bench_serving(
+            lambda: native.Context(flags=native.DDKS_NO_AUTOTUNE), args.serve_requests)
     if extras:
         line["extras"] = extras
 
