@@ -264,8 +264,44 @@ __device__ __forceinline__ void signs(const typename Layout<PATH, D>::T *xs,
     }
 }
 
+// LDS bin addresses of U consecutive points held in buf (U a multiple of 4).
+template <int PATH, int D, int U>
+__device__ __forceinline__ void block_addrs(const typename Layout<PATH, D>::T *buf,
+                                            const Origin<PATH, D> &org, uint32_t base,
+                                            uint32_t (&a)[U])
+{
+    constexpr int PW = Layout<PATH, D>::PW;
+    constexpr int NP = Geo<D>::NPERM;
+    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+#pragma unroll
+    for (int g = 0; g < U; g += 4) {
+        uint32_t R[2][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t r[Geo<D>::NREG];
+            signs<PATH, D>(buf + (g + u) * PW, org, r);
+            R[0][u] = group_bytes<D>(r, 0);
+            R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+        }
+        uint32_t q[4];
+        addr4<NP>(R, base, q, w0, w1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[g + u] = q[u];
+    }
+}
+
+// Waits for every outstanding LDS and scalar-memory operation of the wave
+// (lgkmcnt = 0; vector-memory and export counters left alone).
+__device__ __forceinline__ void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xc07f); }
+
 // Sweeps points [lo, hi) of Z against the lane's origin, adding inc to the
 // lane's bin of each point.  base: LDS byte address of bin KOFF of this lane.
+//
+// Software-pipelined: the scalar loads of block i+1 are issued before block
+// i's addresses are computed, and the wait before block i's LDS atomics then
+// covers only loads and atomics issued a whole block earlier.  (Scalar loads
+// and LDS operations share one wait counter, so waiting for a block's points
+// right after loading them would also wait for the atomics just issued.)
 template <int PATH, int D>
 __device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *__restrict__ Z,
                                             int64_t lo, int64_t hi, const Origin<PATH, D> &org,
@@ -275,29 +311,50 @@ __device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *_
     constexpr int PW = Layout<PATH, D>::PW;
     constexpr int U = Unroll<PATH, D>::U;
     constexpr int NP = Geo<D>::NPERM;
-    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
     int64_t i = lo;
-    for (; i + U <= hi; i += U) {
-        const T *blk = Z + i * PW;
+    int64_t nblk = hi > lo ? (hi - lo) / U : 0;
+    if (nblk & 1) {  // an odd block first, so the pipelined loop runs in pairs
         T buf[U * PW];
 #pragma unroll
-        for (int e = 0; e < U * PW; ++e) buf[e] = blk[e];
+        for (int e = 0; e < U * PW; ++e) buf[e] = Z[i * PW + e];
+        uint32_t a[U];
+        block_addrs<PATH, D, U>(buf, org, base, a);
 #pragma unroll
-        for (int g = 0; g < U; g += 4) {
-            uint32_t R[2][4];
+        for (int u = 0; u < U; ++u) lds_add(a[u], inc);
+        i += U;
+        --nblk;
+    }
+    if (nblk > 0) {
+        // Two blocks per trip and no exit in between, so no load can be moved
+        // past the block that consumes it.  The last trip's prefetch is clamped
+        // to the last full block (a redundant, in-bounds load).
+        const int64_t last = hi - U;
+        T bufA[U * PW], bufB[U * PW];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint32_t r[Geo<D>::NREG];
-                signs<PATH, D>(buf + (g + u) * PW, org, r);
-                R[0][u] = group_bytes<D>(r, 0);
-                R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-            }
-            uint32_t a[4];
-            addr4<NP>(R, base, a, w0, w1);
+        for (int e = 0; e < U * PW; ++e) bufA[e] = Z[i * PW + e];
+        // Settle everything issued before the loop here, once: otherwise the
+        // counter state merged at the loop head forces a full wait (on this
+        // trip's ds_adds as well) at the top of every trip.
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int64_t t = 0; t < nblk; t += 2) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) lds_add(a[u], inc);
+            for (int e = 0; e < U * PW; ++e) bufB[e] = Z[(i + U) * PW + e];
+            uint32_t a[U];
+            block_addrs<PATH, D, U>(bufA, org, base, a);
+            wait_lgkm();
+#pragma unroll
+            for (int u = 0; u < U; ++u) lds_add(a[u], inc);
+            const int64_t na = (i + 2 * U < last) ? i + 2 * U : last;
+#pragma unroll
+            for (int e = 0; e < U * PW; ++e) bufA[e] = Z[na * PW + e];
+            block_addrs<PATH, D, U>(bufB, org, base, a);
+            wait_lgkm();
+#pragma unroll
+            for (int u = 0; u < U; ++u) lds_add(a[u], inc);
+            i += 2 * U;
         }
     }
+    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
     for (; i < hi; ++i) {
         const T *xs = Z + i * PW;
         T buf[PW];

@@ -32,7 +32,10 @@ int hip_check(ddks_ctx *c, hipError_t e, const char *what)
 
 int ensure(ddks_ctx *c, DevBuf &b, size_t bytes, const char *what)
 {
-    if (bytes == 0) bytes = 256;
+    // 256 bytes of slack past every buffer: the sweep's wave-uniform point
+    // reads are merged into wide scalar loads, which may run up to 128 bytes
+    // past the last point they use.
+    bytes += 256;
     if (b.bytes >= bytes) return DDKS_OK;
     // grow geometrically to limit reallocations across calls of rising size
     size_t want = std::max(bytes, b.bytes + b.bytes / 2);

@@ -352,7 +352,7 @@ int serve_start(ddks_ctx *c)
         delete sv;
         return fail(c, DDKS_E_NOMEM, "no device memory budget left for serving");
     }
-    if (hipMalloc(&sv->arena_base, arena) != hipSuccess) {
+    if (hipMalloc(&sv->arena_base, arena + 256) != hipSuccess) {  // + slack for wide scalar loads
         (void)hipGetLastError();
         delete sv;
         return fail(c, DDKS_E_NOMEM, "serving arena allocation failed");
