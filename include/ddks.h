@@ -173,8 +173,13 @@ typedef struct ddks_serve_stats {
  * queue slots free up, and packed into shared launches).  The library
  * copies P and Q before returning; the caller may free them at once.
  * Thread-safe.  *ticket identifies the request for ddks_serve_poll.
+ * Each test is swept by one block shape whose 16-bit per-sample counters
+ * bound a sample to about 8 * 65535 points (4 * 65535 at d = 7, 2 * 65535
+ * at d = 8); larger tests get DDKS_E_NOT_SUPPORTED (ddks_distance has no
+ * such bound).
  * Errors: DDKS_E_AGAIN (queue full), DDKS_E_NOMEM (can never fit the
- * budget), DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_DEVICE.
+ * budget), DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOT_SUPPORTED,
+ * DDKS_E_DEVICE.
  */
 int ddks_serve_submit(ddks_ctx *ctx, const ddks_request *req, uint64_t *ticket);
 

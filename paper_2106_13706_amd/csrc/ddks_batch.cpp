@@ -80,7 +80,7 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
     a.pb = perm_max_group(d);
     a.path = choose_path(c, d, n, flags);
     if (a.path == PATH_R16 && n > 65536) a.path = PATH_F32;  // keep the pipeline free of host syncs
-    a.plan = plan_for(c, a.path, d, n, true);
+    a.plan = plan_for(c, a.path, d, n, n_p);
 
     // every buffer the pipeline touches, allocated before any capture
     const int64_t gq = (a.B + a.pb - 1) / a.pb;

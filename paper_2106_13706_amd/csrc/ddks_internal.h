@@ -30,16 +30,24 @@ struct PackedTest {
     int64_t N, n_p, n_q;
     int64_t groups;     // ceil(N / 64)
     int64_t bb_offset;  // first BlockBest slot of this test
+    int32_t hists;      // LDS histograms per block (sweep_hists for PACKED_WAVES, N)
+    int32_t path;       // PATH_F32 (Z fp32) or PATH_R16 (Z rank-encoded)
 };
+
+// LDS a block may use (gfx950: 160 KB per CU, all of it addressable by one block).
+constexpr int MAX_LDS_BYTES = 160 * 1024;
+// Waves per block of the packed (many-test) sweep.
+constexpr int PACKED_WAVES = 8;
 
 // Launch shape of one sweep.
 struct SweepPlan {
     int path = PATH_F32;
     int d = 1;
-    int waves = 4;          // waves per block; each wave owns one LDS histogram
+    int waves = 4;          // waves per block (1, 2, 4, 8, 16), all on the same 64 origins
+    int hists = 1;          // LDS histograms per block (power of two <= waves)
     int64_t groups = 0;     // ceil(N / 64) origin groups
     int64_t chunks = 1;     // point-range chunks (grid.y)
-    int64_t chunk_len = 0;  // points per chunk (<= waves * 65535)
+    int64_t chunk_len = 0;  // points per chunk
 };
 
 // Words (4-byte) per point in the device point buffer.
@@ -48,8 +56,18 @@ int point_words(int path, int d);
 // Bytes of dynamic LDS a sweep block of this plan uses.
 size_t sweep_lds_bytes(const SweepPlan &p);
 
-// Largest waves-per-block the LDS allows for this d (1..8).
+// Largest waves-per-block of the sweep kernels.
 int max_waves_for_d(int d);
+
+// Bytes of LDS of `hists` histograms of dimension d.
+size_t hist_lds_bytes(int d, int hists);
+
+// Smallest number of histograms per block (a power of two <= waves) with
+// which no 16-bit per-sample counter can overflow when chunks of chunk_len
+// points of a test with n_p + n_q points are swept by `waves` waves; 0 if
+// even one histogram per wave is not enough or the histograms do not fit in
+// LDS.
+int sweep_hists(int d, int waves, int64_t chunk_len, int64_t n_p, int64_t n_q);
 
 // ---------------------------------------------------------------- launches
 // All return the HIP error of the launch (hipSuccess on success).
@@ -90,11 +108,13 @@ hipError_t launch_reduce(const BlockBest *block_best, int64_t nblocks, uint32_t 
 
 // ---------------------------------------------------------------- packed tests
 
-// One launch over work items (test, origin group) of tests of dimension d,
-// each test swept in a single chunk (N <= waves * 65535 points); block results
-// go to bb[test.bb_offset + group].  Waves per block: 4 (d <= 7) or 2 (d = 8).
+// One launch over work items (test, origin group) of tests of dimension d on
+// one path, each test swept in a single chunk by PACKED_WAVES waves with
+// test.hists histograms (nonzero sweep_hists(d, PACKED_WAVES, N, n_p, n_q));
+// block results go to bb[test.bb_offset + group].  max_hists: the largest
+// test.hists of the launch (sizes the LDS).
 hipError_t launch_sweep_packed(int path, int d, const PackedTest *tests, const int2 *items,
-                               int64_t nitems, BlockBest *bb, hipStream_t s);
+                               int64_t nitems, int max_hists, BlockBest *bb, hipStream_t s);
 // out[t] = the test's maximum with the tie rule, for t < ntests.
 hipError_t launch_reduce_packed(const PackedTest *tests, int64_t ntests, const BlockBest *bb,
                                 ResultDev *out, hipStream_t s);

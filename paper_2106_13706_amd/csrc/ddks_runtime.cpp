@@ -80,7 +80,17 @@ void release(ddks_ctx *c, DevBuf &b)
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool /*want_counts*/)
+bool plan_complete(SweepPlan &p, int64_t N, int64_t n_p)
+{
+    if (p.waves != 1 && p.waves != 2 && p.waves != 4 && p.waves != 8 && p.waves != 16) return false;
+    p.groups = cdiv(N, 64);
+    p.chunks = std::max<int64_t>(1, std::min<int64_t>({p.chunks, N, 65535}));
+    p.chunk_len = cdiv(N, p.chunks);
+    p.hists = sweep_hists(p.d, p.waves, p.chunk_len, n_p, N - n_p);
+    return p.hists > 0;
+}
+
+SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p)
 {
     SweepPlan p;
     p.path = path;
@@ -88,13 +98,11 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool /*want_counts*/
     if (c && c->tuner && !(c->opt_flags & DDKS_NO_AUTOTUNE) && tuner_lookup(c->tuner, path, d, N, &p)) {
         p.path = path;
         p.d = d;
-        p.groups = cdiv(N, 64);
-        p.chunk_len = cdiv(N, p.chunks);
-        if (p.chunk_len <= (int64_t)p.waves * 65535) return p;
+        if (plan_complete(p, N, n_p)) return p;
     }
-    p.waves = d <= 7 ? 4 : 2;
-    if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 || c->force_waves == 8) &&
-        c->force_waves <= max_waves_for_d(d))
+    p.waves = 4;
+    if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 ||
+              c->force_waves == 8 || c->force_waves == 16))
         p.waves = c->force_waves;
     p.groups = cdiv(N, 64);
     // about 8 waves per SIMD over the 1024 SIMDs, each sweeping >= 256 points
@@ -102,12 +110,10 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool /*want_counts*/
     int64_t chunks = cdiv(target_waves, p.groups * p.waves);
     int64_t max_chunks = std::max<int64_t>(1, N / ((int64_t)p.waves * 256));
     chunks = std::min(chunks, max_chunks);
-    chunks = std::max<int64_t>(chunks, cdiv(N, (int64_t)p.waves * 65535));
-    if (c && c->force_chunks > 0) chunks = std::min(c->force_chunks, N);
-    chunks = std::max<int64_t>(chunks, cdiv(N, (int64_t)p.waves * 65535));
-    chunks = std::min<int64_t>(chunks, 65535);
+    if (c && c->force_chunks > 0) chunks = c->force_chunks;
     p.chunks = chunks;
-    p.chunk_len = cdiv(N, chunks);
+    // more chunks until the histograms of a block fit (16-bit counters, LDS)
+    while (!plan_complete(p, N, n_p) && p.chunks < std::min<int64_t>(N, 65535)) ++p.chunks;
     return p;
 }
 
@@ -356,7 +362,7 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     }
     st = tune_sweep(c, path, d, N, n_p, n_q, zdata);
     if (st) return st;
-    SweepPlan plan = plan_for(c, path, d, N, counts != nullptr);
+    SweepPlan plan = plan_for(c, path, d, N, n_p);
     st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, s);
     if (st) return st;
     st = hip_check(c, hipMemcpyAsync(c->result_host, c->result_dev, sizeof(ResultDev), hipMemcpyDeviceToHost, s), "D2H result");

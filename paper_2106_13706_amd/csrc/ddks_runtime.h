@@ -85,7 +85,12 @@ int ensure(ddks_ctx *c, DevBuf &b, size_t bytes, const char *what);
 void release(ddks_ctx *c, DevBuf &b);
 
 // Launch shape for one test of N points in dimension d on the given path.
-SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, bool want_counts);
+// Fills groups, chunk_len and hists of a plan whose path, d, waves and chunks
+// are set; false if no admissible histogram count exists for that shape.
+bool plan_complete(SweepPlan &p, int64_t N, int64_t n_p);
+// Launch shape for a sweep of N points (n_p of the first sample): the tuned
+// shape if there is one, else a heuristic.
+SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p);
 
 // Runs the sweep + score + reduce of one test whose points are already in a
 // device buffer (fp32 N x d at zf, and when path == PATH_R16 the rank

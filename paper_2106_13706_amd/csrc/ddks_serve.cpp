@@ -75,6 +75,7 @@ struct Req {
     uint64_t ticket = 0;
     int d = 0;
     int64_t n_p = 0, n_q = 0, N = 0;
+    int hists = 1;            // LDS histograms per block of its packed sweep
     std::vector<float> data;  // P then Q
     size_t pts_bytes = 0, bytes = 0;
     int64_t off = -1;
@@ -123,8 +124,6 @@ struct Serve {
     void retire(Slot &s);
     void loop();
 };
-
-static int64_t packed_max_points(int d) { return (d <= 7 ? 4 : 2) * (int64_t)65535; }
 
 int Serve::grow_slot(Slot &s, size_t tests, size_t items)
 {
@@ -182,6 +181,8 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         t.n_q = r->n_q;
         t.groups = (r->N + 63) / 64;
         t.bb_offset = (int64_t)((r->off + r->pts_bytes) / sizeof(BlockBest));
+        t.hists = r->hists;
+        t.path = PATH_F32;
         for (int64_t g = 0; g < t.groups; ++g) s.items_h[it++] = make_int2((int)i, (int)g);
         if (hipMemcpyAsync(base + r->off, r->data.data(), r->data.size() * sizeof(float),
                            hipMemcpyHostToDevice, s.stream) != hipSuccess) {
@@ -200,12 +201,14 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
     size_t i0 = 0, item0 = 0;
     while (i0 < batch.size()) {
         size_t i1 = i0, items = 0;
+        int max_hists = 1;
         while (i1 < batch.size() && batch[i1]->d == batch[i0]->d) {
             items += (size_t)((batch[i1]->N + 63) / 64);
+            max_hists = std::max(max_hists, batch[i1]->hists);
             ++i1;
         }
         if (launch_sweep_packed(PATH_F32, batch[i0]->d, s.tests_d, s.items_d + item0, (int64_t)items,
-                                bb, s.stream) != hipSuccess) {
+                                max_hists, bb, s.stream) != hipSuccess) {
             error = "packed sweep launch failed";
             return false;
         }
@@ -416,8 +419,12 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
     if (req->d < 1 || req->d > 8) return fail(c, DDKS_E_INVALID_ARG, "d must be in [1, 8]");
     if (req->n_p < 1 || req->n_q < 1) return fail(c, DDKS_E_INVALID_ARG, "each sample needs at least one point");
     const int64_t N = req->n_p + req->n_q;
-    if (N > packed_max_points(req->d))
-        return fail(c, DDKS_E_NOT_SUPPORTED, "serving handles at most 262140 points (131070 at d = 8); use ddks_distance");
+    // one block of PACKED_WAVES waves sweeps a whole test: its histograms must
+    // hold either sample's share without overflow and fit in LDS
+    const int hists = sweep_hists(req->d, PACKED_WAVES, N, req->n_p, req->n_q);
+    if (hists == 0)
+        return fail(c, DDKS_E_NOT_SUPPORTED,
+                    "a sample is too large for serving (about 8 * 65535 points per sample, 4 * 65535 at d = 7, 2 * 65535 at d = 8); use ddks_distance");
     if (c->poisoned) return fail(c, DDKS_E_DEVICE, "context poisoned by an earlier device error");
     {
         std::lock_guard<std::mutex> lk(c->serve_mu);
@@ -435,6 +442,7 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
     r->n_p = req->n_p;
     r->n_q = req->n_q;
     r->N = N;
+    r->hists = hists;
     const size_t np_el = (size_t)req->n_p * req->d, nq_el = (size_t)req->n_q * req->d;
     try {
         r->data.resize(np_el + nq_el);

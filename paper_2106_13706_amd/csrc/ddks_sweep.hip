@@ -2,9 +2,14 @@
 // Sec. 2.1 Eq. ddks_tensor_definition, Eq. g, Eq. membership, Eq. d1).
 //
 // Work decomposition: one origin per lane, 64 origins per wave; every wave of
-// a block holds the same 64 origins and sweeps its own share of the points,
-// so the block's waves are reduced in LDS and only the block's result leaves
-// the CU.  Points are read with wave-uniform (scalar) loads straight into
+// a block holds the same 64 origins and sweeps its own share of the points
+// (an equal part of the chunk's first-sample points and of its second-sample
+// points).  The block's waves add into H shared LDS histograms (wave w into
+// histogram w mod H; LDS atomics are atomic across waves), H chosen by the
+// host as the smallest power of two that keeps every per-sample counter of a
+// histogram within 16 bits, so usually one histogram serves the whole block
+// and the LDS a block needs does not grow with its wave count.  Only the
+// block's result leaves the CU.  Points are read with wave-uniform (scalar) loads straight into
 // SGPRs, so a point costs no VGPR traffic; each lane compares it with its own
 // origin:
 //
@@ -23,8 +28,8 @@
 // the LDS address of the orthant bin.  Histograms are lane-minor
 // (bin * 64 + lane), so a ds_add_u32 from a wave touches 64 distinct banks
 // slots whatever the codes are.  Counts of both samples share one 32-bit
-// counter: +1 for a point of P, +65536 for a point of Q (a wave never sweeps
-// more than 65535 points of either sample).
+// counter: +1 for a point of P, +65536 for a point of Q (no histogram ever
+// receives more than 65535 points of either sample).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -91,14 +96,15 @@ __device__ __forceinline__ void finish_block(Get get, int64_t group, int64_t N, 
 }
 
 // One block of the sweep: origins group*64 .. group*64+63 against the points
-// of chunk `chunk` (of nchunks), split across the W waves.  With nchunks == 1
+// of chunk `chunk` (of nchunks), split across the W waves, which add into
+// `hists` LDS histograms (1 <= hists <= W, a power of two).  With nchunks == 1
 // the block scores in place and writes block_best[group] (and counts);
 // otherwise it writes its partial counts.
 template <int D, int PATH, int W>
 __device__ __forceinline__ void sweep_block(const void *__restrict__ Zv, int64_t N, int64_t n_p,
                                             int64_t n_q, int64_t chunk_len, int64_t chunk,
                                             int64_t nchunks, int64_t group, int64_t groups,
-                                            uint2 *__restrict__ partial,
+                                            int hists, uint2 *__restrict__ partial,
                                             BlockBest *__restrict__ block_best,
                                             uint32_t *__restrict__ counts, uint32_t *smem)
 {
@@ -107,67 +113,70 @@ __device__ __forceinline__ void sweep_block(const void *__restrict__ Zv, int64_t
     const T *__restrict__ Z = static_cast<const T *>(Zv);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int H = __builtin_amdgcn_readfirstlane(hists);
 
-    for (int i = threadIdx.x; i < W * BINS * 64; i += W * 64) smem[i] = 0;
+    for (int i = threadIdx.x; i < H * BINS * 64; i += W * 64) smem[i] = 0;
 
     int64_t k = group * 64 + lane;
     Origin<PATH, D> org;
     org.load(Z, k < N ? k : N - 1);
     __syncthreads();
 
-    // This wave's share of the chunk's points.
+    // This wave's shares of the chunk's points of P and of Q.
     const int64_t c0 = chunk * chunk_len;
     const int64_t c1 = (c0 + chunk_len < N) ? c0 + chunk_len : N;
-    const int64_t per = (c1 - c0 + W - 1) / W;
-    int64_t a = c0 + (int64_t)w * per;
-    int64_t b = a + per;
-    if (a > c1) a = c1;
-    if (b > c1) b = c1;
-    a = __builtin_amdgcn_readfirstlane((int)(a - c0)) + c0;  // keep the range in SGPRs
-    b = __builtin_amdgcn_readfirstlane((int)(b - c0)) + c0;
+    const int64_t p1 = c1 < n_p ? c1 : n_p;      // P part: [c0, p1)
+    const int64_t q0 = c0 > n_p ? c0 : n_p;      // Q part: [q0, c1)
+    const int64_t np_c = p1 > c0 ? p1 - c0 : 0;
+    const int64_t nq_c = c1 > q0 ? c1 - q0 : 0;
+    const int64_t perp = (np_c + W - 1) / W, perq = (nq_c + W - 1) / W;
+    int64_t pa = (int64_t)w * perp, pb = pa + perp;
+    int64_t qa = (int64_t)w * perq, qb = qa + perq;
+    pa = pa < np_c ? pa : np_c;
+    pb = pb < np_c ? pb : np_c;
+    qa = qa < nq_c ? qa : nq_c;
+    qb = qb < nq_c ? qb : nq_c;
+    // keep the ranges in SGPRs (each share is < 2^31 points)
+    pa = __builtin_amdgcn_readfirstlane((int)pa) + c0;
+    pb = __builtin_amdgcn_readfirstlane((int)pb) + c0;
+    qa = __builtin_amdgcn_readfirstlane((int)qa) + q0;
+    qb = __builtin_amdgcn_readfirstlane((int)qb) + q0;
 
+    const int hist = w & (H - 1);
     const uint32_t base =
-        (uint32_t)(uintptr_t)(lds_u32 *)(smem + (w * BINS + Geo<D>::KOFF) * 64 + lane);
-    sweep_range<PATH, D>(Z, a, b < n_p ? b : n_p, org, base, 1u);
-    sweep_range<PATH, D>(Z, a > n_p ? a : n_p, b, org, base, 0x10000u);
+        (uint32_t)(uintptr_t)(lds_u32 *)(smem + (hist * BINS + Geo<D>::KOFF) * 64 + lane);
+    sweep_range<PATH, D>(Z, pa, pb, org, base, 1u);
+    sweep_range<PATH, D>(Z, qa, qb, org, base, 0x10000u);
     __syncthreads();
 
+    auto get = [&](int j) {
+        uint32_t cp = 0, cq = 0;
+        for (int v = 0; v < H; ++v) {
+            uint32_t h = smem[(v * BINS + j) * 64 + lane];
+            cp += h & 0xffffu;
+            cq += h >> 16;
+        }
+        return make_uint2(cp, cq);
+    };
     if (nchunks == 1) {
-        auto get = [&](int j) {
-            uint32_t cp = 0, cq = 0;
-#pragma unroll
-            for (int v = 0; v < W; ++v) {
-                uint32_t h = smem[(v * BINS + j) * 64 + lane];
-                cp += h & 0xffffu;
-                cq += h >> 16;
-            }
-            return make_uint2(cp, cq);
-        };
         finish_block<D, W>(get, group, N, n_p, n_q, block_best, counts, smem);
     } else {
-        for (int j = w; j < BINS; j += W) {
-            uint32_t cp = 0, cq = 0;
-#pragma unroll
-            for (int v = 0; v < W; ++v) {
-                uint32_t h = smem[(v * BINS + j) * 64 + lane];
-                cp += h & 0xffffu;
-                cq += h >> 16;
-            }
-            partial[((chunk * groups + group) * BINS + j) * 64 + lane] = make_uint2(cp, cq);
-        }
+        for (int j = w; j < BINS; j += W)
+            partial[((chunk * groups + group) * BINS + j) * 64 + lane] = get(j);
     }
 }
 
 template <int D, int PATH, int W>
 __global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, int64_t N,
                                                   int64_t n_p, int64_t n_q, int64_t chunk_len,
-                                                  int64_t groups, uint2 *__restrict__ partial,
+                                                  int64_t groups, int hists,
+                                                  uint2 *__restrict__ partial,
                                                   BlockBest *__restrict__ block_best,
                                                   uint32_t *__restrict__ counts)
 {
     extern __shared__ uint32_t smem[];
     sweep_block<D, PATH, W>(Zv, N, n_p, n_q, chunk_len, blockIdx.y, gridDim.y, blockIdx.x, groups,
-                            partial, block_best, counts, smem);
+                            hists, partial, block_best, counts, smem);
 }
 
 // Many tests of one dimension in one launch: block i sweeps work item
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(W * 64) void k_sweep_packed(const PackedTest *__res
     extern __shared__ uint32_t smem[];
     const int2 it = items[blockIdx.x];
     const PackedTest t = tests[it.x];
-    sweep_block<D, PATH, W>(t.Z, t.N, t.n_p, t.n_q, t.N, 0, 1, it.y, t.groups, nullptr,
+    sweep_block<D, PATH, W>(t.Z, t.N, t.n_p, t.n_q, t.N, 0, 1, it.y, t.groups, t.hists, nullptr,
                             block_best + t.bb_offset, nullptr, smem);
 }
 
@@ -315,22 +324,30 @@ int point_words(int path, int d)
     return d <= 2 ? 1 : (d <= 4 ? 2 : 4);
 }
 
+size_t hist_lds_bytes(int d, int hists) { return (size_t)hists * ((size_t)1 << d) * 64 * 4; }
+
 size_t sweep_lds_bytes(const SweepPlan &p)
 {
-    size_t hist = (size_t)p.waves * ((size_t)1 << p.d) * 64 * 4;
+    size_t hist = hist_lds_bytes(p.d, p.hists);
     size_t fin = (size_t)p.waves * 64 * 16;
     return hist > fin ? hist : fin;
 }
 
-int max_waves_for_d(int d)
+int sweep_hists(int d, int waves, int64_t chunk_len, int64_t n_p, int64_t n_q)
 {
-    // 160 KB of LDS per CU; keep at least one block of histograms per CU.
-    size_t per_wave = ((size_t)1 << d) * 64 * 4;
-    int w = (int)((160 * 1024) / per_wave);
-    if (w > 16) w = 16;
-    if (w < 1) w = 1;
-    return w;
+    // A wave sweeps at most ceil(m / waves) points of a sample with m points
+    // in the chunk, and waves / h waves share each of h histograms.
+    const int64_t mp = chunk_len < n_p ? chunk_len : n_p;
+    const int64_t mq = chunk_len < n_q ? chunk_len : n_q;
+    const int64_t perp = (mp + waves - 1) / waves, perq = (mq + waves - 1) / waves;
+    for (int h = 1; h <= waves; h *= 2) {
+        if ((int64_t)(waves / h) * perp <= 65535 && (int64_t)(waves / h) * perq <= 65535)
+            return hist_lds_bytes(d, h) <= (size_t)MAX_LDS_BYTES ? h : 0;
+    }
+    return 0;
 }
+
+int max_waves_for_d(int /*d*/) { return 16; }
 
 hipError_t launch_ingest_f32(const float *P, int64_t n_p, const float *Q, int64_t n_q, int d,
                              float *Z, uint32_t *flags, hipStream_t s)
@@ -344,6 +361,17 @@ hipError_t launch_ingest_f32(const float *P, int64_t n_p, const float *Q, int64_
     return hipGetLastError();
 }
 
+// Lets a kernel instance use more than the default 64 KB of dynamic LDS (once
+// per instance; if the runtime refuses, the launch reports the real error).
+static void allow_big_lds(const void *kernel, bool &done)
+{
+    if (done) return;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, MAX_LDS_BYTES) !=
+        hipSuccess)
+        (void)hipGetLastError();
+    done = true;
+}
+
 template <int D, int PATH, int W>
 static hipError_t launch_sweep_t(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p,
                                  int64_t n_q, uint2 *partial, BlockBest *bb, uint32_t *counts,
@@ -351,17 +379,10 @@ static hipError_t launch_sweep_t(const SweepPlan &p, const void *Z, int64_t N, i
 {
     size_t lds = sweep_lds_bytes(p);
     static bool attr_set = false;
-    if (!attr_set && lds > 64 * 1024) {
-        // Raise the dynamic-LDS cap once; if the runtime refuses, the launch
-        // below reports the real error.
-        if (hipFuncSetAttribute((const void *)k_sweep<D, PATH, W>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            (void)hipGetLastError();
-        attr_set = true;
-    }
+    if (lds > 64 * 1024) allow_big_lds((const void *)k_sweep<D, PATH, W>, attr_set);
     dim3 grid((unsigned)p.groups, (unsigned)p.chunks);
     hipLaunchKernelGGL((k_sweep<D, PATH, W>), grid, dim3(W * 64), lds, s, Z, N, n_p, n_q,
-                       p.chunk_len, p.groups, partial, bb, counts);
+                       p.chunk_len, p.groups, p.hists, partial, bb, counts);
     return hipGetLastError();
 }
 
@@ -373,16 +394,9 @@ static hipError_t launch_sweep_w(const SweepPlan &p, const void *Z, int64_t N, i
     switch (p.waves) {
     case 1: return launch_sweep_t<D, PATH, 1>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     case 2: return launch_sweep_t<D, PATH, 2>(p, Z, N, n_p, n_q, partial, bb, counts, s);
-    case 4:
-        if constexpr (D <= 7)
-            return launch_sweep_t<D, PATH, 4>(p, Z, N, n_p, n_q, partial, bb, counts, s);
-        else
-            return hipErrorInvalidValue;
-    case 8:
-        if constexpr (D <= 6)
-            return launch_sweep_t<D, PATH, 8>(p, Z, N, n_p, n_q, partial, bb, counts, s);
-        else
-            return hipErrorInvalidValue;
+    case 4: return launch_sweep_t<D, PATH, 4>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 8: return launch_sweep_t<D, PATH, 8>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 16: return launch_sweep_t<D, PATH, 16>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -408,9 +422,13 @@ static hipError_t launch_sweep_p(const SweepPlan &p, const void *Z, int64_t N, i
 hipError_t launch_sweep(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p, int64_t n_q,
                         uint2 *partial, BlockBest *bb, uint32_t *counts, hipStream_t s)
 {
-    if (p.groups < 1 || p.chunks < 1 || p.chunk_len < 1 ||
-        p.chunk_len > (int64_t)p.waves * 65535 || p.groups * 64 < N ||
+    if (p.groups < 1 || p.chunks < 1 || p.chunk_len < 1 || p.groups * 64 < N ||
         p.chunks * p.chunk_len < N || p.groups > 0x7fffffff || p.chunks > 65535)
+        return hipErrorInvalidValue;
+    // the 16-bit counters must not overflow and the histograms must fit in LDS
+    const int hmin = sweep_hists(p.d, p.waves, p.chunk_len, n_p, n_q);
+    if (hmin == 0 || p.hists < hmin || p.hists > p.waves || (p.hists & (p.hists - 1)) ||
+        sweep_lds_bytes(p) > (size_t)MAX_LDS_BYTES)
         return hipErrorInvalidValue;
     if (p.path == PATH_F32) return launch_sweep_p<PATH_F32>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     if (p.path == PATH_R16) return launch_sweep_p<PATH_R16>(p, Z, N, n_p, n_q, partial, bb, counts, s);
@@ -419,40 +437,46 @@ hipError_t launch_sweep(const SweepPlan &p, const void *Z, int64_t N, int64_t n_
 
 template <int D, int PATH, int W>
 static hipError_t launch_packed_t(const PackedTest *tests, const int2 *items, int64_t nitems,
-                                  BlockBest *bb, hipStream_t s)
+                                  int max_hists, BlockBest *bb, hipStream_t s)
 {
     SweepPlan p;
     p.d = D;
     p.waves = W;
+    p.hists = max_hists;
     const size_t lds = sweep_lds_bytes(p);
+    if (lds > (size_t)MAX_LDS_BYTES) return hipErrorInvalidValue;
     static bool attr_set = false;
-    if (!attr_set && lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void *)k_sweep_packed<D, PATH, W>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            (void)hipGetLastError();
-        attr_set = true;
-    }
+    if (lds > 64 * 1024) allow_big_lds((const void *)k_sweep_packed<D, PATH, W>, attr_set);
     hipLaunchKernelGGL((k_sweep_packed<D, PATH, W>), dim3((unsigned)nitems), dim3(W * 64), lds, s,
                        tests, items, bb);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_packed(int path, int d, const PackedTest *tests, const int2 *items,
-                               int64_t nitems, BlockBest *bb, hipStream_t s)
+                               int64_t nitems, int max_hists, BlockBest *bb, hipStream_t s)
 {
     if (nitems < 1 || nitems > 0x7fffffff) return hipErrorInvalidValue;
-    if (path != PATH_F32) return hipErrorInvalidValue;
+    if (max_hists < 1 || max_hists > PACKED_WAVES || (max_hists & (max_hists - 1)))
+        return hipErrorInvalidValue;
+    constexpr int W = PACKED_WAVES;
+#define DDKS_PACKED_CASE(DD)                                                                   \
+    case DD:                                                                                   \
+        return path == PATH_F32                                                                \
+                   ? launch_packed_t<DD, PATH_F32, W>(tests, items, nitems, max_hists, bb, s)  \
+                   : launch_packed_t<DD, PATH_R16, W>(tests, items, nitems, max_hists, bb, s);
+    if (path != PATH_F32 && path != PATH_R16) return hipErrorInvalidValue;
     switch (d) {
-    case 1: return launch_packed_t<1, PATH_F32, 4>(tests, items, nitems, bb, s);
-    case 2: return launch_packed_t<2, PATH_F32, 4>(tests, items, nitems, bb, s);
-    case 3: return launch_packed_t<3, PATH_F32, 4>(tests, items, nitems, bb, s);
-    case 4: return launch_packed_t<4, PATH_F32, 4>(tests, items, nitems, bb, s);
-    case 5: return launch_packed_t<5, PATH_F32, 4>(tests, items, nitems, bb, s);
-    case 6: return launch_packed_t<6, PATH_F32, 4>(tests, items, nitems, bb, s);
-    case 7: return launch_packed_t<7, PATH_F32, 4>(tests, items, nitems, bb, s);
-    case 8: return launch_packed_t<8, PATH_F32, 2>(tests, items, nitems, bb, s);
+        DDKS_PACKED_CASE(1)
+        DDKS_PACKED_CASE(2)
+        DDKS_PACKED_CASE(3)
+        DDKS_PACKED_CASE(4)
+        DDKS_PACKED_CASE(5)
+        DDKS_PACKED_CASE(6)
+        DDKS_PACKED_CASE(7)
+        DDKS_PACKED_CASE(8)
     default: return hipErrorInvalidValue;
     }
+#undef DDKS_PACKED_CASE
 }
 
 hipError_t launch_reduce_packed(const PackedTest *tests, int64_t ntests, const BlockBest *bb,

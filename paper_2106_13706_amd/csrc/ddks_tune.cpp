@@ -1,8 +1,9 @@
 // Launch-shape autotuner for the orthant-counting sweep.
 //
-// The sweep's speed depends on how many waves share a block's origins (LDS
-// histograms per block, hence occupancy) and on how many point chunks the
-// origin groups are split into (grid size vs. the cost of partial counts).
+// The sweep's speed depends on how many waves share a block's origins (and
+// how many LDS histograms they need, hence occupancy) and on how many point
+// chunks the origin groups are split into (grid size vs. the cost of partial
+// counts).
 // On the first sizeable call for a (path, d, log2 N) key the tuner times
 // every admissible shape on the real input with HIP events, keeps the
 // fastest, and (optionally) appends it to a text cache file of lines
@@ -76,17 +77,15 @@ int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q
     if (tuner_lookup(c->tuner, path, d, N, &probe)) return DDKS_OK;
     const int64_t groups = (N + 63) / 64;
     std::vector<SweepPlan> cand;
-    for (int w : {1, 2, 4, 8}) {
-        if (w > max_waves_for_d(d) || (d >= 7 && w > 4) || (d == 8 && w > 2)) continue;
+    for (int w : {1, 2, 4, 8, 16}) {
         for (int64_t ch : {1, 2, 3, 4, 6, 8, 12, 16}) {
             SweepPlan p;
             p.path = path;
             p.d = d;
             p.waves = w;
-            p.groups = groups;
             p.chunks = ch;
-            p.chunk_len = (N + ch - 1) / ch;
-            if (p.chunk_len > (int64_t)w * 65535 || p.chunk_len < (int64_t)w * 256) continue;
+            if (!plan_complete(p, N, n_p) || p.chunks != ch) continue;
+            if (p.chunk_len < (int64_t)w * 256) continue;
             if (groups * ch * w > 65536 * 4) continue;
             cand.push_back(p);
         }

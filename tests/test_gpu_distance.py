@@ -98,16 +98,59 @@ def test_subnormals_and_extremes(ctx, oracle_mod, path):
         check(ctx, oracle_mod, P, Q, flags=PATHS[path])
 
 
-@pytest.mark.parametrize("waves,chunks", [(1, 1), (2, 3), (4, 1), (4, 7), (8, 2), (8, 1)])
+@pytest.mark.parametrize("waves,chunks", [(1, 1), (2, 3), (4, 1), (4, 7), (8, 2), (8, 1),
+                                          (16, 1), (16, 3)])
 def test_launch_shapes(oracle_mod, waves, chunks):
     c = _ctx(DDKS_FORCE_WAVES=waves, DDKS_FORCE_CHUNKS=chunks)
     try:
         g = np.random.default_rng(waves * 10 + chunks)
-        for d in (2, 4, 6):
+        for d in (2, 4, 6, 8):
             P = np.rint(g.standard_normal((2345, d)) * 4).astype(np.float32)
             Q = np.rint(g.standard_normal((1999, d)) * 4 + 0.5).astype(np.float32)
             for flags in PATHS.values():
                 check(c, oracle_mod, P, Q, flags=flags)
+    finally:
+        c.close()
+
+
+def _check_sampled(oracle_mod, r, c, P, Q, seed):
+    """Counts at sampled origins against the oracle; at every origin the
+    counts partition both samples and the reported maximum is the maximum of
+    the returned counts."""
+    n_p, n_q = len(P), len(Q)
+    N = n_p + n_q
+    g = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([g.integers(0, N, 40), [0, n_p - 1, n_p, N - 1,
+                                                            r.argmax_origin]]))
+    np.testing.assert_array_equal(c[idx], oracle_mod.origin_counts(P, Q, idx))
+    assert (c[:, :, 0].sum(axis=1, dtype=np.int64) == n_p).all()
+    assert (c[:, :, 1].sum(axis=1, dtype=np.int64) == n_q).all()
+    s = np.abs(c[:, :, 0].astype(np.int64) * n_q - c[:, :, 1].astype(np.int64) * n_p)
+    flat = int(np.argmax(s.reshape(-1)))
+    assert int(s.reshape(-1)[flat]) == r.num
+    assert divmod(flat, s.shape[1]) == (r.argmax_origin, r.argmax_orthant)
+
+
+@pytest.mark.parametrize("waves,chunks", [(16, 1), (8, 1), (1, 1), (0, 0)])
+def test_counter_bound_shapes(oracle_mod, waves, chunks):
+    """A first sample of 70000 points in one chunk: 16 or 8 waves need two
+    LDS histograms per block so that no 16-bit counter overflows; one wave
+    per block cannot hold it in one chunk, so the planner splits the points.
+    (0, 0): the library's own choice.  Every shape must give the same exact
+    result."""
+    env = {} if waves == 0 else dict(DDKS_FORCE_WAVES=waves, DDKS_FORCE_CHUNKS=chunks)
+    c = _ctx(**env)
+    try:
+        g = np.random.default_rng(31)
+        d = 3
+        P = g.standard_normal((70000, d)).astype(np.float32)
+        Q = (g.standard_normal((3001, d)) * 1.2).astype(np.float32)
+        for flags in PATHS.values():
+            print(f"  counter-bound waves={waves} chunks={chunks} flags={flags}", flush=True)
+            r, cnt = c.distance(P, Q, counts=True, flags=flags)
+            _check_sampled(oracle_mod, r, cnt, P, Q, seed=waves + flags)
+            r2 = c.distance(Q, P, flags=flags)
+            assert r2.num == r.num
     finally:
         c.close()
 

@@ -119,6 +119,27 @@ def test_queue_full_and_errors():
         assert e.value.status == native.DDKS_E_INVALID_ARG
 
 
+def test_sample_size_bounds(oracle_mod):
+    """d = 8 with a 70000-point first sample needs two LDS histograms per
+    block of the packed sweep; it is served and matches the oracle.  Twice that
+    cannot be held by any admissible block shape and is refused with
+    DDKS_E_NOT_SUPPORTED before anything is queued."""
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(8)
+    with native.Context() as ctx:
+        P = g.standard_normal((70000, 8)).astype(np.float32)
+        Q = (g.standard_normal((100, 8)) + 0.5).astype(np.float32)
+        t = ctx.serve_submit(P, Q)
+        r = ctx.serve_poll(t, timeout_us=-1)
+        o = oracle_mod.distance(P, Q, counts=False, threads=THREADS)
+        assert _key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+        big = np.zeros((140000, 8), np.float32)
+        with pytest.raises(native.DDKSError) as e:
+            ctx.serve_submit(big, Q)
+        assert e.value.status == native.DDKS_E_NOT_SUPPORTED
+        assert ctx.serve_stats()["submitted"] == 1
+
+
 def test_poll_timeout_reports_pending():
     from paper_2106_13706_amd import native
     g = np.random.default_rng(5)
@@ -129,6 +150,7 @@ def test_poll_timeout_reports_pending():
         assert ctx.serve_poll(t, timeout_us=0) is None
         r = ctx.serve_poll(t, timeout_us=-1)
         assert r is not None and r.den == 60000 * 60000
+        assert _key(r) == _key(ctx.distance(P, Q))
 
 
 def test_destroy_with_outstanding_requests():
