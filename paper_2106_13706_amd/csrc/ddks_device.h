@@ -52,91 +52,13 @@ __host__ __device__ constexpr uint32_t dot_wts(int D, int q)
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 // ---------------------------------------------------------------------------
-// Inline-asm building blocks.  Two gfx950 pipeline hazards are invisible to
-// the compiler inside asm, so each asm block carries a whole dependent chain
-// with the spacing built in:
-//  * v_fma_mix{lo,hi}_f16 write half a VGPR; a read of that VGPR needs one
-//    intervening instruction (the compiler already pads after any asm block
-//    before its own VALU reads).
-//  * a v_dot4 result needs three intervening instructions before a VALU reads
-//    it; the dots of four points are issued back to back, then their address
-//    computations, so every read is at least three instructions later.
+// Inline-asm building blocks.  A gfx950 pipeline hazard is invisible to the
+// compiler inside asm, so each asm block carries a whole dependent chain with
+// the spacing built in: a v_dot4 result needs three intervening instructions
+// before a VALU reads it; the dots of four points are issued back to back,
+// then their address computations, so every read is at least three
+// instructions later.
 // ---------------------------------------------------------------------------
-
-#define MIXLO(d, x, o) "v_fma_mixlo_f16 " d ", " x ", 1.0, -" o " op_sel_hi:[0,0,0]\n\t"
-#define MIXHI(d, x, o) "v_fma_mixhi_f16 " d ", " x ", 1.0, -" o " op_sel_hi:[0,0,0]\n\t"
-
-// Sign registers of one fp32 point: register p holds sign(x_{2p} - o_{2p}) in
-// bit 15 and sign(x_{2p+1} - o_{2p+1}) in bit 31 (bit 31 undefined when 2p+1 = D).
-template <int D>
-__device__ __forceinline__ void signs_f32(const float *x, const float *o, uint32_t (&r)[Geo<D>::NREG]);
-
-template <>
-__device__ __forceinline__ void signs_f32<1>(const float *x, const float *o, uint32_t (&r)[1])
-{
-    asm(MIXLO("%0", "%1", "%2") : "=v"(r[0]) : "s"(x[0]), "v"(o[0]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<2>(const float *x, const float *o, uint32_t (&r)[1])
-{
-    asm(MIXLO("%0", "%1", "%2") "s_nop 0\n\t" MIXHI("%0", "%3", "%4")
-        : "=&v"(r[0]) : "s"(x[0]), "v"(o[0]), "s"(x[1]), "v"(o[1]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<3>(const float *x, const float *o, uint32_t (&r)[2])
-{
-    asm(MIXLO("%0", "%2", "%3") MIXLO("%1", "%4", "%5") MIXHI("%0", "%6", "%7")
-        : "=&v"(r[0]), "=&v"(r[1])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[1]), "v"(o[1]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<4>(const float *x, const float *o, uint32_t (&r)[2])
-{
-    asm(MIXLO("%0", "%2", "%3") MIXLO("%1", "%4", "%5") MIXHI("%0", "%6", "%7")
-            MIXHI("%1", "%8", "%9")
-        : "=&v"(r[0]), "=&v"(r[1])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[1]), "v"(o[1]), "s"(x[3]),
-          "v"(o[3]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<5>(const float *x, const float *o, uint32_t (&r)[3])
-{
-    asm(MIXLO("%0", "%3", "%4") MIXLO("%1", "%5", "%6") MIXLO("%2", "%7", "%8")
-            MIXHI("%0", "%9", "%10") MIXHI("%1", "%11", "%12")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[1]),
-          "v"(o[1]), "s"(x[3]), "v"(o[3]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<6>(const float *x, const float *o, uint32_t (&r)[3])
-{
-    asm(MIXLO("%0", "%3", "%4") MIXLO("%1", "%5", "%6") MIXLO("%2", "%7", "%8")
-            MIXHI("%0", "%9", "%10") MIXHI("%1", "%11", "%12") MIXHI("%2", "%13", "%14")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[1]),
-          "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<7>(const float *x, const float *o, uint32_t (&r)[4])
-{
-    asm(MIXLO("%0", "%4", "%5") MIXLO("%1", "%6", "%7") MIXLO("%2", "%8", "%9")
-            MIXLO("%3", "%10", "%11") MIXHI("%0", "%12", "%13") MIXHI("%1", "%14", "%15")
-                MIXHI("%2", "%16", "%17")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[6]),
-          "v"(o[6]), "s"(x[1]), "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]));
-}
-template <>
-__device__ __forceinline__ void signs_f32<8>(const float *x, const float *o, uint32_t (&r)[4])
-{
-    asm(MIXLO("%0", "%4", "%5") MIXLO("%1", "%6", "%7") MIXLO("%2", "%8", "%9")
-            MIXLO("%3", "%10", "%11") MIXHI("%0", "%12", "%13") MIXHI("%1", "%14", "%15")
-                MIXHI("%2", "%16", "%17") MIXHI("%3", "%18", "%19")
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
-        : "s"(x[0]), "v"(o[0]), "s"(x[2]), "v"(o[2]), "s"(x[4]), "v"(o[4]), "s"(x[6]),
-          "v"(o[6]), "s"(x[1]), "v"(o[1]), "s"(x[3]), "v"(o[3]), "s"(x[5]), "v"(o[5]),
-          "s"(x[7]), "v"(o[7]));
-}
 
 // sign(x - o) of two rank-encoded dimensions (int16, saturating) into bits 15 and 31.
 __device__ __forceinline__ uint32_t sgn2_r16(uint32_t x, uint32_t o)
@@ -251,13 +173,28 @@ struct Origin<PATH_R16, D> {
     }
 };
 
+// fp32 signs by subtraction: with gradual underflow x - o is zero only when
+// x == o (and then +0), so its sign bit is [x < o]; v_cvt_pkrtz_f16_f32 keeps
+// the signs of two differences (rounding toward zero never flips a sign) in
+// bits 15 and 31.
+template <int D>
+__device__ __forceinline__ void signs_sub(const float *x, const float *o, uint32_t (&r)[Geo<D>::NREG])
+{
+#pragma unroll
+    for (int p = 0; p < Geo<D>::NREG; ++p) {
+        const float a = x[2 * p] - o[2 * p];
+        const float b = (2 * p + 1 < D) ? x[2 * p + 1] - o[2 * p + 1] : 0.0f;
+        r[p] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+    }
+}
+
 // Sign registers of point x (PW words at xs) against the lane's origin.
 template <int PATH, int D>
 __device__ __forceinline__ void signs(const typename Layout<PATH, D>::T *xs,
                                       const Origin<PATH, D> &org, uint32_t (&r)[Geo<D>::NREG])
 {
     if constexpr (PATH == PATH_F32) {
-        signs_f32<D>(xs, org.o, r);
+        signs_sub<D>(xs, org.o, r);
     } else {
 #pragma unroll
         for (int p = 0; p < Geo<D>::NREG; ++p) r[p] = sgn2_r16(xs[p], org.o[p]);

@@ -13,11 +13,12 @@
 // SGPRs, so a point costs no VGPR traffic; each lane compares it with its own
 // origin:
 //
-//   fp32 path: v_fma_mix{lo,hi}_f16(x, 1.0, -o) gives sign(x - o) in bit 15 or
-//              31 of a register; x - o is exact in sign (zero only when
-//              x == o, which rounds to +0 since -0 was mapped to +0 on ingest;
-//              subnormals are kept: the kernels run with fp32/fp16 denormals
-//              preserved).
+//   fp32 path: v_sub_f32 (x - o) is exact in sign: zero only when x == o,
+//              and then +0 (-0 was mapped to +0 on ingest; subnormals are
+//              kept: the kernels run with fp32 denormals preserved);
+//              v_cvt_pkrtz_f16_f32 packs the signs of two differences into
+//              bits 15 and 31 of one register (rounding toward zero never
+//              flips a sign).
 //   rank path: coordinates replaced by per-dimension dense ranks biased to
 //              int16, two dimensions per word; v_pk_sub_i16 with saturation
 //              gives both signs in one instruction.
