@@ -6,10 +6,13 @@
 //   admit   a scheduler thread moves queued requests, oldest first, into a
 //           device arena while it has room (the arena is charged to the
 //           context's memory budget);
-//   launch  admitted tests are packed, per dimension, into one launch whose
-//           blocks are (test, origin group) work items, on one of several
-//           streams, so launches overlap on the device and requests that
-//           arrive while others run join the next launch;
+//   launch  admitted tests are packed, per dimension and compare path, into
+//           one launch whose blocks are (test, origin group) work items, on
+//           one of several streams, so launches overlap on the device and
+//           requests that arrive while others run join the next launch;
+//           mid-size tests (SERVE_R16_MIN <= N <= 65536) are first rank
+//           encoded on the device for the 16-bit compare path (at most N
+//           distinct values per dimension, so the ranks always fit);
 //   retire  finished launches (HIP events) hand their results to the
 //           tickets, free their arena space and wake pollers.
 #include <string.h>
@@ -71,13 +74,19 @@ struct Arena {
     }
 };
 
+// Smallest test swept on the rank-encoded path: below it the two encoding
+// launches cost about what the 16-bit compares save.
+static constexpr int64_t SERVE_R16_MIN = 16384;
+
 struct Req {
     uint64_t ticket = 0;
     int d = 0;
     int64_t n_p = 0, n_q = 0, N = 0;
     int hists = 1;            // LDS histograms per block of its packed sweep
+    int path = PATH_F32;      // compare path of its sweep
     std::vector<float> data;  // P then Q
-    size_t pts_bytes = 0, bytes = 0;
+    // arena layout: fp32 points | rank-encoded points (PATH_R16) | block results
+    size_t pts_bytes = 0, r16_bytes = 0, bytes = 0;
     int64_t off = -1;
     bool done = false;
     int status = DDKS_OK;
@@ -96,6 +105,9 @@ struct Slot {
     int2 *items_h = nullptr, *items_d = nullptr;
     ResultDev *res_h = nullptr, *res_d = nullptr;
     size_t cap_tests = 0, cap_items = 0;
+    // rank encoding of this slot's requests, one after another on its stream
+    void *rank_scratch = nullptr;
+    uint32_t *rank_distinct = nullptr;
 };
 
 struct Serve {
@@ -109,6 +121,8 @@ struct Serve {
     size_t held = 0;  // requests submitted and not yet collected
     Arena arena;
     void *arena_base = nullptr;
+    size_t slot_bytes = 0;  // per-slot device scratch charged to the budget
+    bool use_r16 = false;   // rank-encoded path available (set once at start)
     std::vector<Slot> slots;
     std::thread th;
     bool stop = false;
@@ -162,7 +176,9 @@ int Serve::grow_slot(Slot &s, size_t tests, size_t items)
 // dimension present, then the per-test reductions and the result copy.
 bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
 {
-    std::stable_sort(batch.begin(), batch.end(), [](const Req *a, const Req *b) { return a->d < b->d; });
+    std::stable_sort(batch.begin(), batch.end(), [](const Req *a, const Req *b) {
+        return a->d != b->d ? a->d < b->d : a->path < b->path;
+    });
     size_t nitems = 0;
     for (Req *r : batch) nitems += (size_t)((r->N + 63) / 64);
     if (grow_slot(s, batch.size(), nitems) != DDKS_OK) {
@@ -175,18 +191,25 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
     for (size_t i = 0; i < batch.size(); ++i) {
         Req *r = batch[i];
         PackedTest &t = s.tests_h[i];
-        t.Z = base + r->off;
+        char *zf = base + r->off, *zr = zf + r->pts_bytes;
+        t.Z = r->path == PATH_R16 ? (const void *)zr : (const void *)zf;
         t.N = r->N;
         t.n_p = r->n_p;
         t.n_q = r->n_q;
         t.groups = (r->N + 63) / 64;
-        t.bb_offset = (int64_t)((r->off + r->pts_bytes) / sizeof(BlockBest));
+        t.bb_offset = (int64_t)((r->off + r->pts_bytes + r->r16_bytes) / sizeof(BlockBest));
         t.hists = r->hists;
-        t.path = PATH_F32;
+        t.path = r->path;
         for (int64_t g = 0; g < t.groups; ++g) s.items_h[it++] = make_int2((int)i, (int)g);
-        if (hipMemcpyAsync(base + r->off, r->data.data(), r->data.size() * sizeof(float),
+        if (hipMemcpyAsync(zf, r->data.data(), r->data.size() * sizeof(float),
                            hipMemcpyHostToDevice, s.stream) != hipSuccess) {
             error = "H2D request copy failed";
+            return false;
+        }
+        if (r->path == PATH_R16 &&
+            launch_rank16((const float *)zf, r->N, r->d, (uint32_t *)zr, s.rank_scratch,
+                          s.rank_distinct, s.stream) != hipSuccess) {
+            error = "rank encoding launch failed";
             return false;
         }
     }
@@ -197,18 +220,18 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         error = "H2D table copy failed";
         return false;
     }
-    // one launch per run of equal dimension (the batch is sorted by d)
+    // one launch per run of equal dimension and path (the batch is sorted so)
     size_t i0 = 0, item0 = 0;
     while (i0 < batch.size()) {
         size_t i1 = i0, items = 0;
         int max_hists = 1;
-        while (i1 < batch.size() && batch[i1]->d == batch[i0]->d) {
+        while (i1 < batch.size() && batch[i1]->d == batch[i0]->d && batch[i1]->path == batch[i0]->path) {
             items += (size_t)((batch[i1]->N + 63) / 64);
             max_hists = std::max(max_hists, batch[i1]->hists);
             ++i1;
         }
-        if (launch_sweep_packed(PATH_F32, batch[i0]->d, s.tests_d, s.items_d + item0, (int64_t)items,
-                                max_hists, bb, s.stream) != hipSuccess) {
+        if (launch_sweep_packed(batch[i0]->path, batch[i0]->d, s.tests_d, s.items_d + item0,
+                                (int64_t)items, max_hists, bb, s.stream) != hipSuccess) {
             error = "packed sweep launch failed";
             return false;
         }
@@ -347,22 +370,44 @@ int serve_start(ddks_ctx *c)
     Serve *sv = new (std::nothrow) Serve();
     if (!sv) return DDKS_E_NOMEM;
     sv->c = c;
-    // the arena takes what the budget leaves, up to 8 GB
+    sv->slots.resize((size_t)std::max(1, c->serve_streams));
+    // Per-slot rank scratch (charged to the budget) when the budget also
+    // leaves a 64 MB arena; otherwise every test takes the fp32 path.  Then
+    // the arena takes what the budget leaves, up to 8 GB.
+    const size_t rank_bytes = rank16_scratch_bytes(65536, 8) + 64;
+    {
+        const uint64_t used = c->used.load();
+        const uint64_t need = (uint64_t)sv->slots.size() * rank_bytes + (64ull << 20);
+        sv->use_r16 = c->budget > used && c->budget - used >= need;
+    }
+    for (Slot &s : sv->slots) {
+        if (!sv->use_r16) break;
+        if (hipMalloc(&s.rank_scratch, rank_bytes - 64) != hipSuccess ||
+            hipMalloc((void **)&s.rank_distinct, 64) != hipSuccess) {
+            (void)hipGetLastError();
+            c->serve = sv;
+            serve_stop(c);
+            return fail(c, DDKS_E_NOMEM, "serving scratch allocation failed");
+        }
+        c->used += rank_bytes;
+        sv->slot_bytes += rank_bytes;
+    }
     uint64_t left = c->budget > c->used.load() ? c->budget - c->used.load() : 0;
     uint64_t arena = std::min<uint64_t>(left, 8ull << 30);
     arena &= ~(uint64_t)255;
     if (arena < 4096) {
-        delete sv;
+        c->serve = sv;
+        serve_stop(c);
         return fail(c, DDKS_E_NOMEM, "no device memory budget left for serving");
     }
     if (hipMalloc(&sv->arena_base, arena + 256) != hipSuccess) {  // + slack for wide scalar loads
         (void)hipGetLastError();
-        delete sv;
+        c->serve = sv;
+        serve_stop(c);
         return fail(c, DDKS_E_NOMEM, "serving arena allocation failed");
     }
     c->used += arena;
     sv->arena.init(arena);
-    sv->slots.resize((size_t)std::max(1, c->serve_streams));
     for (Slot &s : sv->slots) {
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
@@ -396,7 +441,10 @@ void serve_stop(ddks_ctx *c)
         if (s.items_d) (void)hipFree(s.items_d);
         if (s.res_h) (void)hipHostFree(s.res_h);
         if (s.res_d) (void)hipFree(s.res_d);
+        if (s.rank_scratch) (void)hipFree(s.rank_scratch);
+        if (s.rank_distinct) (void)hipFree(s.rank_distinct);
     }
+    c->used -= sv->slot_bytes;
     if (sv->arena_base) {
         (void)hipFree(sv->arena_base);
         c->used -= sv->arena.size;
@@ -465,8 +513,12 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
         delete r;
         return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
     }
+    r->path = (sv->use_r16 && N >= SERVE_R16_MIN && N <= 65536) ? PATH_R16 : PATH_F32;
     r->pts_bytes = align256((np_el + nq_el) * sizeof(float));
-    r->bytes = r->pts_bytes + align256((size_t)((N + 63) / 64) * sizeof(BlockBest));
+    r->r16_bytes = r->path == PATH_R16
+                       ? align256((size_t)N * point_words(PATH_R16, req->d) * sizeof(uint32_t))
+                       : 0;
+    r->bytes = r->pts_bytes + r->r16_bytes + align256((size_t)((N + 63) / 64) * sizeof(BlockBest));
     std::lock_guard<std::mutex> lk(sv->m);
     if (sv->failed) {
         delete r;

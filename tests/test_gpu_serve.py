@@ -119,6 +119,32 @@ def test_queue_full_and_errors():
         assert e.value.status == native.DDKS_E_INVALID_ARG
 
 
+def test_rank_encoded_requests(oracle_mod):
+    """Mid-size tests (16384 <= N <= 65536) are rank encoded on the device
+    and swept with 16-bit compares; smaller and larger ones keep fp32.  A mix
+    of both, with ties and signed zeros in some, against the oracle."""
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(21)
+    shapes = [(9000, 8000, 3), (20000, 15000, 5), (30000, 35000, 2), (12000, 5000, 8),
+              (3000, 2000, 3), (70000, 100, 4), (16384, 16384, 1), (8192, 8193, 6)]
+    reqs = []
+    for i, (n_p, n_q, d) in enumerate(shapes):
+        P = g.standard_normal((n_p, d)).astype(np.float32)
+        Q = (g.standard_normal((n_q, d)) + 0.2).astype(np.float32)
+        if i % 2:
+            P = (np.rint(P * 3) / 3).astype(np.float32)
+            Q = (np.rint(Q * 3) / 3).astype(np.float32)
+            P[P == 0] = -0.0
+        reqs.append((P, Q))
+    with native.Context() as ctx:
+        tickets = [ctx.serve_submit(P, Q) for P, Q in reqs]
+        for (P, Q), t in zip(reqs, tickets):
+            print(f"  served n_p={len(P)} n_q={len(Q)} d={P.shape[1]}", flush=True)
+            r = ctx.serve_poll(t, timeout_us=-1)
+            o = oracle_mod.distance(P, Q, counts=False, threads=THREADS)
+            assert _key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+
+
 def test_sample_size_bounds(oracle_mod):
     """d = 8 with a 70000-point first sample needs two LDS histograms per
     block of the packed sweep; it is served and matches the oracle.  Twice that
