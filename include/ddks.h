@@ -204,6 +204,7 @@ typedef struct ddks_profile {
     double batch_ms;      /* summed device time of whole permutation batches (graph launches) */
     uint64_t compares;    /* origin*point*dim compares those sweeps evaluated */
     uint64_t batches;     /* permutation batches timed */
+    uint64_t graph_calls; /* ddks_distance calls run as a replayed captured graph */
 } ddks_profile;
 
 /*

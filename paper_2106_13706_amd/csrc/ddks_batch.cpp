@@ -35,11 +35,11 @@ int enqueue_batch(ddks_ctx *c, const BatchArgs &a, hipStream_t s)
     const void *zdata = Z;
     if (a.path == PATH_R16) {
         st = hip_check(c, launch_rank16(Z, a.n, a.d, (uint32_t *)c->zr.ptr, c->rank_scratch.ptr,
-                                        c->rank_distinct_dev, s), "rank launch");
+                                        c->rank_ctl_dev, s), "rank launch");
         if (st) return st;
         zdata = c->zr.ptr;
     }
-    st = run_sweep(c, a.plan, zdata, a.n, a.n_p, a.n - a.n_p, (uint32_t *)c->obs.ptr, s);
+    st = run_sweep(c, a.plan, zdata, a.n, a.n_p, a.n - a.n_p, (uint32_t *)c->obs.ptr, c->result_dev, s);
     if (st) return st;
     if (a.B == 0) return DDKS_OK;
     st = hip_check(c, launch_perm(a.path, a.d, a.pb, zdata, a.n, a.n_p, (const uint64_t *)c->inc.ptr,
@@ -157,6 +157,7 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
     if (c->graph_pending) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->prof.batch_ms += ms;
+        else (void)hipGetLastError();
         c->prof.batches += 1;
         c->graph_pending = false;
     }

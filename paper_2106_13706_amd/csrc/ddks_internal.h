@@ -77,14 +77,17 @@ int sweep_hists(int d, int waves, int64_t chunk_len, int64_t n_p, int64_t n_q);
 hipError_t launch_ingest_f32(const float *P, int64_t n_p, const float *Q, int64_t n_q, int d,
                              float *Z, uint32_t *flags, hipStream_t s);
 
+// Words of the device control block of launch_rank16.
+constexpr int RANK_CTL_WORDS = 16;
+
 // Encodes Z (N x d fp32, -0 already mapped to +0) as per-dimension ranks
 // biased to int16, two dimensions per word, point_words(PATH_R16, d) words per
-// point, into R.  scratch: rank16_scratch_bytes(N, d) bytes.  For N <= 65536
-// the ranks always fit; for larger N, *distinct_max (device) receives the
-// largest per-dimension count of distinct values and the encoding is valid
-// only when it is <= 65536.
+// point, into R.  scratch: rank16_scratch_bytes(N, d) bytes.  ctl: a device
+// block of RANK_CTL_WORDS words.  For N <= 65536 the ranks always fit; for
+// larger N, ctl[0] receives the largest per-dimension count of distinct values
+// and the encoding is valid only when it is <= 65536.
 hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch,
-                         uint32_t *distinct_max, hipStream_t s);
+                         uint32_t *ctl, hipStream_t s);
 size_t rank16_scratch_bytes(int64_t N, int d);
 
 // The O(2^d N^2) sweep.  With plan.chunks == 1 the epilogue scores in place and

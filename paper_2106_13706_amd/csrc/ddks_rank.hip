@@ -7,17 +7,23 @@
 // the ranks fit int16 (biased by -32768) and one saturating v_pk_sub_i16
 // compares two dimensions.
 //
-// Per dimension (grid.y = dimension):
-//   1. k_rank_tiles  sorts tiles of TILE (key, index) pairs in LDS (bitonic);
-//                    key = an order-preserving uint32 image of the fp32 value.
-//   2a. N <= 65536:  k_rank_min     each value's rank = number of pooled values
-//                                   strictly below it (binary search in every
-//                                   sorted tile); fits 16 bits since N <= 65536.
-//   2b. N > 65536:   k_rank_place   places each pair at its sorted position,
-//                    k_rank_flags   counts first occurrences per segment,
-//                    k_rank_dense   dense rank = number of distinct values
-//                                   below, from the segment counts and a block
-//                                   scan; records the distinct-value count.
+// N <= 65536 (grid.y = dimension):
+//   1. k_rank_sort32  sorts each tile of TILE order keys (an order-preserving
+//                     uint32 image of the fp32 value) in registers, wave
+//                     shuffles and LDS (bitonic network).
+//   2. k_rank_count   block (t, t') stages sorted tile t' in LDS and counts,
+//                     for every point of tile t, the values of t' strictly
+//                     below its own (binary search);
+//   3. k_rank_sum     the rank of a point is the sum of its counts over all
+//                     tiles: the number of pooled values below it, which fits
+//                     16 bits since N <= 65536.
+// N > 65536:
+//   1. k_rank_tiles   sorts tiles of (key, index) pairs in LDS (bitonic);
+//   2. k_rank_place   places each pair at its sorted position,
+//      k_rank_flags   counts first occurrences per segment,
+//      k_rank_dense   dense rank = number of distinct values below, from the
+//                     segment counts and a block scan; records the
+//                     distinct-value count.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,6 +45,133 @@ __device__ __forceinline__ uint32_t order_key(float f)
     uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
+
+// ------------------------------------------------------------ N <= 65536
+
+static constexpr int S32_THREADS = 1024;  // four keys per thread
+static_assert(TILE == 4 * S32_THREADS, "k_rank_sort32 holds four keys per thread");
+
+// Sorts tile blockIdx.x of dimension blockIdx.y: K[m][t][0..TILE) = the order
+// keys of points t*TILE .. t*TILE+TILE-1, ascending (0xffffffff past N).
+// Bitonic network, fully unrolled: thread tid holds elements e = 4*tid + r;
+// partners at distance j < 4 are in the same thread, j < 256 in the same wave
+// (shuffles), j >= 256 in another wave (double-buffered LDS, one barrier per
+// stage).  For j >= 4 the direction of a thread's four compare-exchanges is
+// the same (it depends on bits of e above bit 1 only).
+__global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__restrict__ Z, int64_t N,
+                                                             int d, int64_t tiles,
+                                                             uint32_t *__restrict__ K)
+{
+    __shared__ uint4 buf[2][S32_THREADS];
+    const int m = blockIdx.y;
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int e0 = 4 * tid;
+    uint32_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = t * TILE + e0 + r;
+        v[r] = i < N ? order_key(Z[i * d + m]) : 0xffffffffu;
+    }
+    int cur = 0;
+#pragma unroll
+    for (int lk = 1; lk <= 12; ++lk) {
+        const int k = 1 << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
+            if (j >= 4) {
+                const bool keep_min = ((e0 & j) == 0) == ((e0 & k) == 0);
+                uint32_t pv[4];
+                if (j >= 256) {
+                    buf[cur][tid] = make_uint4(v[0], v[1], v[2], v[3]);
+                    __syncthreads();
+                    const uint4 p = buf[cur][tid ^ (j >> 2)];
+                    pv[0] = p.x;
+                    pv[1] = p.y;
+                    pv[2] = p.z;
+                    pv[3] = p.w;
+                    cur ^= 1;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) pv[r] = __shfl_xor(v[r], j >> 2, 64);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = keep_min ? min(v[r], pv[r]) : max(v[r], pv[r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r & j) continue;
+                    const bool up = (((e0 + r) & k) == 0);
+                    const uint32_t lo = min(v[r], v[r | j]), hi = max(v[r], v[r | j]);
+                    v[r] = up ? lo : hi;
+                    v[r | j] = up ? hi : lo;
+                }
+            }
+        }
+    }
+    uint4 *out = reinterpret_cast<uint4 *>(K + ((size_t)m * tiles + t) * TILE);
+    out[tid] = make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+// Number of entries of the sorted LDS tile below key (branchless; 0..TILE).
+__device__ __forceinline__ int count_below(const uint32_t *tile, uint32_t key)
+{
+    int p = 0;
+#pragma unroll
+    for (int step = TILE / 2; step >= 1; step >>= 1)
+        if (tile[p + step - 1] < key) p += step;
+    return p + (tile[p] < key ? 1 : 0);
+}
+
+// Writes the biased 16-bit rank of dimension m of point i.
+__device__ __forceinline__ void put_rank(uint16_t *R16, int64_t i, int pw, int m, int64_t rank)
+{
+    R16[(i * pw) * 2 + m] = (uint16_t)(uint32_t)(rank - 32768);
+}
+
+// Block (t, u, m) with u = blockIdx.z: part[u][m][i] = number of values of
+// sorted tile u below point i's value, for the points i of tile t.
+__global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restrict__ Z, int64_t N,
+                                                            int d, int64_t tiles,
+                                                            const uint32_t *__restrict__ K,
+                                                            uint16_t *__restrict__ part)
+{
+    __shared__ uint32_t tile[TILE];
+    const int m = blockIdx.y;
+    const int64_t t = blockIdx.x, u = blockIdx.z;
+    const int tid = threadIdx.x;
+    const uint4 *src = reinterpret_cast<const uint4 *>(K + ((size_t)m * tiles + u) * TILE);
+    reinterpret_cast<uint4 *>(tile)[tid] = src[tid];
+    uint32_t key[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = t * TILE + tid + r * S32_THREADS;
+        key[r] = i < N ? order_key(Z[i * d + m]) : 0u;
+    }
+    __syncthreads();
+    uint16_t *pu = part + ((size_t)u * d + m) * tiles * TILE + t * TILE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pu[tid + r * S32_THREADS] = (uint16_t)count_below(tile, key[r]);
+}
+
+// The rank of point i in dimension m (values below it over all tiles), from
+// the partial counts; also zeroes the padding dimensions of each point.
+__global__ void k_rank_sum(const uint16_t *__restrict__ part, int64_t N, int d, int pw,
+                           int64_t tiles, uint16_t *__restrict__ R16)
+{
+    const int m = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t rank = 0;
+        for (int64_t u = 0; u < tiles; ++u) rank += part[((size_t)u * d + m) * tiles * TILE + i];
+        put_rank(R16, i, pw, m, rank);
+        if (m == 0)
+            for (int mm = d; mm < 2 * pw; ++mm) R16[(i * pw) * 2 + mm] = 0;
+    }
+}
+
+// ------------------------------------------------------------ N > 65536
 
 __global__ __launch_bounds__(TILE_THREADS) void k_rank_tiles(const float *__restrict__ Z, int64_t N,
                                                              int d, int64_t tiles,
@@ -87,30 +220,6 @@ __device__ __forceinline__ int lower_bound_tile(const uint64_t *__restrict__ til
     return lo;
 }
 
-// Writes the biased 16-bit rank of dimension m of point i.
-__device__ __forceinline__ void put_rank(uint16_t *R16, int64_t i, int pw, int m, int64_t rank)
-{
-    R16[(i * pw) * 2 + m] = (uint16_t)(uint32_t)(rank - 32768);
-}
-
-__global__ void k_rank_min(const uint64_t *__restrict__ A, int64_t N, int d, int pw, int64_t tiles,
-                           uint16_t *__restrict__ R16)
-{
-    const int m = blockIdx.y;
-    const uint64_t *Am = A + (size_t)m * tiles * TILE;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tiles * TILE;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t item = Am[q];
-        if (item == ~0ull) continue;
-        const int64_t i = (int64_t)(uint32_t)item;
-        const uint64_t probe = item & 0xffffffff00000000ull;  // (key, index 0)
-        int64_t rank = 0;
-        for (int64_t t = 0; t < tiles; ++t) rank += lower_bound_tile(Am + t * TILE, probe);
-        put_rank(R16, i, pw, m, rank);
-        if (m == 0)
-            for (int mm = d; mm < 2 * pw; ++mm) R16[(i * pw) * 2 + mm] = 0;
-    }
-}
 
 __global__ void k_rank_place(const uint64_t *__restrict__ A, int64_t N, int64_t tiles,
                              uint64_t *__restrict__ S)
@@ -208,39 +317,53 @@ static int64_t tiles_of(int64_t N) { return (N + TILE - 1) / TILE; }
 size_t rank16_scratch_bytes(int64_t N, int d)
 {
     const int64_t tiles = tiles_of(N);
+    if (N <= 65536) {
+        size_t k = (size_t)d * tiles * TILE * sizeof(uint32_t);
+        size_t part = (size_t)tiles * d * tiles * TILE * sizeof(uint16_t);
+        return k + part + 256;
+    }
     size_t a = (size_t)d * tiles * TILE * sizeof(uint64_t);
-    size_t s = N > 65536 ? (size_t)d * N * sizeof(uint64_t) : 0;
-    size_t c = N > 65536 ? (size_t)d * ((N + SEG - 1) / SEG) * sizeof(uint32_t) : 0;
+    size_t s = (size_t)d * N * sizeof(uint64_t);
+    size_t c = (size_t)d * ((N + SEG - 1) / SEG) * sizeof(uint32_t);
     return a + s + c + 256;
 }
 
-hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch,
-                         uint32_t *distinct_max, hipStream_t st)
+hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch, uint32_t *ctl,
+                         hipStream_t st)
 {
     const int pw = point_words(PATH_R16, d);
     const int64_t tiles = tiles_of(N);
-    uint64_t *A = (uint64_t *)scratch;
     uint16_t *R16 = (uint16_t *)R;
-    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)tiles, d), dim3(TILE_THREADS), 0, st, Z, N, d,
-                       tiles, A);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t items = tiles * TILE;
-    unsigned blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 4096);
+    hipError_t e;
     if (N <= 65536) {
-        hipLaunchKernelGGL(k_rank_min, dim3(blocks, d), dim3(256), 0, st, A, N, d, pw, tiles, R16);
+        uint32_t *Kt = (uint32_t *)scratch;
+        uint16_t *part = (uint16_t *)(Kt + (size_t)d * tiles * TILE);
+        hipLaunchKernelGGL(k_rank_sort32, dim3((unsigned)tiles, d), dim3(S32_THREADS), 0, st, Z, N, d,
+                           tiles, Kt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rank_count, dim3((unsigned)tiles, d, (unsigned)tiles), dim3(S32_THREADS),
+                           0, st, Z, N, d, tiles, Kt, part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const unsigned sblocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_rank_sum, dim3(sblocks, d), dim3(256), 0, st, part, N, d, pw, tiles, R16);
         return hipGetLastError();
     }
+    uint64_t *A = (uint64_t *)scratch;
+    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)tiles, d), dim3(TILE_THREADS), 0, st, Z, N, d,
+                       tiles, A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t items = tiles * TILE;
+    unsigned blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 4096);
     uint64_t *S = A + (size_t)d * tiles * TILE;
     uint32_t *C = (uint32_t *)(S + (size_t)d * N);
     const int64_t segs = (N + SEG - 1) / SEG;
     hipLaunchKernelGGL(k_rank_place, dim3(blocks, d), dim3(256), 0, st, A, N, tiles, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_flags, dim3((unsigned)segs, d), dim3(SEG_THREADS), 0, st, S, N, segs, C,
-                       distinct_max);
+                       ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_dense, dim3((unsigned)segs, d), dim3(SEG_THREADS), 0, st, S, N, d, pw,
-                       segs, C, R16, distinct_max);
+                       segs, C, R16, ctl);
     return hipGetLastError();
 }
 

@@ -135,14 +135,14 @@ int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok)
     st = ensure(c, c->rank_scratch, rank16_scratch_bytes(N, d), "rank scratch");
     if (st) return st;
     st = hip_check(c, launch_rank16((const float *)c->z.ptr, N, d, (uint32_t *)c->zr.ptr,
-                                    c->rank_scratch.ptr, c->rank_distinct_dev, c->stream),
+                                    c->rank_scratch.ptr, c->rank_ctl_dev, c->stream),
                    "rank launch");
     if (st) return st;
     if (N <= 65536) {
         *ok = true;  // at most N distinct values per dimension
         return DDKS_OK;
     }
-    st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, c->rank_distinct_dev, sizeof(uint32_t),
+    st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, c->rank_ctl_dev, sizeof(uint32_t),
                                      hipMemcpyDeviceToHost, c->stream), "D2H distinct count");
     if (!st) st = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     if (st) return st;
@@ -151,7 +151,7 @@ int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok)
 }
 
 int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
-              int64_t n_q, uint32_t *counts_dev, hipStream_t s)
+              int64_t n_q, uint32_t *counts_dev, ResultDev *res, hipStream_t s)
 {
     int st = ensure(c, c->block_best, (size_t)plan.groups * sizeof(BlockBest), "block results");
     if (st) return st;
@@ -178,16 +178,20 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
         c->ev_score = plan.chunks > 1;
         c->ev_compares = N * N * plan.d;
     }
-    return hip_check(c, launch_reduce(bb, plan.groups, c->flags_dev, c->result_dev, s), "reduce launch");
+    return hip_check(c, launch_reduce(bb, plan.groups, c->flags_dev, res, s), "reduce launch");
 }
 
 void profile_collect(ddks_ctx *c)
 {
     if (!c->ev_pending) return;
     float ms = 0.f;
+    // a failed query must not leave its error for the next launch check
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->prof.sweep_ms += ms;
-    if (c->ev_score && hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess)
-        c->prof.score_ms += ms;
+    else (void)hipGetLastError();
+    if (c->ev_score) {
+        if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess) c->prof.score_ms += ms;
+        else (void)hipGetLastError();
+    }
     c->prof.sweeps += 1;
     c->prof.compares += (uint64_t)c->ev_compares;
     c->ev_pending = false;
@@ -196,6 +200,78 @@ void profile_collect(ddks_ctx *c)
 }  // namespace ddks
 
 // ==================================================================== C ABI
+
+// Everything one single-test call enqueues after its buffers exist.
+struct DistArgs {
+    const float *P, *Q;
+    int64_t n_p, n_q;
+    int d, path;
+    uint32_t *counts;
+    SweepPlan plan;
+};
+
+// Allocates (outside any capture) every buffer enqueue_distance uses.
+static int prepare_distance(ddks_ctx *c, const DistArgs &a)
+{
+    const int64_t N = a.n_p + a.n_q;
+    int st = DDKS_OK;
+    if (a.path == PATH_R16) {
+        st = ensure(c, c->zr, (size_t)N * point_words(PATH_R16, a.d) * sizeof(uint32_t), "rank encoding");
+        if (!st) st = ensure(c, c->rank_scratch, rank16_scratch_bytes(N, a.d), "rank scratch");
+    }
+    if (!st) st = ensure(c, c->block_best, (size_t)a.plan.groups * sizeof(BlockBest), "block results");
+    if (!st && a.plan.chunks > 1)
+        st = ensure(c, c->partial,
+                    (size_t)a.plan.chunks * a.plan.groups * ((size_t)1 << a.d) * 64 * sizeof(uint2),
+                    "partial counts");
+    return st;
+}
+
+// Ingest, rank encoding (N <= 65536 only: no host decision) and, if
+// with_sweep, the sweep of device-resident P and Q; the result lands in the
+// pinned c->result_host.
+static int enqueue_distance(ddks_ctx *c, const DistArgs &a, hipStream_t s, bool with_sweep)
+{
+    const int64_t N = a.n_p + a.n_q;
+    float *Z = (float *)c->z.ptr;
+    int st = hip_check(c, launch_ingest_f32(a.P, a.n_p, a.Q, a.n_q, a.d, Z, c->flags_dev, s),
+                       "ingest launch");
+    if (st) return st;
+    const void *zdata = Z;
+    if (a.path == PATH_R16) {
+        st = hip_check(c, launch_rank16(Z, N, a.d, (uint32_t *)c->zr.ptr, c->rank_scratch.ptr,
+                                        c->rank_ctl_dev, s), "rank launch");
+        if (st) return st;
+        zdata = c->zr.ptr;
+    }
+    if (!with_sweep) return DDKS_OK;
+    return run_sweep(c, a.plan, zdata, N, a.n_p, a.n_q, a.counts, c->result_host, s);
+}
+
+// Waits for the call's work, copies host counts if asked, fills *out.
+static int finish_distance(ddks_ctx *c, int64_t n_p, int64_t n_q, int d, ddks_result *out,
+                           uint32_t *counts_host, const uint32_t *counts_dev, size_t counts_bytes)
+{
+    hipStream_t s = c->stream;
+    int st = DDKS_OK;
+    if (counts_host)
+        st = hip_check(c, hipMemcpyAsync(counts_host, counts_dev, counts_bytes, hipMemcpyDeviceToHost, s),
+                       "D2H counts");
+    if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (st) return st;
+    profile_collect(c);
+    const ResultDev r = *c->result_host;
+    if (r.flags & 1u) return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
+    out->num = r.num;
+    out->den = (uint64_t)n_p * (uint64_t)n_q;
+    out->D = (double)r.num / (double)out->den;
+    out->argmax_origin = r.origin;
+    out->argmax_orthant = r.code;
+    out->d = d;
+    out->n_p = n_p;
+    out->n_q = n_q;
+    return DDKS_OK;
+}
 
 extern "C" {
 
@@ -269,7 +345,8 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     if (!st) st = hip_check(c, hipMalloc((void **)&c->result_dev, sizeof(ResultDev)), "hipMalloc");
     if (!st) st = hip_check(c, hipMalloc((void **)&c->flags_dev, 2 * sizeof(uint32_t)), "hipMalloc");
     if (!st) st = hip_check(c, hipMemset(c->flags_dev, 0, 2 * sizeof(uint32_t)), "hipMemset");
-    if (!st) st = hip_check(c, hipMalloc((void **)&c->rank_distinct_dev, 16 * sizeof(uint32_t)), "hipMalloc");
+    if (!st) st = hip_check(c, hipMalloc((void **)&c->rank_ctl_dev, RANK_CTL_WORDS * sizeof(uint32_t)), "hipMalloc");
+    if (!st) st = hip_check(c, hipMemset(c->rank_ctl_dev, 0, RANK_CTL_WORDS * sizeof(uint32_t)), "hipMemset");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->result_host, sizeof(ResultDev), 0), "hipHostMalloc");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->rank_distinct_host, 16 * sizeof(uint32_t), 0), "hipHostMalloc");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->sig_host, 2 * sizeof(double), 0), "hipHostMalloc");
@@ -298,12 +375,13 @@ int ddks_destroy(ddks_ctx *c)
     for (DevBuf *b : bufs) release(c, *b);
     if (c->result_dev) (void)hipFree(c->result_dev);
     if (c->flags_dev) (void)hipFree(c->flags_dev);
-    if (c->rank_distinct_dev) (void)hipFree(c->rank_distinct_dev);
+    if (c->rank_ctl_dev) (void)hipFree(c->rank_ctl_dev);
     if (c->result_host) (void)hipHostFree(c->result_host);
     if (c->rank_distinct_host) (void)hipHostFree(c->rank_distinct_host);
     if (c->sig_host) (void)hipHostFree(c->sig_host);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->dist_exec) (void)hipGraphExecDestroy(c->dist_exec);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     tuner_destroy(c->tuner);
     delete c;
@@ -329,17 +407,6 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     int st = ensure(c, c->z, (size_t)N * d * sizeof(float), "points");
     if (st) return st;
     float *Z = (float *)c->z.ptr;
-    const float *srcP = P, *srcQ = Q;
-    if (!dev) {
-        st = hip_check(c, hipMemcpyAsync(Z, P, (size_t)n_p * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D P");
-        if (!st) st = hip_check(c, hipMemcpyAsync(Z + n_p * d, Q, (size_t)n_q * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D Q");
-        if (st) return st;
-        srcP = Z;
-        srcQ = Z + n_p * d;
-    }
-    st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
-    if (st) return st;
-
     uint32_t *counts_dev = nullptr;
     if (counts) {
         if (dev) {
@@ -350,8 +417,86 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
             counts_dev = (uint32_t *)c->counts.ptr;
         }
     }
-
     int path = choose_path(c, d, N, flags);
+
+    // Device-resident inputs and outputs, a launch shape already known and no
+    // decision on the host halfway (the rank encoding of more than 65536
+    // points checks its distinct counts on the host): the whole call is one
+    // captured graph, replayed while its key matches.  With kernel profiling
+    // the graph stops before the sweep, which is launched between timing
+    // events (events recorded inside a graph cannot be timed).
+    const bool graphable = c->dist_graphs && dev && (path == PATH_F32 || N <= 65536) &&
+                           !tune_pending(c, path, d, N);
+    if (graphable) {
+        DistArgs a;
+        a.P = P;
+        a.Q = Q;
+        a.n_p = n_p;
+        a.n_q = n_q;
+        a.d = d;
+        a.path = path;
+        a.counts = counts_dev;
+        a.plan = plan_for(c, path, d, N, n_p);
+        st = prepare_distance(c, a);
+        if (st) return st;
+        const std::vector<uint64_t> key = {
+            (uint64_t)(uintptr_t)P, (uint64_t)(uintptr_t)Q, (uint64_t)n_p, (uint64_t)n_q,
+            (uint64_t)d, (uint64_t)path, (uint64_t)(uintptr_t)counts_dev, (uint64_t)a.plan.waves,
+            (uint64_t)a.plan.chunks, (uint64_t)a.plan.hists, c->buf_gen, (uint64_t)(uintptr_t)s,
+            (uint64_t)c->profile};
+        if (c->dist_exec && c->dist_key != key) {
+            (void)hipGraphExecDestroy(c->dist_exec);
+            c->dist_exec = nullptr;
+        }
+        if (!c->dist_exec) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ex = nullptr;
+            bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            int st2 = DDKS_OK;
+            if (ok) {
+                st2 = enqueue_distance(c, a, s, !c->profile);
+                ok = hipStreamEndCapture(s, &g) == hipSuccess && st2 == DDKS_OK;
+            }
+            ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (!ok) {
+                // Capture is an optimisation: fall back to eager launches for
+                // good.  Launches refused inside a failed capture are not
+                // device errors, so they do not poison the context; a real
+                // fault shows again on the eager path.
+                (void)hipGetLastError();
+                if (ex) (void)hipGraphExecDestroy(ex);
+                c->dist_graphs = false;
+                c->ev_pending = false;
+                c->poisoned = false;
+            } else {
+                c->dist_exec = ex;
+                c->dist_key = key;
+            }
+        }
+        if (c->dist_exec) {
+            st = hip_check(c, hipGraphLaunch(c->dist_exec, s), "graph launch");
+            if (st) return st;
+            if (c->profile) {
+                c->prof.graph_calls += 1;
+                const void *zdata = path == PATH_R16 ? c->zr.ptr : c->z.ptr;
+                st = run_sweep(c, a.plan, zdata, N, n_p, n_q, counts_dev, c->result_host, s);
+                if (st) return st;
+            }
+            return finish_distance(c, n_p, n_q, d, out, nullptr, nullptr, 0);
+        }
+    }
+
+    const float *srcP = P, *srcQ = Q;
+    if (!dev) {
+        st = hip_check(c, hipMemcpyAsync(Z, P, (size_t)n_p * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D P");
+        if (!st) st = hip_check(c, hipMemcpyAsync(Z + n_p * d, Q, (size_t)n_q * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D Q");
+        if (st) return st;
+        srcP = Z;
+        srcQ = Z + n_p * d;
+    }
+    st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
+    if (st) return st;
     const void *zdata = Z;
     if (path == PATH_R16) {
         bool ok = false;
@@ -363,28 +508,10 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     st = tune_sweep(c, path, d, N, n_p, n_q, zdata);
     if (st) return st;
     SweepPlan plan = plan_for(c, path, d, N, n_p);
-    st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, s);
+    st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, c->result_host, s);
     if (st) return st;
-    st = hip_check(c, hipMemcpyAsync(c->result_host, c->result_dev, sizeof(ResultDev), hipMemcpyDeviceToHost, s), "D2H result");
-    if (st) return st;
-    if (counts && !dev) {
-        st = hip_check(c, hipMemcpyAsync(counts, counts_dev, (size_t)N * bins * 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "D2H counts");
-        if (st) return st;
-    }
-    st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
-    if (st) return st;
-    profile_collect(c);
-    const ResultDev r = *c->result_host;
-    if (r.flags & 1u) return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
-    out->num = r.num;
-    out->den = (uint64_t)n_p * (uint64_t)n_q;
-    out->D = (double)r.num / (double)out->den;
-    out->argmax_origin = r.origin;
-    out->argmax_orthant = r.code;
-    out->d = d;
-    out->n_p = n_p;
-    out->n_q = n_q;
-    return DDKS_OK;
+    return finish_distance(c, n_p, n_q, d, out, counts && !dev ? counts : nullptr, counts_dev,
+                           (size_t)N * bins * 2 * sizeof(uint32_t));
 }
 
 int ddks_profile_get(ddks_ctx *c, ddks_profile *out, int32_t reset)

@@ -51,12 +51,16 @@ struct ddks_ctx {
     // captured permutation-batch graph, replayed while its key matches
     hipGraphExec_t batch_exec = nullptr;
     std::vector<uint64_t> batch_key;
+    // captured single-test graph (device-resident inputs), same scheme
+    hipGraphExec_t dist_exec = nullptr;
+    std::vector<uint64_t> dist_key;
+    bool dist_graphs = true;  // cleared for good if a capture ever fails
     ddks::ResultDev *result_dev = nullptr;  // device
     ddks::ResultDev *result_host = nullptr; // pinned
     uint32_t *flags_dev = nullptr;          // device, cleared by the reduction
     uint32_t *rank_distinct_host = nullptr; // pinned
     double *sig_host = nullptr;             // pinned, 2 doubles
-    uint32_t *rank_distinct_dev = nullptr;
+    uint32_t *rank_ctl_dev = nullptr;
 
     // kernel timing (DDKS_PROFILE_KERNELS)
     bool profile = false;
@@ -96,7 +100,7 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p);
 // device buffer (fp32 N x d at zf, and when path == PATH_R16 the rank
 // encoding at zr).  Leaves the result in c->result_dev; does not synchronise.
 int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
-              int64_t n_q, uint32_t *counts_dev, hipStream_t s);
+              int64_t n_q, uint32_t *counts_dev, ddks::ResultDev *res, hipStream_t s);
 
 // Folds the events recorded by the last run_sweep into c->prof (after the
 // stream has been synchronised).
@@ -122,5 +126,7 @@ bool tuner_lookup(Tuner *t, int path, int d, int64_t N, SweepPlan *plan);
 // Times the admissible launch shapes of a sweep on the given (already
 // ingested) input once per (path, d, N bucket) and records the fastest.
 int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q, const void *zdata);
+// True if tune_sweep would time candidate shapes for this key.
+bool tune_pending(ddks_ctx *c, int path, int d, int64_t N);
 
 }  // namespace ddks

@@ -107,7 +107,7 @@ struct Slot {
     size_t cap_tests = 0, cap_items = 0;
     // rank encoding of this slot's requests, one after another on its stream
     void *rank_scratch = nullptr;
-    uint32_t *rank_distinct = nullptr;
+    uint32_t *rank_ctl = nullptr;  // launch_rank16 control block
 };
 
 struct Serve {
@@ -208,7 +208,7 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         }
         if (r->path == PATH_R16 &&
             launch_rank16((const float *)zf, r->N, r->d, (uint32_t *)zr, s.rank_scratch,
-                          s.rank_distinct, s.stream) != hipSuccess) {
+                          s.rank_ctl, s.stream) != hipSuccess) {
             error = "rank encoding launch failed";
             return false;
         }
@@ -374,7 +374,8 @@ int serve_start(ddks_ctx *c)
     // Per-slot rank scratch (charged to the budget) when the budget also
     // leaves a 64 MB arena; otherwise every test takes the fp32 path.  Then
     // the arena takes what the budget leaves, up to 8 GB.
-    const size_t rank_bytes = rank16_scratch_bytes(65536, 8) + 64;
+    const size_t ctl_bytes = RANK_CTL_WORDS * sizeof(uint32_t);
+    const size_t rank_bytes = rank16_scratch_bytes(65536, 8) + ctl_bytes;
     {
         const uint64_t used = c->used.load();
         const uint64_t need = (uint64_t)sv->slots.size() * rank_bytes + (64ull << 20);
@@ -382,8 +383,9 @@ int serve_start(ddks_ctx *c)
     }
     for (Slot &s : sv->slots) {
         if (!sv->use_r16) break;
-        if (hipMalloc(&s.rank_scratch, rank_bytes - 64) != hipSuccess ||
-            hipMalloc((void **)&s.rank_distinct, 64) != hipSuccess) {
+        if (hipMalloc(&s.rank_scratch, rank_bytes - ctl_bytes) != hipSuccess ||
+            hipMalloc((void **)&s.rank_ctl, ctl_bytes) != hipSuccess ||
+            hipMemset(s.rank_ctl, 0, ctl_bytes) != hipSuccess) {
             (void)hipGetLastError();
             c->serve = sv;
             serve_stop(c);
@@ -442,7 +444,7 @@ void serve_stop(ddks_ctx *c)
         if (s.res_h) (void)hipHostFree(s.res_h);
         if (s.res_d) (void)hipFree(s.res_d);
         if (s.rank_scratch) (void)hipFree(s.rank_scratch);
-        if (s.rank_distinct) (void)hipFree(s.rank_distinct);
+        if (s.rank_ctl) (void)hipFree(s.rank_ctl);
     }
     c->used -= sv->slot_bytes;
     if (sv->arena_base) {

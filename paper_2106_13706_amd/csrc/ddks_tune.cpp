@@ -68,13 +68,18 @@ static void tuner_store(Tuner *t, int path, int d, int64_t N, int waves, int64_t
         }
 }
 
-int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q, const void *zdata)
+bool tune_pending(ddks_ctx *c, int path, int d, int64_t N)
 {
     if (!c->tuner || (c->opt_flags & DDKS_NO_AUTOTUNE) || c->force_waves || c->force_chunks)
-        return DDKS_OK;
-    if (N < 16384) return DDKS_OK;  // launch-bound sizes: the heuristic is as good
+        return false;
+    if (N < 16384) return false;  // launch-bound sizes: the heuristic is as good
     SweepPlan probe;
-    if (tuner_lookup(c->tuner, path, d, N, &probe)) return DDKS_OK;
+    return !tuner_lookup(c->tuner, path, d, N, &probe);
+}
+
+int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q, const void *zdata)
+{
+    if (!tune_pending(c, path, d, N)) return DDKS_OK;
     const int64_t groups = (N + 63) / 64;
     std::vector<SweepPlan> cand;
     for (int w : {1, 2, 4, 8, 16}) {
@@ -103,11 +108,14 @@ int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q
         float ms_min = 1e30f;
         for (int rep = 0; rep < 2 && !st; ++rep) {
             st = hip_check(c, hipEventRecord(e0, c->stream), "hipEventRecord");
-            if (!st) st = run_sweep(c, p, zdata, N, n_p, n_q, nullptr, c->stream);
+            if (!st) st = run_sweep(c, p, zdata, N, n_p, n_q, nullptr, c->result_dev, c->stream);
             if (!st) st = hip_check(c, hipEventRecord(e1, c->stream), "hipEventRecord");
             if (!st) st = hip_check(c, hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.f;
-            if (!st && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+            if (!st) {
+                if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+                else (void)hipGetLastError();
+            }
         }
         if (ms_min < best_ms) {
             best_ms = ms_min;

@@ -199,6 +199,42 @@ def test_device_pointers(oracle_mod):
         c.close()
 
 
+@pytest.mark.parametrize("flags", [0x0, 0x2, 0x10])
+def test_graph_replays(oracle_mod, flags):
+    """Device-resident inputs: the call is captured once and then replayed.
+    Replays see data rewritten in place, eager calls in between do not
+    disturb them, and a new size is captured again; every result against the
+    oracle."""
+    import torch
+    from paper_2106_13706_amd import native
+    c = native.Context(stream=torch.cuda.current_stream(), flags=native.DDKS_PROFILE_KERNELS)
+    try:
+        g = np.random.default_rng(40 + flags)
+        d = 3
+        Pt = torch.empty((3000, d), dtype=torch.float32, device="cuda")
+        Qt = torch.empty((2500, d), dtype=torch.float32, device="cuda")
+        key = lambda r: (r.num, r.den, r.argmax_origin, r.argmax_orthant)
+        for rep in range(4):
+            P = (np.rint(g.standard_normal((3000, d)) * 4) / 4).astype(np.float32)
+            Q = (np.rint(g.standard_normal((2500, d)) * 4 + 1) / 4).astype(np.float32)
+            Pt.copy_(torch.from_numpy(P))
+            Qt.copy_(torch.from_numpy(Q))
+            print(f"  replay {rep} flags={flags}", flush=True)
+            r = c.distance(Pt, Qt, flags=flags)
+            assert key(r) == key(oracle_mod.distance(P, Q, counts=False, threads=THREADS))
+            if rep == 1:
+                r2 = c.distance(P[:100], Q[:50], flags=flags)  # eager: host inputs
+                assert key(r2) == key(oracle_mod.distance(P[:100], Q[:50], counts=False))
+        r = c.distance(Pt[:2000], Qt[:1000], flags=flags)  # new key: captured again
+        assert key(r) == key(oracle_mod.distance(P[:2000], Q[:1000], counts=False,
+                                                 threads=THREADS))
+        prof = c.profile()
+        assert prof["sweeps"] == 6
+        assert prof["graph_calls"] == 5
+    finally:
+        c.close()
+
+
 # ------------------------------------------------------------- the workloads
 
 def test_workload_gaussian_shift_d3_500(ctx, oracle_mod):
@@ -227,6 +263,20 @@ def test_workload_mixture_grid_d6_scaled(ctx, oracle_mod):
     assert np.signbit(P).any()
     check(ctx, oracle_mod, P, Q)
     check(ctx, oracle_mod, P, Q, counts=False, flags=PATHS["f32"])
+
+
+@pytest.mark.parametrize("n_p,n_q,d", [(4095, 0, 2), (2048, 2048, 3), (4000, 97, 2),
+                                       (4097, 4096, 1), (32768, 32768, 2)])
+def test_rank16_tile_edges(ctx, oracle_mod, n_p, n_q, d):
+    """Rank encoding at tile boundaries (4096 keys per sorted tile) up to the
+    largest size whose ranks always fit 16 bits (65536 points); ties and
+    signed zeros so that equal values span tiles."""
+    g = np.random.default_rng(n_p + n_q)
+    n_q = max(n_q, 1)
+    P = (np.rint(g.standard_normal((n_p, d)) * 40) / 8).astype(np.float32)
+    Q = (np.rint(g.standard_normal((n_q, d)) * 40 + 3) / 8).astype(np.float32)
+    P[P == 0] = -0.0
+    check(ctx, oracle_mod, P, Q, counts=n_p + n_q < 20000, flags=PATHS["rank16"])
 
 
 def test_rank16_dense_path_and_fallback(ctx, oracle_mod):
