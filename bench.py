@@ -201,11 +201,14 @@ def bench_serving(ctx_factory, n_requests, seed_rate=None):
                     "p50_latency_ms": st["p50_latency_us"] / 1e3,
                     "p99_latency_ms": st["p99_latency_us"] / 1e3,
                     "launches": st["launches"], "mean_tests_per_launch": st["mean_batch"],
-                    "compares_per_s": total_compares / wall}
+                    "compares_per_s": total_compares / wall,
+                    "gpu_busy_fraction": st["busy_us"] / 1e6 / wall}
 
     out["saturation"] = run(None)
     out["open_loop_at_mu_seq"] = run(mu_seq)
     out["open_loop_at_mu_seq"]["arrival_rate_per_s"] = mu_seq
+    out["open_loop_at_2mu_seq"] = run(2 * mu_seq)
+    out["open_loop_at_2mu_seq"]["arrival_rate_per_s"] = 2 * mu_seq
     return out
 
 

@@ -165,6 +165,8 @@ typedef struct ddks_serve_stats {
     double p99_latency_us;
     double mean_batch;         /* tests per packed launch */
     uint64_t resident_bytes;   /* device bytes currently held by admitted requests */
+    double busy_us;            /* device time covered by at least one retired launch
+                                  (copies, encodings, sweeps, reductions) */
 } ddks_serve_stats;
 
 /*

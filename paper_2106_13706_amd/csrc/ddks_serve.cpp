@@ -98,6 +98,7 @@ struct Req {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;  // timing events around the launch in flight
     bool busy = false;
     std::vector<Req *> reqs;
     // pinned staging and device copies of the launch's tables and results
@@ -132,6 +133,9 @@ struct Serve {
     uint64_t submitted = 0, completed = 0, rej_again = 0, rej_nomem = 0, launches = 0,
              launched_tests = 0;
     std::vector<double> lat_us;
+    // device time: [start, end) of every retired launch in ms after `ref`
+    hipEvent_t ref = nullptr;
+    std::vector<std::pair<float, float>> spans;
 
     int grow_slot(Slot &s, size_t tests, size_t items);
     bool launch_batch(Slot &s, std::vector<Req *> &batch);
@@ -188,6 +192,10 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
     char *base = (char *)arena_base;
     BlockBest *bb = (BlockBest *)arena_base;
     size_t it = 0;
+    if (hipEventRecord(s.t0, s.stream) != hipSuccess) {
+        error = "event record failed";
+        return false;
+    }
     for (size_t i = 0; i < batch.size(); ++i) {
         Req *r = batch[i];
         PackedTest &t = s.tests_h[i];
@@ -241,6 +249,7 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
     if (launch_reduce_packed(s.tests_d, (int64_t)batch.size(), bb, s.res_d, s.stream) != hipSuccess ||
         hipMemcpyAsync(s.res_h, s.res_d, batch.size() * sizeof(ResultDev), hipMemcpyDeviceToHost,
                        s.stream) != hipSuccess ||
+        hipEventRecord(s.t1, s.stream) != hipSuccess ||
         hipEventRecord(s.done, s.stream) != hipSuccess) {
         error = "packed reduction launch failed";
         return false;
@@ -256,6 +265,11 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
 void Serve::retire(Slot &s)
 {
     const auto now = Clock::now();
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, ref, s.t0) == hipSuccess && hipEventElapsedTime(&b, ref, s.t1) == hipSuccess)
+        spans.emplace_back(a, b);
+    else
+        (void)hipGetLastError();
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         Req *r = s.reqs[i];
         const ResultDev &x = s.res_h[i];
@@ -412,11 +426,18 @@ int serve_start(ddks_ctx *c)
     sv->arena.init(arena);
     for (Slot &s : sv->slots) {
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreate(&s.t0) != hipSuccess || hipEventCreate(&s.t1) != hipSuccess) {
             c->serve = sv;
             serve_stop(c);
             return hip_check(c, hipErrorOutOfMemory, "serving stream creation");
         }
+    }
+    if (hipEventCreate(&sv->ref) != hipSuccess || hipEventRecord(sv->ref, sv->slots[0].stream) != hipSuccess ||
+        hipEventSynchronize(sv->ref) != hipSuccess) {
+        c->serve = sv;
+        serve_stop(c);
+        return hip_check(c, hipErrorOutOfMemory, "serving event creation");
     }
     c->serve = sv;
     sv->th = std::thread([sv] { sv->loop(); });
@@ -436,6 +457,8 @@ void serve_stop(ddks_ctx *c)
     for (Slot &s : sv->slots) {
         if (s.stream) (void)hipStreamSynchronize(s.stream);
         if (s.done) (void)hipEventDestroy(s.done);
+        if (s.t0) (void)hipEventDestroy(s.t0);
+        if (s.t1) (void)hipEventDestroy(s.t1);
         if (s.stream) (void)hipStreamDestroy(s.stream);
         if (s.tests_h) (void)hipHostFree(s.tests_h);
         if (s.tests_d) (void)hipFree(s.tests_d);
@@ -451,6 +474,7 @@ void serve_stop(ddks_ctx *c)
         (void)hipFree(sv->arena_base);
         c->used -= sv->arena.size;
     }
+    if (sv->ref) (void)hipEventDestroy(sv->ref);
     for (auto &kv : sv->table) delete kv.second;
     delete sv;
     c->serve = nullptr;
@@ -596,10 +620,26 @@ int ddks_serve_stats_get(ddks_ctx *c, ddks_serve_stats *out, int32_t reset)
         out->p50_latency_us = pct(0.50);
         out->p99_latency_us = pct(0.99);
     }
+    // union of the launches' device intervals (launches on several streams overlap)
+    std::vector<std::pair<float, float>> sp = sv->spans;
+    std::sort(sp.begin(), sp.end());
+    double busy = 0.0, cur_a = 0.0, cur_b = -1.0;
+    for (const auto &x : sp) {
+        if (x.first > cur_b) {
+            if (cur_b > cur_a) busy += cur_b - cur_a;
+            cur_a = x.first;
+            cur_b = x.second;
+        } else if (x.second > cur_b) {
+            cur_b = x.second;
+        }
+    }
+    if (cur_b > cur_a) busy += cur_b - cur_a;
+    out->busy_us = busy * 1e3;
     if (reset) {
         sv->submitted = sv->completed = sv->rej_again = sv->rej_nomem = 0;
         sv->launches = sv->launched_tests = 0;
         sv->lat_us.clear();
+        sv->spans.clear();
     }
     return DDKS_OK;
 }

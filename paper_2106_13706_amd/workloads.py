@@ -111,6 +111,7 @@ class Request:
     Q: np.ndarray
     d: int
     delta: float
+    seed: int = 0  # generator seed of P and Q (see materialize)
 
 
 @dataclass
@@ -143,8 +144,17 @@ def serving_stream(n_requests: int = 10000, rate: float = 1000.0, d_range=(2, 8)
         else:
             P = np.empty((n_p, d), np.float32)
             Q = np.empty((n_q, d), np.float32)
-        reqs.append(Request(t, P, Q, d, delta))
+        reqs.append(Request(t, P, Q, d, delta, sub))
     return Stream(reqs)
+
+
+def materialize(r: Request):
+    """(P, Q) of a request from serving_stream(materialize=False): the same
+    arrays the materialized stream holds."""
+    h = _rng(r.seed)
+    P = h.standard_normal((r.P.shape[0], r.d)).astype(np.float32)
+    Q = (h.standard_normal((r.Q.shape[0], r.d)) + r.delta).astype(np.float32)
+    return P, Q
 
 
 # The five workloads by name, as (callable, description).

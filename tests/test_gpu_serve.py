@@ -53,6 +53,7 @@ def test_mix_matches_oracle_and_single_path(oracle_mod):
         assert a.D == o.D
     assert st["completed"] == 240 and st["submitted"] == 240
     assert st["launches"] >= 2 and st["p99_latency_us"] >= st["p50_latency_us"] > 0
+    assert 0 < st["busy_us"] <= st["p99_latency_us"] * st["launches"]
 
 
 def test_concurrent_submitters(oracle_mod):
@@ -93,6 +94,28 @@ def test_memory_budget_admission(oracle_mod):
             ctx.serve_submit(big[:65000], big[65000:])
         assert e.value.status == native.DDKS_E_NOMEM
         assert ctx.serve_stats()["rejected_nomem"] == 1
+
+
+def test_workload_serving_stratified(oracle_mod):
+    """The 10^4-test serving stream: a seeded stratified subset served
+    together and checked against the oracle -- every test with N <= 8192 among
+    the first 1200 of the stream, plus for each d the first four tests with
+    8192 < N <= 32768 (these take the rank-encoded path from N = 16384)."""
+    from paper_2106_13706_amd import native, workloads
+    stream = workloads.serving_stream(materialize=False)
+    reqs = stream.requests
+    N = [r.P.shape[0] + r.Q.shape[0] for r in reqs]
+    pick = [i for i in range(1200) if N[i] <= 8192]
+    for d in range(2, 9):
+        pick += [i for i in range(len(reqs)) if reqs[i].d == d and 8192 < N[i] <= 32768][:4]
+    assert len(pick) >= 400
+    data = [workloads.materialize(reqs[i]) for i in pick]
+    with native.Context() as ctx:
+        tickets = [ctx.serve_submit(P, Q) for P, Q in data]
+        got = [ctx.serve_poll(t) for t in tickets]
+    for i, (P, Q), r in zip(pick, data, got):
+        o = oracle_mod.distance(P, Q, counts=False, threads=THREADS)
+        assert _key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant), (i, P.shape, Q.shape)
 
 
 def test_queue_full_and_errors():
