@@ -29,6 +29,10 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+
+# rate models of the analytic significance (Sec. 3)
+_MODELS = {"binomial": 0, "poisson": 1}
+
 def _load():
     global _lib
     if _lib is not None:
@@ -47,6 +51,11 @@ def _load():
     lib.ddks_oracle_permutation.restype = ctypes.c_int
     lib.ddks_oracle_tail.argtypes = [i64, i64, ctypes.c_double, ctypes.c_uint64]
     lib.ddks_oracle_tail.restype = ctypes.c_double
+    lib.ddks_oracle_tail_model.argtypes = [i64, i64, ctypes.c_double, ctypes.c_uint64, ctypes.c_int]
+    lib.ddks_oracle_tail_model.restype = ctypes.c_double
+    lib.ddks_oracle_significance_model.argtypes = [vp, i64, i64, i32, ctypes.c_uint64, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_double)]
+    lib.ddks_oracle_significance_model.restype = ctypes.c_int
     lib.ddks_oracle_significance.argtypes = [vp, i64, i64, i32, ctypes.c_uint64,
                                              ctypes.POINTER(ctypes.c_double)]
     lib.ddks_oracle_significance.restype = ctypes.c_int
@@ -156,19 +165,21 @@ def pvalue(nums, num_obs: int) -> tuple[float, float]:
     return (1 + hits) / (1 + B), (hits / B if B else float("nan"))
 
 
-def tail(n_p: int, n_q: int, lam: float, num: int) -> float:
-    """1 - P(|a/n_p - b/n_q| <= num/(n_p n_q)), a~Bi(n_p,lam), b~Bi(n_q,lam)."""
-    return float(_load().ddks_oracle_tail(n_p, n_q, lam, num))
+def tail(n_p: int, n_q: int, lam: float, num: int, model: str = "binomial") -> float:
+    """1 - P(|a/n_p - b/n_q| <= num/(n_p n_q)), a~Bi(n_p,lam), b~Bi(n_q,lam); with
+    model="poisson" the pmfs are Poisson of the same means on the same supports."""
+    return float(_load().ddks_oracle_tail_model(n_p, n_q, lam, num, _MODELS[model]))
 
 
-def significance(counts, n_p: int, n_q: int, d: int, num: int) -> float:
+def significance(counts, n_p: int, n_q: int, d: int, num: int, model: str = "binomial") -> float:
     """Analytic significance S of num/(n_p n_q) from the [N, 2^d, 2] counts."""
     lib = _load()
     c = np.ascontiguousarray(counts, dtype=np.uint32)
     if c.shape != (n_p + n_q, 1 << d, 2):
         raise ValueError("counts must be [n_p+n_q, 2^d, 2]")
     S = ctypes.c_double()
-    st = lib.ddks_oracle_significance(c.ctypes.data, n_p, n_q, d, num, ctypes.byref(S))
+    st = lib.ddks_oracle_significance_model(c.ctypes.data, n_p, n_q, d, num, _MODELS[model],
+                                            ctypes.byref(S))
     if st != 0:
         raise ValueError(f"oracle significance failed with status {st}")
     return S.value

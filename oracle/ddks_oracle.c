@@ -36,7 +36,11 @@
  *   P(delta <= D | n_P, n_T, lambda), lambda = (M_T + 1)/(N_T + 2) (Bayes
  *   estimator with a uniform prior), delta the absolute difference of two
  *   binomial proportions (Eq. abs_difference, Eq. binomial_probability,
- *   Eq. ddks_significance).
+ *   Eq. ddks_significance).  Sec. 3 also proposes, for large samples and
+ *   small rates, replacing each binomial pmf by the Poisson pmf of the same
+ *   mean and carrying the derivation through; reading: the sums keep their
+ *   support 0..m (the set Delta), so P(delta <= D) is the windowed sum of
+ *   products of Poisson pmfs over that support.
  *
  *   Sec. 3 / Sec. 4.2: permutation test -- the statistic recomputed for
  *   relabelled pooled samples; here each relabelling is rebuilt as two
@@ -55,6 +59,10 @@
 #define ORACLE_OK 0
 #define ORACLE_EINVAL -1
 #define ORACLE_ENOMEM -4
+
+/* Rate models of the significance (Sec. 3). */
+#define DDKS_ORACLE_BINOMIAL 0
+#define DDKS_ORACLE_POISSON 1
 
 /* ------------------------------------------------------------------------- */
 /* Exact statistic by the definition                                         */
@@ -285,6 +293,34 @@ static double binom_pmf(int64_t k, int64_t m, double lam)
     return exp(lc + (double)k * log(lam) + (double)(m - k) * log1p(-lam));
 }
 
+/* Poisson pmf e^-mu mu^k / k!, the replacement of Eq. binomial_probability
+   that Sec. 3 proposes for large samples and small rates (mu = m * lambda). */
+static double pois_pmf(int64_t k, double mu)
+{
+    if (k < 0) return 0.0;
+    if (mu <= 0.0) return k == 0 ? 1.0 : 0.0;
+    return exp((double)k * log(mu) - mu - lgamma((double)k + 1.0));
+}
+
+/* P(X > m) for X ~ Poisson(mu): the terms k > m summed directly (no
+   difference of probabilities), until they stop mattering. */
+static double pois_upper(int64_t m, double mu)
+{
+    double sum = 0.0;
+    for (int64_t k = m + 1;; ++k) {
+        double t = pois_pmf(k, mu);
+        sum += t;
+        if ((double)k > mu && (t == 0.0 || t < sum * 1e-18)) break;
+    }
+    return sum;
+}
+
+static double model_pmf(int64_t k, int64_t m, double lam, int model)
+{
+    if (model == DDKS_ORACLE_POISSON) return k > m ? 0.0 : pois_pmf(k, (double)m * lam);
+    return binom_pmf(k, m, lam);
+}
+
 static int64_t floor_div(int64_t a, int64_t b) /* b > 0 */
 {
     int64_t q = a / b;
@@ -303,8 +339,15 @@ static int64_t ceil_div(int64_t a, int64_t b) /* b > 0 */
  * the complement of Sec. 3's p(d <= delta), summed directly over the
  * excluded (a, b) so that no cancellation occurs.
  * |a/n_p - b/n_q| <= num/(n_p n_q)  <=>  |a*n_q - b*n_p| <= num.
+ *
+ * model DDKS_ORACLE_POISSON: each binomial pmf replaced by the Poisson pmf of
+ * mean m*lambda over the same support 0..m (Sec. 3's large-sample
+ * approximation, carried through the same sums).  Then
+ * p(d <= delta) = Z_a Z_b - excluded with Z the pmf mass on the support, and
+ * its complement is (1 - Z_a Z_b) + excluded, where
+ * 1 - Z_a Z_b = U_a + U_b - U_a U_b and U = P(Poisson > m) is summed directly.
  */
-double ddks_oracle_tail(int64_t n_p, int64_t n_q, double lam, uint64_t num)
+double ddks_oracle_tail_model(int64_t n_p, int64_t n_q, double lam, uint64_t num, int model)
 {
     double *pb = (double *)malloc((size_t)(n_q + 1) * sizeof(double));
     double *below = (double *)malloc((size_t)(n_q + 2) * sizeof(double)); /* below[t] = sum_{b<t} */
@@ -315,7 +358,7 @@ double ddks_oracle_tail(int64_t n_p, int64_t n_q, double lam, uint64_t num)
         free(above);
         return NAN;
     }
-    for (int64_t b = 0; b <= n_q; ++b) pb[b] = binom_pmf(b, n_q, lam);
+    for (int64_t b = 0; b <= n_q; ++b) pb[b] = model_pmf(b, n_q, lam, model);
     below[0] = 0.0;
     for (int64_t t = 1; t <= n_q + 1; ++t) below[t] = below[t - 1] + pb[t - 1];
     above[n_q + 1] = 0.0;
@@ -329,11 +372,17 @@ double ddks_oracle_tail(int64_t n_p, int64_t n_q, double lam, uint64_t num)
         if (hi > n_q) hi = n_q;
         double excluded;
         if (lo > hi) {
-            excluded = 1.0; /* no b is close enough */
+            /* no b is close enough: all of b's mass (1 for the binomial) */
+            excluded = model == DDKS_ORACLE_POISSON ? below[n_q + 1] : 1.0;
         } else {
             excluded = below[lo] + above[hi + 1];
         }
-        tail += binom_pmf(a, n_p, lam) * excluded;
+        tail += model_pmf(a, n_p, lam, model) * excluded;
+    }
+    if (model == DDKS_ORACLE_POISSON) {
+        const double ua = pois_upper(n_p, (double)n_p * lam);
+        const double ub = pois_upper(n_q, (double)n_q * lam);
+        tail += ua + ub - ua * ub;
     }
     free(pb);
     free(below);
@@ -341,6 +390,11 @@ double ddks_oracle_tail(int64_t n_p, int64_t n_q, double lam, uint64_t num)
     if (tail < 0.0) tail = 0.0;
     if (tail > 1.0) tail = 1.0;
     return tail;
+}
+
+double ddks_oracle_tail(int64_t n_p, int64_t n_q, double lam, uint64_t num)
+{
+    return ddks_oracle_tail_model(n_p, n_q, lam, num, DDKS_ORACLE_BINOMIAL);
 }
 
 /*
@@ -352,9 +406,10 @@ double ddks_oracle_tail(int64_t n_p, int64_t n_q, double lam, uint64_t num)
  * Computed as S = -expm1(sum log1p(-tail_jk)); tails are cached by the
  * value of c_Q (the only thing lambda depends on).
  */
-int ddks_oracle_significance(const uint32_t *counts, int64_t n_p, int64_t n_q, int32_t d,
-                             uint64_t num, double *S_out)
+int ddks_oracle_significance_model(const uint32_t *counts, int64_t n_p, int64_t n_q, int32_t d,
+                                   uint64_t num, int model, double *S_out)
 {
+    if (model != DDKS_ORACLE_BINOMIAL && model != DDKS_ORACLE_POISSON) return ORACLE_EINVAL;
     if (!counts || !S_out || n_p < 1 || n_q < 1 || d < 1 || d > 16) return ORACLE_EINVAL;
     const int64_t N = n_p + n_q;
     const uint32_t bins = (uint32_t)1 << d;
@@ -373,7 +428,7 @@ int ddks_oracle_significance(const uint32_t *counts, int64_t n_p, int64_t n_q, i
             if ((int64_t)t > n_q) { status = ORACLE_EINVAL; break; }
             if (!have[t]) {
                 double lam = ((double)t + 1.0) / ((double)n_q + 2.0);
-                cache[t] = ddks_oracle_tail(n_p, n_q, lam, num);
+                cache[t] = ddks_oracle_tail_model(n_p, n_q, lam, num, model);
                 have[t] = 1;
             }
             log_keep += log1p(-cache[t]);
@@ -384,6 +439,12 @@ int ddks_oracle_significance(const uint32_t *counts, int64_t n_p, int64_t n_q, i
     if (status != ORACLE_OK) return status;
     *S_out = -expm1(log_keep);
     return ORACLE_OK;
+}
+
+int ddks_oracle_significance(const uint32_t *counts, int64_t n_p, int64_t n_q, int32_t d,
+                             uint64_t num, double *S_out)
+{
+    return ddks_oracle_significance_model(counts, n_p, n_q, d, num, DDKS_ORACLE_BINOMIAL, S_out);
 }
 
 /* ------------------------------------------------------------------------- */
