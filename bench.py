@@ -86,6 +86,23 @@ def cpu_baseline(P, Q, compares):
                          f"{len(times)} run(s), {med:.2f} s each"}
 
 
+def bench_significance(ctx, native, torch, Pt, Qt, workload, reps=5):
+    """ddks_distance with the analytic significance of Sec. 3 computed on the
+    device in the same call (binomial and Poisson models), against the plain
+    call on the same device-resident inputs."""
+    out = {"workload": workload}
+    for name, fl in (("plain", 0), ("binomial", native.DDKS_WITH_SIGNIFICANCE),
+                     ("poisson", native.DDKS_WITH_SIGNIFICANCE | native.DDKS_SIG_POISSON)):
+        r = ctx.distance(Pt, Qt, flags=fl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ctx.distance(Pt, Qt, flags=fl)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_call": (time.perf_counter() - t0) / reps * 1e3, "S": r.S}
+    return out
+
+
 def bench_batch(ctx, torch, dev, reps=5):
     """Permutation batch (d=5, pooled 2x4096, 1024 relabellings): one call =
     observed split + all relabellings, replayed from a captured graph; against
@@ -298,6 +315,8 @@ def main():
             "kernel_avg_ms": k3 * 1e3, "frac": (c3 / k3) / VALU_COMPARE_PEAK,
             "num": r3.num, "den": r3.den}
         del P3t, Q3t
+        _log("[bench] extra: analytic significance")
+        extras["significance"] = bench_significance(ctx, native, torch, Pt, Qt, workload)
         _log("[bench] extra: permutation batch")
         extras["permutation_batch"] = bench_batch(ctx, torch, dev)
         _log(f"[bench] extra: serving ({args.serve_requests} requests)")

@@ -59,6 +59,8 @@ typedef enum ddks_status {
 #define DDKS_FORCE_RANK16 0x10u /* per call: use the rank encoding even for small inputs */
 #define DDKS_NO_AUTOTUNE 0x4u   /* ctx option: use the built-in launch heuristics only */
 #define DDKS_PROFILE_KERNELS 0x8u /* ctx option: time the sweep kernels with HIP events */
+#define DDKS_WITH_SIGNIFICANCE 0x20u /* ddks_distance: also compute the analytic significance S */
+#define DDKS_SIG_POISSON 0x40u    /* significance: Poisson instead of binomial counts (Sec. 3) */
 
 typedef struct ddks_ctx ddks_ctx;
 
@@ -80,6 +82,7 @@ typedef struct ddks_result {
     int32_t argmax_orthant;   /* its lowest maximising orthant code */
     int32_t d;
     int64_t n_p, n_q;
+    double S;                 /* analytic significance (DDKS_WITH_SIGNIFICANCE), else -1 */
 } ddks_result;
 
 /* Fills *opt with defaults (device 0, library stream, budget 0, no flags). */
@@ -99,6 +102,10 @@ int ddks_destroy(ddks_ctx *ctx);
  * in P-then-Q order, sample 0 = P -- the membership matrices M of
  * Eq. membership for both origin sets.  Host memory unless DDKS_DEVICE_PTRS.
  * Synchronous: returns after the result (and counts) are available.
+ * flags DDKS_WITH_SIGNIFICANCE: out->S also receives the analytic
+ * significance of the result (as ddks_significance, DDKS_SIG_POISSON for the
+ * Poisson model), computed on the device from counts that stay there;
+ * otherwise out->S = -1.
  * Limits: 1 <= n_p, n_q; n_p + n_q <= 2^31 - 1; 1 <= d <= 8.
  * Errors: DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOMEM, DDKS_E_DEVICE.
  */
@@ -139,9 +146,11 @@ int ddks_permutation_batch(ddks_ctx *ctx, const float *Z, int64_t n, int32_t d, 
  *   S = 1 - prod over origins k and orthants j of P(delta <= D | lambda_kj),
  *   lambda_kj = (c_Q[k][j] + 1) / (n_q + 2)   (Bayes estimator, uniform prior),
  * delta = |a/n_p - b/n_q| with a ~ Bi(n_p, lambda), b ~ Bi(n_q, lambda)
- * (Eq. abs_difference, Eq. binomial_probability).  Computed on the device
- * in fp64.  counts: [n_p+n_q][2^d][2] as written by ddks_distance (host
- * memory unless DDKS_DEVICE_PTRS).
+ * (Eq. abs_difference, Eq. binomial_probability).  flags DDKS_SIG_POISSON:
+ * the large-sample approximation of Sec. 3, each binomial pmf replaced by the
+ * Poisson pmf of the same mean over the same supports 0..n.  Computed on the
+ * device in fp64.  counts: [n_p+n_q][2^d][2] as written by ddks_distance
+ * (host memory unless DDKS_DEVICE_PTRS).
  * Errors: DDKS_E_INVALID_ARG, DDKS_E_NOMEM, DDKS_E_DEVICE.
  */
 int ddks_significance(ddks_ctx *ctx, const uint32_t *counts, int64_t n_p, int64_t n_q, int32_t d,

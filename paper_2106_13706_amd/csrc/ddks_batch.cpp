@@ -180,6 +180,7 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
         observed->d = d;
         observed->n_p = n_p;
         observed->n_q = n - n_p;
+        observed->S = -1.0;
     }
     return DDKS_OK;
 }

@@ -144,14 +144,21 @@ hipError_t launch_perm(int path, int d, int pb, const void *Z, int64_t N, int64_
 
 // ---------------------------------------------------------------- significance
 
-// Scratch bytes for launch_significance with `rows` concurrent tail rows.
-size_t significance_scratch_bytes(int64_t n_p, int64_t n_q, int rows);
+// Rate models of the analytic significance (Sec. 3).
+enum : int { SIG_MODEL_BINOMIAL = 0, SIG_MODEL_POISSON = 1 };
 
-// *S = analytic significance of num/(n_p n_q) from counts [N][2^d][2] (fp64).
-// Sets bit 2 of *flags if a second-sample count exceeds n_q.
+// Waves of the significance tail kernel in flight for n_q (a multiple of 4).
+int significance_rows(int64_t n_q, int model);
+// Scratch bytes for launch_significance with `rows` waves in flight.
+size_t significance_scratch_bytes(int64_t n_p, int64_t n_q, int rows, int model);
+
+// *S = analytic significance of num/(n_p n_q) from counts [N][2^d][2] (fp64),
+// with num read from *num_dev when num_dev is not null (a device word written
+// earlier on the same stream).  model: SIG_MODEL_*.  Sets bit 2 of *flags if
+// a second-sample count exceeds n_q.
 hipError_t launch_significance(const uint32_t *counts, int64_t N, int d, int64_t n_p, int64_t n_q,
-                               uint64_t num, void *scratch, int rows, uint32_t *flags, double *S,
-                               hipStream_t s);
+                               uint64_t num, const uint64_t *num_dev, int model, void *scratch,
+                               int rows, uint32_t *flags, double *S, hipStream_t s);
 
 // res->ge = #{b : nums[b] >= res->num}.
 hipError_t launch_count_ge(const unsigned long long *nums, int B, ResultDev *res, hipStream_t s);

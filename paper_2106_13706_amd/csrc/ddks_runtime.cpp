@@ -250,7 +250,8 @@ static int enqueue_distance(ddks_ctx *c, const DistArgs &a, hipStream_t s, bool 
 
 // Waits for the call's work, copies host counts if asked, fills *out.
 static int finish_distance(ddks_ctx *c, int64_t n_p, int64_t n_q, int d, ddks_result *out,
-                           uint32_t *counts_host, const uint32_t *counts_dev, size_t counts_bytes)
+                           uint32_t *counts_host, const uint32_t *counts_dev, size_t counts_bytes,
+                           bool with_S)
 {
     hipStream_t s = c->stream;
     int st = DDKS_OK;
@@ -270,6 +271,7 @@ static int finish_distance(ddks_ctx *c, int64_t n_p, int64_t n_q, int d, ddks_re
     out->d = d;
     out->n_p = n_p;
     out->n_q = n_q;
+    out->S = with_S ? c->sig_host[0] : -1.0;
     return DDKS_OK;
 }
 
@@ -418,6 +420,7 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
         }
     }
     int path = choose_path(c, d, N, flags);
+    const bool with_S = (flags & DDKS_WITH_SIGNIFICANCE) != 0;
 
     // Device-resident inputs and outputs, a launch shape already known and no
     // decision on the host halfway (the rank encoding of more than 65536
@@ -425,7 +428,7 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     // captured graph, replayed while its key matches.  With kernel profiling
     // the graph stops before the sweep, which is launched between timing
     // events (events recorded inside a graph cannot be timed).
-    const bool graphable = c->dist_graphs && dev && (path == PATH_F32 || N <= 65536) &&
+    const bool graphable = c->dist_graphs && dev && !with_S && (path == PATH_F32 || N <= 65536) &&
                            !tune_pending(c, path, d, N);
     if (graphable) {
         DistArgs a;
@@ -483,10 +486,24 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
                 st = run_sweep(c, a.plan, zdata, N, n_p, n_q, counts_dev, c->result_host, s);
                 if (st) return st;
             }
-            return finish_distance(c, n_p, n_q, d, out, nullptr, nullptr, 0);
+            return finish_distance(c, n_p, n_q, d, out, nullptr, nullptr, 0, false);
         }
     }
 
+    // The significance reads the counts on the device; they stay there unless
+    // the caller asked for them.
+    const int sig_model = (flags & DDKS_SIG_POISSON) ? SIG_MODEL_POISSON : SIG_MODEL_BINOMIAL;
+    const int sig_rows = with_S ? significance_rows(n_q, sig_model) : 0;
+    if (with_S) {
+        if (!counts_dev) {
+            st = ensure(c, c->counts, (size_t)N * bins * 2 * sizeof(uint32_t), "counts");
+            if (st) return st;
+            counts_dev = (uint32_t *)c->counts.ptr;
+        }
+        st = ensure(c, c->sig, significance_scratch_bytes(n_p, n_q, sig_rows, sig_model) + 64,
+                    "significance scratch");
+        if (st) return st;
+    }
     const float *srcP = P, *srcQ = Q;
     if (!dev) {
         st = hip_check(c, hipMemcpyAsync(Z, P, (size_t)n_p * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D P");
@@ -508,10 +525,22 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     st = tune_sweep(c, path, d, N, n_p, n_q, zdata);
     if (st) return st;
     SweepPlan plan = plan_for(c, path, d, N, n_p);
-    st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, c->result_host, s);
+    st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, with_S ? c->result_dev : c->result_host, s);
     if (st) return st;
+    if (with_S) {
+        // S of the statistic just found: num is read on the device
+        double *Sdev = (double *)((char *)c->sig.ptr + significance_scratch_bytes(n_p, n_q, sig_rows, sig_model));
+        st = hip_check(c, launch_significance(counts_dev, N, d, n_p, n_q, 0, &c->result_dev->num, sig_model,
+                                              c->sig.ptr, sig_rows, c->flags_dev, Sdev, s),
+                       "significance launch");
+        if (!st) st = hip_check(c, hipMemcpyAsync(c->result_host, c->result_dev, sizeof(ResultDev),
+                                                  hipMemcpyDeviceToHost, s), "D2H result");
+        if (!st) st = hip_check(c, hipMemcpyAsync(c->sig_host, Sdev, sizeof(double), hipMemcpyDeviceToHost, s),
+                                "D2H S");
+        if (st) return st;
+    }
     return finish_distance(c, n_p, n_q, d, out, counts && !dev ? counts : nullptr, counts_dev,
-                           (size_t)N * bins * 2 * sizeof(uint32_t));
+                           (size_t)N * bins * 2 * sizeof(uint32_t), with_S);
 }
 
 int ddks_profile_get(ddks_ctx *c, ddks_profile *out, int32_t reset)

@@ -281,6 +281,7 @@ void Serve::retire(Slot &s)
         r->result.d = r->d;
         r->result.n_p = r->n_p;
         r->result.n_q = r->n_q;
+        r->result.S = -1.0;
         r->status = DDKS_OK;
         r->done = true;
         r->t_done = now;

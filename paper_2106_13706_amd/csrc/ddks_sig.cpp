@@ -23,10 +23,9 @@ extern "C" int ddks_significance(ddks_ctx *c, const uint32_t *counts, int64_t n_
     hipStream_t s = c->stream;
     const int64_t N = n_p + n_q;
     const size_t cbytes = (size_t)N * ((size_t)1 << d) * 2 * sizeof(uint32_t);
-    // one tail row (2 x (n_q + 2) doubles) per block in flight, at most 64 MB of rows
-    int64_t rows = (int64_t)(64ull << 20) / (16 * (n_q + 2));
-    rows = std::max<int64_t>(1, std::min<int64_t>({rows, n_q + 1, 1024}));
-    int st = ensure(c, c->sig, significance_scratch_bytes(n_p, n_q, (int)rows) + 64, "significance scratch");
+    const int model = (flags & DDKS_SIG_POISSON) ? SIG_MODEL_POISSON : SIG_MODEL_BINOMIAL;
+    const int rows = significance_rows(n_q, model);
+    int st = ensure(c, c->sig, significance_scratch_bytes(n_p, n_q, rows, model) + 64, "significance scratch");
     if (st) return st;
     const uint32_t *cd = counts;
     if (!dev) {
@@ -36,9 +35,9 @@ extern "C" int ddks_significance(ddks_ctx *c, const uint32_t *counts, int64_t n_
         if (st) return st;
         cd = (const uint32_t *)c->counts.ptr;
     }
-    double *Sdev = (double *)((char *)c->sig.ptr + significance_scratch_bytes(n_p, n_q, (int)rows));
-    st = hip_check(c, launch_significance(cd, N, d, n_p, n_q, num, c->sig.ptr, (int)rows, c->flags_dev,
-                                          Sdev, s), "significance launch");
+    double *Sdev = (double *)((char *)c->sig.ptr + significance_scratch_bytes(n_p, n_q, rows, model));
+    st = hip_check(c, launch_significance(cd, N, d, n_p, n_q, num, nullptr, model, c->sig.ptr, rows,
+                                          c->flags_dev, Sdev, s), "significance launch");
     if (st) return st;
     double S = 0.0;
     uint32_t fl = 0;

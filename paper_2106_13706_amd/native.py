@@ -32,6 +32,8 @@ DDKS_FORCE_F32 = 0x2
 DDKS_NO_AUTOTUNE = 0x4
 DDKS_PROFILE_KERNELS = 0x8
 DDKS_FORCE_RANK16 = 0x10
+DDKS_WITH_SIGNIFICANCE = 0x20
+DDKS_SIG_POISSON = 0x40
 
 # Every symbol include/ddks.h declares.
 EXPORTS = (
@@ -58,7 +60,8 @@ class _Options(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("num", ctypes.c_uint64), ("den", ctypes.c_uint64), ("D", ctypes.c_double),
                 ("argmax_origin", ctypes.c_int64), ("argmax_orthant", ctypes.c_int32),
-                ("d", ctypes.c_int32), ("n_p", ctypes.c_int64), ("n_q", ctypes.c_int64)]
+                ("d", ctypes.c_int32), ("n_p", ctypes.c_int64), ("n_q", ctypes.c_int64),
+                ("S", ctypes.c_double)]
 
 
 class _Request(ctypes.Structure):
@@ -96,10 +99,11 @@ class Result:
     d: int
     n_p: int
     n_q: int
+    S: float = -1.0  # analytic significance when asked for (DDKS_WITH_SIGNIFICANCE)
 
     @classmethod
     def _from(cls, r: _Result) -> "Result":
-        return cls(r.num, r.den, r.D, r.argmax_origin, r.argmax_orthant, r.d, r.n_p, r.n_q)
+        return cls(r.num, r.den, r.D, r.argmax_origin, r.argmax_orthant, r.d, r.n_p, r.n_q, r.S)
 
 
 _lib = None

@@ -68,3 +68,19 @@ def test_create_without_device(lib):
     assert lib.ddks_create(None, ctypes.byref(h)) == native.DDKS_E_NO_DEVICE
     with pytest.raises(native.DDKSError):
         native.Context()
+
+
+def test_constants_match_header():
+    """Every DDKS_ flag and status the binding defines has the header's value."""
+    from paper_2106_13706_amd import native
+    src = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2), 0)
+            for m in re.finditer(r"#define (DDKS_[A-Z0-9_]+) (0x[0-9a-fA-F]+|-?[0-9]+)u?", src)}
+    enum = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"\b(DDKS_E_[A-Z_]+|DDKS_OK)\s*=\s*(-?[0-9]+)", src)}
+    defs.update(enum)
+    names = [n for n in dir(native) if n.startswith("DDKS_")]
+    assert len(names) >= 15
+    for n in names:
+        assert n in defs, n
+        assert getattr(native, n) == defs[n], n
