@@ -59,6 +59,9 @@ def _load():
     lib.ddks_oracle_significance.argtypes = [vp, i64, i64, i32, ctypes.c_uint64,
                                              ctypes.POINTER(ctypes.c_double)]
     lib.ddks_oracle_significance.restype = ctypes.c_int
+    lib.ddks_oracle_vdks.argtypes = [vp, i64, vp, i64, i32, i32, u64p, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.ddks_oracle_vdks.restype = ctypes.c_int
     lib.ddks_oracle_origin_counts.argtypes = [vp, i64, vp, i64, i32, vp, i64, vp]
     lib.ddks_oracle_origin_counts.restype = ctypes.c_int
     _lib = lib
@@ -183,3 +186,33 @@ def significance(counts, n_p: int, n_q: int, d: int, num: int, model: str = "bin
     if st != 0:
         raise ValueError(f"oracle significance failed with status {st}")
     return S.value
+
+
+@dataclass
+class VdksResult:
+    num: int
+    den: int
+    D: float
+    argmax_voxel: int    # sum_m v_m V^m of the maximising voxel (lowest)
+    argmax_orthant: int
+    n_filled: int        # voxels holding at least one point
+
+
+def vdks(P, Q, V: int) -> VdksResult:
+    """vdKS (Alg. 1) with V voxels per dimension."""
+    lib = _load()
+    P, Q = _f32(P), _f32(Q)
+    if P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must have the same dimension")
+    n_p, d = P.shape
+    n_q = Q.shape[0]
+    num = ctypes.c_uint64()
+    kv = ctypes.c_int64()
+    jo = ctypes.c_int32()
+    nf = ctypes.c_int64()
+    st = lib.ddks_oracle_vdks(P.ctypes.data, n_p, Q.ctypes.data, n_q, d, V, ctypes.byref(num),
+                              ctypes.byref(kv), ctypes.byref(jo), ctypes.byref(nf))
+    if st != 0:
+        raise ValueError(f"oracle vdks failed with status {st}")
+    den = n_p * n_q
+    return VdksResult(num.value, den, num.value / den, kv.value, jo.value, nf.value)

@@ -42,6 +42,11 @@
  *   support 0..m (the set Delta), so P(delta <= D) is the windowed sum of
  *   products of Poisson pmfs over that support.
  *
+ *   Sec. 2.2.2, Alg. 1 (vdKS): the voxel approximation -- the pooled points
+ *   binned on a V^d grid of the normalised data, orthant sums of the two
+ *   samples' voxel counts around every filled voxel (readings at
+ *   ddks_oracle_vdks).
+ *
  *   Sec. 3 / Sec. 4.2: permutation test -- the statistic recomputed for
  *   relabelled pooled samples; here each relabelling is rebuilt as two
  *   samples in index order and the definition is re-run from scratch.
@@ -478,5 +483,152 @@ int ddks_oracle_origin_counts(const float *P, int64_t n_p, const float *Q, int64
         for (int64_t i = 0; i < n_p; ++i) c[orthant_code(P + i * d, o, d) * 2 + 0] += 1;
         for (int64_t i = 0; i < n_q; ++i) c[orthant_code(Q + i * d, o, d) * 2 + 1] += 1;
     }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* vdKS: voxel approximation of the statistic (Sec. 2.2.2, Alg. 1)            */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Readings of Alg. 1:
+ *  - NormalizeData maps each dimension of the pooled points linearly onto
+ *    [0, 1]: u = (x - lo) / (hi - lo) with lo, hi the pooled minimum and
+ *    maximum (u = 0 where hi == lo);
+ *  - IndexFromPoint gives the voxel coordinate v_m = min(V - 1, floor(u_m V))
+ *    with V voxels per dimension -- all of it in fp64 (the float inputs
+ *    convert exactly, then one subtraction, one division, one product);
+ *  - SumOrthants splits the voxels around a filled voxel as Eq. g splits the
+ *    points around an origin: bit m of the orthant is [w_m >= u_m], so the
+ *    origin voxel lies in its own all-upper orthant;
+ *  - the value of an orthant is the absolute difference of the two samples'
+ *    proportions in it (Eq. d1), taken exactly in integers as
+ *    |c_P n_q - c_Q n_p|, over every filled voxel (either sample).
+ * The reported maximiser is the lowest voxel key sum_m v_m V^m, then the
+ * lowest orthant code.
+ */
+typedef struct {
+    uint64_t key;
+    int sample; /* 0 = P, 1 = Q */
+} vox_point;
+
+static int cmp_vox_point(const void *a, const void *b)
+{
+    const vox_point *x = (const vox_point *)a, *y = (const vox_point *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->sample - y->sample;
+}
+
+int ddks_oracle_vdks(const float *P, int64_t n_p, const float *Q, int64_t n_q, int32_t d, int32_t V,
+                     uint64_t *num, int64_t *arg_voxel, int32_t *arg_orthant, int64_t *n_filled)
+{
+    if (!P || !Q || !num || n_p < 1 || n_q < 1 || d < 1 || d > 16 || V < 1) return ORACLE_EINVAL;
+    {
+        double cells = 1.0;
+        for (int m = 0; m < d; ++m) cells *= (double)V;
+        if (cells > 4.0e18) return ORACLE_EINVAL; /* keys must fit 63 bits */
+    }
+    const int64_t N = n_p + n_q;
+    double lo[16], hi[16];
+    for (int m = 0; m < d; ++m) {
+        lo[m] = INFINITY;
+        hi[m] = -INFINITY;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        const float *x = i < n_p ? P + i * d : Q + (i - n_p) * d;
+        for (int m = 0; m < d; ++m) {
+            double v = (double)x[m];
+            if (!isfinite(v)) return ORACLE_EINVAL;
+            if (v < lo[m]) lo[m] = v;
+            if (v > hi[m]) hi[m] = v;
+        }
+    }
+    vox_point *pts = (vox_point *)malloc((size_t)N * sizeof(vox_point));
+    if (!pts) return ORACLE_ENOMEM;
+    for (int64_t i = 0; i < N; ++i) {
+        const float *x = i < n_p ? P + i * d : Q + (i - n_p) * d;
+        uint64_t key = 0, scale = 1;
+        for (int m = 0; m < d; ++m) {
+            int64_t v = 0;
+            if (hi[m] > lo[m]) {
+                double u = ((double)x[m] - lo[m]) / (hi[m] - lo[m]);
+                v = (int64_t)floor(u * (double)V);
+                if (v > V - 1) v = V - 1;
+                if (v < 0) v = 0;
+            }
+            key += (uint64_t)v * scale;
+            scale *= (uint64_t)V;
+        }
+        pts[i].key = key;
+        pts[i].sample = i < n_p ? 0 : 1;
+    }
+    qsort(pts, (size_t)N, sizeof(vox_point), cmp_vox_point);
+    /* the filled voxels, in key order, with their counts per sample */
+    int64_t M = 0;
+    for (int64_t i = 0; i < N; ++i)
+        if (i == 0 || pts[i].key != pts[i - 1].key) ++M;
+    uint64_t *vk = (uint64_t *)malloc((size_t)M * sizeof(uint64_t));
+    int64_t *vc = (int64_t *)calloc((size_t)M * 2, sizeof(int64_t));
+    int32_t *coord = (int32_t *)malloc((size_t)M * d * sizeof(int32_t));
+    const uint32_t bins = (uint32_t)1 << d;
+    int64_t *cp = (int64_t *)malloc(bins * sizeof(int64_t));
+    int64_t *cq = (int64_t *)malloc(bins * sizeof(int64_t));
+    if (!vk || !vc || !coord || !cp || !cq) {
+        free(pts);
+        free(vk);
+        free(vc);
+        free(coord);
+        free(cp);
+        free(cq);
+        return ORACLE_ENOMEM;
+    }
+    M = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        if (i == 0 || pts[i].key != pts[i - 1].key) {
+            vk[M] = pts[i].key;
+            uint64_t k = pts[i].key;
+            for (int m = 0; m < d; ++m) {
+                coord[M * d + m] = (int32_t)(k % (uint64_t)V);
+                k /= (uint64_t)V;
+            }
+            ++M;
+        }
+        vc[(M - 1) * 2 + pts[i].sample] += 1;
+    }
+    uint64_t best = 0;
+    int64_t bk = 0;
+    int32_t bj = 0;
+    int have = 0;
+    for (int64_t a = 0; a < M; ++a) {
+        memset(cp, 0, bins * sizeof(int64_t));
+        memset(cq, 0, bins * sizeof(int64_t));
+        for (int64_t b = 0; b < M; ++b) {
+            uint32_t code = 0;
+            for (int m = 0; m < d; ++m)
+                if (coord[b * d + m] >= coord[a * d + m]) code |= 1u << m;
+            cp[code] += vc[b * 2];
+            cq[code] += vc[b * 2 + 1];
+        }
+        for (uint32_t j = 0; j < bins; ++j) {
+            int64_t diff = cp[j] * n_q - cq[j] * n_p;
+            uint64_t sc = (uint64_t)(diff < 0 ? -diff : diff);
+            if (!have || sc > best) {
+                best = sc;
+                bk = (int64_t)vk[a];
+                bj = (int32_t)j;
+                have = 1;
+            }
+        }
+    }
+    *num = best;
+    if (arg_voxel) *arg_voxel = bk;
+    if (arg_orthant) *arg_orthant = bj;
+    if (n_filled) *n_filled = M;
+    free(pts);
+    free(vk);
+    free(vc);
+    free(coord);
+    free(cp);
+    free(cq);
     return ORACLE_OK;
 }
