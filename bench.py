@@ -103,6 +103,31 @@ def bench_significance(ctx, native, torch, Pt, Qt, workload, reps=5):
     return out
 
 
+def bench_vdks(ctx, torch, dev, reps=5):
+    """vdKS (Alg. 1) on the d = 4 and d = 6 workloads with device-resident
+    inputs: time per call, filled voxels M, the weighted sweep's M^2 d
+    compares per second, and D beside the exact statistic."""
+    from paper_2106_13706_amd import workloads
+    out = {}
+    for name, gen, V in (("gaussian_scale_d4_20000", workloads.gaussian_scale, 16),
+                         ("mixture_grid_d6_100000", workloads.mixture_grid, 8)):
+        P, Q = gen()
+        Pt, Qt = torch.from_numpy(P).to(dev), torch.from_numpy(Q).to(dev)
+        r, M = ctx.vdks(Pt, Qt, V)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r, M = ctx.vdks(Pt, Qt, V)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        exact = ctx.distance(Pt, Qt)
+        out[f"{name}_V{V}"] = {"voxels_per_dim": V, "ms_per_call": sec * 1e3, "filled_voxels": M,
+                               "weighted_compares_per_s": M * M * P.shape[1] / sec,
+                               "D": r.D, "exact_D": exact.D}
+        del Pt, Qt
+    return out
+
+
 def bench_batch(ctx, torch, dev, reps=5):
     """Permutation batch (d=5, pooled 2x4096, 1024 relabellings): one call =
     observed split + all relabellings, replayed from a captured graph; against
@@ -317,6 +342,8 @@ def main():
         del P3t, Q3t
         _log("[bench] extra: analytic significance")
         extras["significance"] = bench_significance(ctx, native, torch, Pt, Qt, workload)
+        _log("[bench] extra: vdKS")
+        extras["vdks"] = bench_vdks(ctx, torch, dev)
         _log("[bench] extra: permutation batch")
         extras["permutation_batch"] = bench_batch(ctx, torch, dev)
         _log(f"[bench] extra: serving ({args.serve_requests} requests)")

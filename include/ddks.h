@@ -156,6 +156,25 @@ int ddks_permutation_batch(ddks_ctx *ctx, const float *Z, int64_t n, int32_t d, 
 int ddks_significance(ddks_ctx *ctx, const uint32_t *counts, int64_t n_p, int64_t n_q, int32_t d,
                       uint64_t num, uint32_t flags, double *S_out);
 
+/*
+ * vdKS, the voxel approximation of the statistic (Sec. 2.2.2, Alg. 1): the
+ * pooled points normalised per dimension onto [0, 1] (u = (x - lo)/(hi - lo),
+ * u = 0 where hi == lo) and binned on a grid of voxels_per_dim^d voxels,
+ * coordinate v_m = min(V - 1, floor(u_m V)) evaluated in fp64; around every
+ * filled voxel the voxels split into orthants as points do around an origin
+ * (Eq. g, >= per coordinate); out->num / out->den is the largest absolute
+ * difference of the two samples' proportions in one orthant (Eq. d1).
+ * out->argmax_origin receives the lowest maximising voxel's key
+ * sum_m v_m V^m (not a point index), argmax_orthant its lowest code, S = -1.
+ * n_filled (nullable): the number of voxels holding a point.
+ * P, Q as in ddks_distance (host memory unless DDKS_DEVICE_PTRS).
+ * Limits: 1 <= d <= 8, 1 <= voxels_per_dim <= 65535, voxels_per_dim^d < 4e18,
+ * n_p + n_q < 2^30.
+ * Errors: DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOMEM, DDKS_E_DEVICE.
+ */
+int ddks_vdks(ddks_ctx *ctx, const float *P, int64_t n_p, const float *Q, int64_t n_q, int32_t d,
+              int32_t voxels_per_dim, uint32_t flags, ddks_result *out, int64_t *n_filled);
+
 /* ---------------------------------------------------------------- serving */
 
 typedef struct ddks_request {

@@ -142,6 +142,28 @@ hipError_t launch_perm(int path, int d, int pb, const void *Z, int64_t N, int64_
                        const uint64_t *inc, int B, const uint32_t *obs_counts,
                        unsigned long long *nums, hipStream_t s);
 
+// ---------------------------------------------------------------- vdKS
+
+// Slots of the voxel hash table for N points (a power of two >= 2 N).
+size_t vdks_table_slots(int64_t N);
+// Bytes of the per-block results of the voxel sweep over M filled voxels.
+size_t vdks_best_bytes(int64_t M);
+
+// Per-dimension extent of Z (N x d, -0 already mapped to +0), each point's
+// voxel key sum_m v_m V^m merged into the table (slots entries: keys, then 2
+// counts each), and the filled voxels compacted into keys[] and inc[]
+// (c_P | c_Q << 32), their number in *counter.  mm: 2 d words of scratch.
+hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V, uint32_t *mm,
+                            uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots, uint32_t *counter,
+                            uint64_t *keys, uint64_t *inc, hipStream_t s);
+
+// The weighted sweep over the M filled voxels (R: M x point_words(R16, d)
+// scratch, bb: vdks_best_bytes(M)); *out = (num, lowest maximising voxel key,
+// its lowest code, *flags), *flags cleared.
+hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
+                         int64_t n_q, uint32_t *R, void *bb, uint32_t *flags, ResultDev *out,
+                         hipStream_t s);
+
 // ---------------------------------------------------------------- significance
 
 // Rate models of the analytic significance (Sec. 3).

@@ -372,7 +372,7 @@ int ddks_destroy(ddks_ctx *c)
     serve_stop(c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
-    DevBuf *bufs[] = {&c->z, &c->zr, &c->partial, &c->block_best, &c->counts, &c->rank_scratch,
+    DevBuf *bufs[] = {&c->z, &c->zr, &c->vox, &c->partial, &c->block_best, &c->counts, &c->rank_scratch,
                       &c->labels, &c->nums, &c->sig, &c->inc, &c->obs};
     for (DevBuf *b : bufs) release(c, *b);
     if (c->result_dev) (void)hipFree(c->result_dev);

@@ -45,7 +45,7 @@ struct ddks_ctx {
     std::mutex mu;  // serialises the synchronous calls on `stream`
 
     // buffers of the synchronous path
-    ddks::DevBuf z, zr, partial, block_best, counts, rank_scratch, labels, nums, sig, inc, obs;
+    ddks::DevBuf z, zr, partial, block_best, counts, rank_scratch, labels, nums, sig, inc, obs, vox;
     uint64_t buf_gen = 0;  // bumped whenever a buffer is reallocated
 
     // captured permutation-batch graph, replayed while its key matches

@@ -1,0 +1,82 @@
+// Host side of vdKS (arXiv:2106.13706, Sec. 2.2.2, Alg. 1): ddks_vdks.
+#include <math.h>
+
+#include "ddks_runtime.h"
+
+using namespace ddks;
+
+extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int64_t n_q,
+                         int32_t d, int32_t voxels_per_dim, uint32_t flags, ddks_result *out,
+                         int64_t *n_filled)
+{
+    if (!c) return DDKS_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->poisoned) return fail(c, DDKS_E_DEVICE, "context poisoned by an earlier device error");
+    if (!P || !Q || !out) return fail(c, DDKS_E_INVALID_ARG, "null pointer argument");
+    if (d < 1 || d > 8) return fail(c, DDKS_E_INVALID_ARG, "d must be in [1, 8]");
+    if (n_p < 1 || n_q < 1) return fail(c, DDKS_E_INVALID_ARG, "each sample needs at least one point");
+    const int64_t N = n_p + n_q;
+    if (N > 0x3fffffffLL) return fail(c, DDKS_E_INVALID_ARG, "n_p + n_q exceeds 2^30 - 1");
+    const int V = voxels_per_dim;
+    if (V < 1 || V > 65535) return fail(c, DDKS_E_INVALID_ARG, "voxels_per_dim must be in [1, 65535]");
+    if (pow((double)V, (double)d) > 4.0e18)
+        return fail(c, DDKS_E_INVALID_ARG, "voxels_per_dim^d must stay below 4e18");
+    if (hipSetDevice(c->device) != hipSuccess) return hip_check(c, hipGetLastError(), "hipSetDevice");
+    const bool dev = (flags & DDKS_DEVICE_PTRS) != 0;
+    hipStream_t s = c->stream;
+
+    const int64_t slots = (int64_t)vdks_table_slots(N);
+    const size_t pts = (size_t)N * d * sizeof(float);
+    const size_t table = (size_t)slots * (sizeof(uint64_t) + 2 * sizeof(uint32_t));
+    const size_t list = (size_t)N * 2 * sizeof(uint64_t);  // keys, increments
+    const size_t r16 = (size_t)N * point_words(PATH_R16, d) * sizeof(uint32_t);
+    const size_t best = vdks_best_bytes(N);
+    int st = ensure(c, c->z, pts, "points");
+    if (!st) st = ensure(c, c->vox, table + list + 128, "voxel table");  // + counter and extents
+    if (!st) st = ensure(c, c->zr, r16, "voxel encoding");
+    if (!st) st = ensure(c, c->block_best, best, "block results");
+    if (st) return st;
+    float *Z = (float *)c->z.ptr;
+    uint64_t *tab_key = (uint64_t *)c->vox.ptr;
+    uint32_t *tab_cnt = (uint32_t *)(tab_key + slots);
+    uint64_t *keys = (uint64_t *)(tab_cnt + 2 * slots);
+    uint64_t *inc = keys + N;
+    uint32_t *counter = (uint32_t *)(inc + N);
+    uint32_t *mm = counter + 4;  // 2 d words
+
+    const float *srcP = P, *srcQ = Q;
+    if (!dev) {
+        st = hip_check(c, hipMemcpyAsync(Z, P, (size_t)n_p * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D P");
+        if (!st) st = hip_check(c, hipMemcpyAsync(Z + n_p * d, Q, (size_t)n_q * d * sizeof(float), hipMemcpyHostToDevice, s), "H2D Q");
+        if (st) return st;
+        srcP = Z;
+        srcQ = Z + n_p * d;
+    }
+    st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
+    if (!st) st = hip_check(c, launch_vox_front(Z, N, n_p, d, V, mm, tab_key, tab_cnt, slots, counter, keys,
+                                                inc, s), "voxel launch");
+    // the number of filled voxels sizes the sweep
+    if (!st) st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, counter, sizeof(uint32_t),
+                                              hipMemcpyDeviceToHost, s), "D2H voxel count");
+    if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (st) return st;
+    const int64_t M = *c->rank_distinct_host;
+    if (M < 1 || M > N) return fail(c, DDKS_E_DEVICE, "voxel compaction produced an invalid count");
+    st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, (uint32_t *)c->zr.ptr, c->block_best.ptr,
+                                    c->flags_dev, c->result_host, s), "voxel sweep launch");
+    if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (st) return st;
+    const ResultDev r = *c->result_host;
+    if (r.flags & 1u) return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
+    out->num = r.num;
+    out->den = (uint64_t)n_p * (uint64_t)n_q;
+    out->D = (double)r.num / (double)out->den;
+    out->argmax_origin = r.origin;
+    out->argmax_orthant = r.code;
+    out->d = d;
+    out->n_p = n_p;
+    out->n_q = n_q;
+    out->S = -1.0;
+    if (n_filled) *n_filled = M;
+    return DDKS_OK;
+}

@@ -1,0 +1,459 @@
+// vdKS, the voxel approximation of the statistic (arXiv:2106.13706,
+// Sec. 2.2.2, Alg. 1), on gfx950.
+//
+// Readings: the pooled points are normalised per dimension onto [0, 1]
+// (u = (x - lo)/(hi - lo), u = 0 where hi == lo) and binned on a V^d grid,
+// voxel coordinate v_m = min(V - 1, floor(u_m V)) in fp64; around every filled
+// voxel the voxels split into orthants as points do around an origin in
+// Eq. g (bit m = [w_m >= u_m]); the statistic is the largest absolute
+// difference of the two samples' proportions in an orthant (Eq. d1).
+//
+// That is the exact statistic of the voxel coordinates with every filled
+// voxel as an origin, so the device work is:
+//   1. per-dimension minimum and maximum (ordered-key atomics);
+//   2. each point's voxel key sum_m v_m V^m, merged into an open-addressing
+//      hash table (64-bit CAS) that counts each sample's points per voxel;
+//   3. the filled voxels compacted into a list, their coordinates written as
+//      biased int16 ranks (a voxel coordinate is its own rank) and their
+//      counts as one 64-bit increment (P in the low, Q in the high word);
+//   4. the weighted sweep: every filled voxel against every filled voxel,
+//      the orthant code exactly as in the exact sweep, 64-bit LDS bins so
+//      that any sample size fits, then the scores |c_P n_Q - c_Q n_P| and the
+//      maximum with ties to the lowest voxel key, then the lowest code.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "ddks_device.h"
+
+namespace ddks {
+
+typedef __attribute__((address_space(3))) uint64_t lds_u64v;
+
+static constexpr uint64_t VOX_EMPTY = ~0ull;
+
+// Order-preserving image of a finite fp32 value, and its inverse.
+__device__ __forceinline__ uint32_t vox_order_key(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float vox_from_key(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+__global__ void k_vox_init(uint32_t *__restrict__ mm, int d, uint64_t *__restrict__ tab_key,
+                           uint32_t *__restrict__ tab_cnt, int64_t slots, uint32_t *__restrict__ counter)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slots;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        tab_key[i] = VOX_EMPTY;
+        tab_cnt[2 * i] = 0u;
+        tab_cnt[2 * i + 1] = 0u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)d) {
+        mm[2 * threadIdx.x] = 0xffffffffu;  // running minimum key
+        mm[2 * threadIdx.x + 1] = 0u;       // running maximum key
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_vox_minmax(const float *__restrict__ Z, int64_t N,
+                                                    uint32_t *__restrict__ mm)
+{
+    uint32_t lo[D], hi[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        lo[m] = 0xffffffffu;
+        hi[m] = 0u;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            const uint32_t k = vox_order_key(Z[i * D + m]);
+            lo[m] = min(lo[m], k);
+            hi[m] = max(hi[m], k);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            lo[m] = min(lo[m], (uint32_t)__shfl_xor((int)lo[m], off, 64));
+            hi[m] = max(hi[m], (uint32_t)__shfl_xor((int)hi[m], off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&mm[2 * m], lo[m]);
+            atomicMax(&mm[2 * m + 1], hi[m]);
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t vox_hash(uint64_t key, uint64_t mask)
+{
+    return (key * 0x9e3779b97f4a7c15ull >> 17) & mask;
+}
+
+// Voxel key of every point, merged into the table (linear probing; the table
+// has at least twice as many slots as points, so every probe ends).
+template <int D>
+__global__ __launch_bounds__(256) void k_vox_insert(const float *__restrict__ Z, int64_t N, int64_t n_p,
+                                                    int V, const uint32_t *__restrict__ mm,
+                                                    uint64_t *__restrict__ tab_key,
+                                                    uint32_t *__restrict__ tab_cnt, uint64_t mask)
+{
+    double lo[D], span[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        lo[m] = (double)vox_from_key(mm[2 * m]);
+        span[m] = (double)vox_from_key(mm[2 * m + 1]) - lo[m];
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t key = 0, scale = 1;
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            int64_t v = 0;
+            if (span[m] > 0.0) {
+                const double u = ((double)Z[i * D + m] - lo[m]) / span[m];
+                v = (int64_t)floor(u * (double)V);
+                v = v > V - 1 ? V - 1 : (v < 0 ? 0 : v);
+            }
+            key += (uint64_t)v * scale;
+            scale *= (uint64_t)V;
+        }
+        uint64_t h = vox_hash(key, mask);
+        while (true) {
+            const unsigned long long old = atomicCAS((unsigned long long *)&tab_key[h], VOX_EMPTY, key);
+            if (old == VOX_EMPTY || old == key) break;
+            h = (h + 1) & mask;
+        }
+        atomicAdd(&tab_cnt[2 * h + (i < n_p ? 0 : 1)], 1u);
+    }
+}
+
+// Filled slots to a list: key, and the 64-bit increment c_P | c_Q << 32.
+__global__ void k_vox_compact(const uint64_t *__restrict__ tab_key, const uint32_t *__restrict__ tab_cnt,
+                              int64_t slots, uint32_t *__restrict__ counter, uint64_t *__restrict__ keys,
+                              uint64_t *__restrict__ inc)
+{
+    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < slots;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = tab_key[h];
+        if (k == VOX_EMPTY) continue;
+        const uint32_t at = atomicAdd(counter, 1u);
+        keys[at] = k;
+        inc[at] = (uint64_t)tab_cnt[2 * h] | ((uint64_t)tab_cnt[2 * h + 1] << 32);
+    }
+}
+
+// Voxel coordinates as biased int16 ranks in the rank-16 point layout.
+template <int D>
+__global__ void k_vox_encode(const uint64_t *__restrict__ keys, int64_t M, int V,
+                             uint32_t *__restrict__ R)
+{
+    constexpr int PW = Layout<PATH_R16, D>::PW;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t k = keys[i];
+        uint32_t w[PW];
+#pragma unroll
+        for (int p = 0; p < PW; ++p) w[p] = 0u;
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            const uint32_t v = (uint32_t)(k % (uint64_t)V);
+            k /= (uint64_t)V;
+            const uint32_t r = (v - 32768u) & 0xffffu;
+            w[m >> 1] |= r << (16 * (m & 1));
+        }
+#pragma unroll
+        for (int p = 0; p < PW; ++p) R[i * PW + p] = w[p];
+    }
+}
+
+struct VBest {
+    uint64_t num;
+    uint64_t key;
+    int32_t code;
+    int32_t pad;
+};
+
+__device__ __forceinline__ bool vbetter(uint64_t an, uint64_t ak, int32_t ac, uint64_t bn, uint64_t bk,
+                                        int32_t bc)
+{
+    if (an != bn) return an > bn;
+    if (ak != bk) return ak < bk;
+    return ac < bc;
+}
+
+// Block (group): the 64 filled voxels group*64 + lane as origins, every filled
+// voxel as a weighted point, split over the W waves, one shared histogram of
+// 64-bit bins (lane-minor: bin*64 + lane).
+template <int D, int W>
+__global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ R,
+                                                   const uint64_t *__restrict__ inc,
+                                                   const uint64_t *__restrict__ keys, int64_t M,
+                                                   int64_t n_p, int64_t n_q, VBest *__restrict__ bb)
+{
+    constexpr int BINS = Geo<D>::BINS;
+    constexpr int PW = Layout<PATH_R16, D>::PW;
+    constexpr int NP = Geo<D>::NPERM;
+    constexpr int U = 4;
+    extern __shared__ uint64_t h64[];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t group = blockIdx.x;
+
+    for (int i = threadIdx.x; i < BINS * 64; i += W * 64) h64[i] = 0;
+    const int64_t k = group * 64 + lane;
+    Origin<PATH_R16, D> org;
+    org.load(R, k < M ? k : M - 1);
+    __syncthreads();
+
+    const int64_t per = (M + W - 1) / W;
+    int64_t a = (int64_t)w * per, b = a + per;
+    a = a < M ? a : M;
+    b = b < M ? b : M;
+    a = __builtin_amdgcn_readfirstlane((int)a);
+    b = __builtin_amdgcn_readfirstlane((int)b);
+
+    const uint32_t base = (uint32_t)(uintptr_t)(lds_u64v *)(h64 + Geo<D>::KOFF * 64 + lane);
+    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+    int64_t i = a;
+    for (; i + U <= b; i += U) {
+        uint32_t buf[U * PW];
+        uint64_t iv[U];
+#pragma unroll
+        for (int e = 0; e < U * PW; ++e) buf[e] = R[i * PW + e];
+#pragma unroll
+        for (int u = 0; u < U; ++u) iv[u] = inc[i + u];
+        uint32_t Rg[2][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint32_t r[Geo<D>::NREG];
+            signs<PATH_R16, D>(buf + u * PW, org, r);
+            Rg[0][u] = group_bytes<D>(r, 0);
+            Rg[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+        }
+        uint32_t ad[4];
+        addr4<NP, 9>(Rg, base, ad, w0, w1);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            __hip_atomic_fetch_add((lds_u64v *)(uintptr_t)ad[u], iv[u], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    for (; i < b; ++i) {
+        uint32_t buf[PW];
+#pragma unroll
+        for (int e = 0; e < PW; ++e) buf[e] = R[i * PW + e];
+        uint32_t r[Geo<D>::NREG];
+        signs<PATH_R16, D>(buf, org, r);
+        const uint32_t R0 = group_bytes<D>(r, 0);
+        const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+        __hip_atomic_fetch_add((lds_u64v *)(uintptr_t)addr1<NP, 9>(R0, R1, base, w0, w1), inc[i],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+
+    // scores of this lane's origin over the bins j = w, w + W, ...
+    const bool valid = k < M;
+    uint64_t best = 0;
+    int32_t bcode = 0x7fffffff;
+    if (valid) {
+        for (int j = w; j < BINS; j += W) {
+            const uint64_t c = h64[j * 64 + lane];
+            const int64_t cp = (int64_t)(uint32_t)c, cq = (int64_t)(c >> 32);
+            const int64_t sd = cp * n_q - cq * n_p;
+            const uint64_t s = (uint64_t)(sd < 0 ? -sd : sd);
+            const int32_t code = j ^ Geo<D>::FLIP;
+            if (s > best || (s == best && code < bcode)) {
+                best = s;
+                bcode = code;
+            }
+        }
+    }
+    __syncthreads();  // the histogram has been read; its LDS is reused below
+    uint64_t *sn = h64;
+    int32_t *sc = reinterpret_cast<int32_t *>(h64 + W * 64);
+    sn[w * 64 + lane] = best;
+    sc[w * 64 + lane] = bcode;
+    __syncthreads();
+    if (w == 0) {
+        for (int v = 1; v < W; ++v) {
+            const uint64_t n2 = sn[v * 64 + lane];
+            const int32_t c2 = sc[v * 64 + lane];
+            if (n2 > best || (n2 == best && c2 < bcode)) {
+                best = n2;
+                bcode = c2;
+            }
+        }
+        uint64_t key = valid ? keys[k] : VOX_EMPTY;
+        if (!valid) {
+            best = 0;
+            bcode = 0x7fffffff;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const uint64_t n2 = __shfl_xor(best, off, 64);
+            const uint64_t k2 = __shfl_xor(key, off, 64);
+            const int32_t c2 = __shfl_xor(bcode, off, 64);
+            if (vbetter(n2, k2, c2, best, key, bcode)) {
+                best = n2;
+                key = k2;
+                bcode = c2;
+            }
+        }
+        if (lane == 0) {
+            VBest r;
+            r.num = best;
+            r.key = key;
+            r.code = bcode;
+            r.pad = 0;
+            bb[group] = r;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_vreduce(const VBest *__restrict__ bb, int64_t n,
+                                                  uint32_t *__restrict__ flags,
+                                                  ResultDev *__restrict__ out)
+{
+    __shared__ uint64_t sn[16], sk[16];
+    __shared__ int32_t sc[16];
+    uint64_t best = 0, key = VOX_EMPTY;
+    int32_t code = 0x7fffffff;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const VBest b = bb[i];
+        if (vbetter(b.num, b.key, b.code, best, key, code)) {
+            best = b.num;
+            key = b.key;
+            code = b.code;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t n2 = __shfl_xor(best, off, 64);
+        const uint64_t k2 = __shfl_xor(key, off, 64);
+        const int32_t c2 = __shfl_xor(code, off, 64);
+        if (vbetter(n2, k2, c2, best, key, code)) {
+            best = n2;
+            key = k2;
+            code = c2;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sn[w] = best;
+        sk[w] = key;
+        sc[w] = code;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x >> 6); ++v)
+            if (vbetter(sn[v], sk[v], sc[v], best, key, code)) {
+                best = sn[v];
+                key = sk[v];
+                code = sc[v];
+            }
+        out->num = best;
+        out->origin = (int64_t)key;
+        out->code = code;
+        out->flags = *flags;
+        out->ge = 0;
+        *flags = 0u;
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+static unsigned grid_for(int64_t n, int per_block = 256, int64_t cap = 4096)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, cap));
+}
+
+size_t vdks_table_slots(int64_t N)
+{
+    size_t s = 64;
+    while (s < (size_t)(2 * N)) s <<= 1;
+    return s;
+}
+
+template <int D>
+static hipError_t launch_vox_front_d(const float *Z, int64_t N, int64_t n_p, int V, uint32_t *mm,
+                                     uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots,
+                                     uint32_t *counter, uint64_t *keys, uint64_t *inc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vox_init, dim3(grid_for(slots)), dim3(256), 0, s, mm, D, tab_key, tab_cnt,
+                       slots, counter);
+    hipLaunchKernelGGL(k_vox_minmax<D>, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s, Z, N, mm);
+    hipLaunchKernelGGL(k_vox_insert<D>, dim3(grid_for(N)), dim3(256), 0, s, Z, N, n_p, V, mm, tab_key,
+                       tab_cnt, (uint64_t)(slots - 1));
+    hipLaunchKernelGGL(k_vox_compact, dim3(grid_for(slots)), dim3(256), 0, s, tab_key, tab_cnt, slots,
+                       counter, keys, inc);
+    return hipGetLastError();
+}
+
+hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V, uint32_t *mm,
+                            uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots, uint32_t *counter,
+                            uint64_t *keys, uint64_t *inc, hipStream_t s)
+{
+    if (slots < 2 * N || (slots & (slots - 1))) return hipErrorInvalidValue;
+    switch (d) {
+#define DDKS_VF(DD) \
+    case DD: return launch_vox_front_d<DD>(Z, N, n_p, V, mm, tab_key, tab_cnt, slots, counter, keys, inc, s);
+        DDKS_VF(1) DDKS_VF(2) DDKS_VF(3) DDKS_VF(4) DDKS_VF(5) DDKS_VF(6) DDKS_VF(7) DDKS_VF(8)
+#undef DDKS_VF
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static constexpr int VSWEEP_WAVES = 8;
+
+size_t vsweep_lds_bytes(int d)
+{
+    const size_t hist = ((size_t)1 << d) * 64 * 8;
+    const size_t fin = (size_t)VSWEEP_WAVES * 64 * 12;
+    return std::max(hist, fin);
+}
+
+template <int D>
+static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int64_t M, int V,
+                                  int64_t n_p, int64_t n_q, uint32_t *R, void *bb, uint32_t *flags,
+                                  ResultDev *out, hipStream_t s)
+{
+    constexpr int W = VSWEEP_WAVES;
+    hipLaunchKernelGGL(k_vox_encode<D>, dim3(grid_for(M)), dim3(256), 0, s, keys, M, V, R);
+    const size_t lds = vsweep_lds_bytes(D);
+    static bool attr = false;
+    if (!attr && lds > 64 * 1024) {
+        if (hipFuncSetAttribute((const void *)k_vsweep<D, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                MAX_LDS_BYTES) != hipSuccess)
+            (void)hipGetLastError();
+        attr = true;
+    }
+    const int64_t groups = (M + 63) / 64;
+    hipLaunchKernelGGL((k_vsweep<D, W>), dim3((unsigned)groups), dim3(W * 64), lds, s, R, inc, keys, M,
+                       n_p, n_q, (VBest *)bb);
+    hipLaunchKernelGGL(k_vreduce, dim3(1), dim3(1024), 0, s, (const VBest *)bb, groups, flags, out);
+    return hipGetLastError();
+}
+
+size_t vdks_best_bytes(int64_t M) { return (size_t)((M + 63) / 64) * sizeof(VBest); }
+
+hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
+                         int64_t n_q, uint32_t *R, void *bb, uint32_t *flags, ResultDev *out,
+                         hipStream_t s)
+{
+    if (M < 1 || M > 0x7fffffff) return hipErrorInvalidValue;
+    switch (d) {
+#define DDKS_VS(DD) case DD: return launch_vsweep_d<DD>(keys, inc, M, V, n_p, n_q, R, bb, flags, out, s);
+        DDKS_VS(1) DDKS_VS(2) DDKS_VS(3) DDKS_VS(4) DDKS_VS(5) DDKS_VS(6) DDKS_VS(7) DDKS_VS(8)
+#undef DDKS_VS
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ddks

@@ -40,7 +40,7 @@ EXPORTS = (
     "ddks_default_options", "ddks_create", "ddks_destroy", "ddks_distance",
     "ddks_permutation_batch", "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
     "ddks_serve_stats_get", "ddks_profile_get", "ddks_status_string", "ddks_last_error",
-    "ddks_version",
+    "ddks_version", "ddks_vdks",
 )
 
 
@@ -139,6 +139,8 @@ def load(path: str = LIB_PATH):
     lib.ddks_serve_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(u64)]
     lib.ddks_serve_poll.argtypes = [vp, u64, i32, ctypes.POINTER(_Result)]
     lib.ddks_serve_stats_get.argtypes = [vp, ctypes.POINTER(_ServeStats), i32]
+    lib.ddks_vdks.argtypes = [vp, vp, i64, vp, i64, i32, i32, u32, ctypes.POINTER(_Result),
+                              ctypes.POINTER(i64)]
     lib.ddks_profile_get.argtypes = [vp, ctypes.POINTER(_Profile), i32]
     lib.ddks_status_string.argtypes = [ctypes.c_int]
     lib.ddks_status_string.restype = ctypes.c_char_p
@@ -284,6 +286,24 @@ class Context:
         self._check(st, "ddks_permutation_batch")
         summary = {"B": sm.B, "n_ge": sm.n_ge, "p_value": sm.p_value, "fraction": sm.fraction}
         return nums, Result._from(r), summary
+
+    def vdks(self, P, Q, voxels_per_dim: int, *, flags: int = 0):
+        """vdKS (Alg. 1) of P and Q on a voxels_per_dim^d grid: (Result,
+        number of filled voxels); Result.argmax_origin is the voxel key."""
+        pp, n_p, d, kp, dev_p = _points(P)
+        qp, n_q, dq, kq, dev_q = _points(Q)
+        if d != dq:
+            raise ValueError("P and Q must have the same number of columns")
+        if dev_p != dev_q:
+            raise ValueError("P and Q must both be host arrays or both device tensors")
+        if dev_p:
+            flags |= DDKS_DEVICE_PTRS
+        r = _Result()
+        nf = ctypes.c_int64()
+        st = self._lib.ddks_vdks(self._h, pp, n_p, qp, n_q, d, voxels_per_dim, flags, ctypes.byref(r),
+                                 ctypes.byref(nf))
+        self._check(st, "ddks_vdks")
+        return Result._from(r), nf.value
 
     def significance(self, counts, n_p: int, n_q: int, d: int, num: int, *, flags: int = 0):
         if _is_torch(counts) and counts.is_cuda:

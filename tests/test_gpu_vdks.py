@@ -1,0 +1,93 @@
+"""GPU vdKS (Sec. 2.2.2, Alg. 1) against the CPU oracle: the statistic, the
+lowest maximising voxel key and orthant, and the number of filled voxels,
+all exactly (integer results, tolerance 0)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2106_13706_amd import native
+    c = native.Context()
+    yield c
+    c.close()
+
+
+def check(ctx, oracle_mod, P, Q, V, **kw):
+    print(f"  vdks n=({len(P)},{len(Q)}) d={P.shape[1]} V={V}", flush=True)
+    r, nf = ctx.vdks(P, Q, V, **kw)
+    o = oracle_mod.vdks(P, Q, V)
+    assert (r.num, r.den, r.argmax_origin, r.argmax_orthant, nf) == (
+        o.num, o.den, o.argmax_voxel, o.argmax_orthant, o.n_filled)
+    assert r.D == o.D and r.S == -1.0
+    return r
+
+
+@pytest.mark.parametrize("d", range(1, 9))
+def test_random_all_d(ctx, oracle_mod, d):
+    g = np.random.default_rng(300 + d)
+    for V, n_p, n_q in [(2, 50, 70), (4, 333, 280), (7, 1000, 1200), (64, 900, 100)]:
+        P = g.standard_normal((n_p, d)).astype(np.float32)
+        Q = (g.standard_normal((n_q, d)) * 1.2 + 0.3).astype(np.float32)
+        check(ctx, oracle_mod, P, Q, V)
+
+
+def test_ties_signed_zero_and_constant_dimension(ctx, oracle_mod):
+    g = np.random.default_rng(5)
+    P = np.rint(g.standard_normal((400, 3)) * 2).astype(np.float32)
+    Q = np.rint(g.standard_normal((350, 3)) * 2 + 1).astype(np.float32)
+    P[P == 0] = -0.0
+    P[:, 2] = 1.5
+    Q[:, 2] = 1.5
+    for V in (1, 3, 5, 8):
+        check(ctx, oracle_mod, P, Q, V)
+
+
+def test_lattice_equals_exact(ctx, oracle_mod):
+    g = np.random.default_rng(8)
+    V = 6
+    P = g.integers(0, V, size=(500, 3)).astype(np.float32)
+    Q = g.integers(0, V, size=(450, 3)).astype(np.float32)
+    P[0], P[1] = 0, V - 1
+    r = check(ctx, oracle_mod, P, Q, V)
+    assert r.num == oracle_mod.distance(P, Q).num
+
+
+def test_workload_scale_and_fine_grid(ctx, oracle_mod):
+    """The d = 4, 20000 + 20000 workload on a 16^4 grid, and a grid so fine that
+    most points have a voxel of their own."""
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.gaussian_scale()
+    check(ctx, oracle_mod, P, Q, 16)
+    check(ctx, oracle_mod, P[:3000], Q[:3000], 4096)
+
+
+def test_device_pointers_and_errors(ctx, oracle_mod):
+    import torch
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(9)
+    P = g.standard_normal((700, 5)).astype(np.float32)
+    Q = (g.standard_normal((800, 5)) + 0.2).astype(np.float32)
+    c = native.Context(stream=torch.cuda.current_stream())
+    try:
+        r, nf = c.vdks(torch.from_numpy(P).cuda(), torch.from_numpy(Q).cuda(), 5)
+        o = oracle_mod.vdks(P, Q, 5)
+        assert (r.num, r.argmax_origin, r.argmax_orthant, nf) == (o.num, o.argmax_voxel,
+                                                                  o.argmax_orthant, o.n_filled)
+    finally:
+        c.close()
+    for bad_v in (0, 65536):
+        with pytest.raises(native.DDKSError) as e:
+            ctx.vdks(P, Q, bad_v)
+        assert e.value.status == native.DDKS_E_INVALID_ARG
+    with pytest.raises(native.DDKSError) as e:
+        ctx.vdks(np.zeros((5, 8), np.float32), np.ones((5, 8), np.float32), 300)  # 300^8 > 4e18
+    assert e.value.status == native.DDKS_E_INVALID_ARG
+    bad = P.copy()
+    bad[3, 2] = np.inf
+    with pytest.raises(native.DDKSError) as e:
+        ctx.vdks(bad, Q, 5)
+    assert e.value.status == native.DDKS_E_NONFINITE
+    assert ctx.vdks(P, Q, 5)[0].num == o.num  # the context keeps working
