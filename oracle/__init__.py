@@ -62,6 +62,8 @@ def _load():
     lib.ddks_oracle_vdks.argtypes = [vp, i64, vp, i64, i32, i32, u64p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     lib.ddks_oracle_vdks.restype = ctypes.c_int
+    lib.ddks_oracle_rdks.argtypes = [vp, i64, vp, i64, i32, u64p, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.ddks_oracle_rdks.restype = ctypes.c_int
     lib.ddks_oracle_origin_counts.argtypes = [vp, i64, vp, i64, i32, vp, i64, vp]
     lib.ddks_oracle_origin_counts.restype = ctypes.c_int
     _lib = lib
@@ -216,3 +218,32 @@ def vdks(P, Q, V: int) -> VdksResult:
         raise ValueError(f"oracle vdks failed with status {st}")
     den = n_p * n_q
     return VdksResult(num.value, den, num.value / den, kv.value, jo.value, nf.value)
+
+
+@dataclass
+class RdksResult:
+    num: int
+    den: int
+    D: float
+    argmax_corner: int   # 0 = the origin, m + 1 = the unit point e_m (lowest maximising)
+    per_corner: np.ndarray  # numerator of each corner
+
+
+def rdks(P, Q) -> RdksResult:
+    """rdKS (Alg. 2): the two-sample KS statistic of the distances from each of
+    the d + 1 corners of the normalised space, maximised over the corners."""
+    lib = _load()
+    P, Q = _f32(P), _f32(Q)
+    if P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must have the same dimension")
+    n_p, d = P.shape
+    n_q = Q.shape[0]
+    num = ctypes.c_uint64()
+    corner = ctypes.c_int32()
+    per = np.zeros(d + 1, dtype=np.uint64)
+    st = lib.ddks_oracle_rdks(P.ctypes.data, n_p, Q.ctypes.data, n_q, d, ctypes.byref(num),
+                              ctypes.byref(corner), per.ctypes.data)
+    if st != 0:
+        raise ValueError(f"oracle rdks failed with status {st}")
+    den = n_p * n_q
+    return RdksResult(num.value, den, num.value / den, corner.value, per)
