@@ -128,6 +128,34 @@ def bench_vdks(ctx, torch, dev, reps=5):
     return out
 
 
+def bench_rdks(ctx, torch, dev, reps=5):
+    """rdKS (Alg. 2) with device-resident inputs: the d = 4 workload (with the
+    exact statistic beside it) and 100 + 100 points in 1000 dimensions."""
+    import numpy as np
+    from paper_2106_13706_amd import workloads
+    g = np.random.default_rng(workloads.SEED_BASE + 77)
+    cases = [("gaussian_scale_d4_20000", *workloads.gaussian_scale()),
+             ("diag_vs_uniform_d1000_100",
+              g.standard_normal((100, 1000)).astype(np.float32),
+              g.uniform(-1.7, 1.7, size=(100, 1000)).astype(np.float32))]
+    out = {}
+    for name, P, Q in cases:
+        Pt, Qt = torch.from_numpy(P).to(dev), torch.from_numpy(Q).to(dev)
+        r, _ = ctx.rdks(Pt, Qt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r, _ = ctx.rdks(Pt, Qt)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        entry = {"ms_per_call": sec * 1e3, "corners": P.shape[1] + 1, "D": r.D,
+                 "corner": r.argmax_origin}
+        if P.shape[1] <= 8:
+            entry["exact_D"] = ctx.distance(Pt, Qt).D
+        out[name] = entry
+    return out
+
+
 def bench_batch(ctx, torch, dev, reps=5):
     """Permutation batch (d=5, pooled 2x4096, 1024 relabellings): one call =
     observed split + all relabellings, replayed from a captured graph; against
@@ -344,6 +372,8 @@ def main():
         extras["significance"] = bench_significance(ctx, native, torch, Pt, Qt, workload)
         _log("[bench] extra: vdKS")
         extras["vdks"] = bench_vdks(ctx, torch, dev)
+        _log("[bench] extra: rdKS")
+        extras["rdks"] = bench_rdks(ctx, torch, dev)
         _log("[bench] extra: permutation batch")
         extras["permutation_batch"] = bench_batch(ctx, torch, dev)
         _log(f"[bench] extra: serving ({args.serve_requests} requests)")

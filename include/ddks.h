@@ -175,6 +175,23 @@ int ddks_significance(ddks_ctx *ctx, const uint32_t *counts, int64_t n_p, int64_
 int ddks_vdks(ddks_ctx *ctx, const float *P, int64_t n_p, const float *Q, int64_t n_q, int32_t d,
               int32_t voxels_per_dim, uint32_t flags, ddks_result *out, int64_t *n_filled);
 
+/*
+ * rdKS, the radial approximation of the statistic (Sec. 2.2.3, Alg. 2): the
+ * pooled points normalised per dimension onto [0, 1] as for ddks_vdks; for
+ * each of the d + 1 corners of that space (0 = the origin, m + 1 = the unit
+ * point e_m) the two-sample KS statistic of the samples' squared Euclidean
+ * distances from the corner (fp32, summed over the dimensions in ascending
+ * order, every operation rounded on its own), evaluated at the distinct
+ * distances; out->num / out->den is the largest over the corners and
+ * out->argmax_origin the lowest maximising corner (argmax_orthant 0, S -1).
+ * corner_nums (nullable, host): d + 1 numerators, one per corner.
+ * P, Q as in ddks_distance (host memory unless DDKS_DEVICE_PTRS).
+ * Limits: 1 <= d <= 4096, (n_p + n_q) (d + 1) <= 2^34.
+ * Errors: DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOMEM, DDKS_E_DEVICE.
+ */
+int ddks_rdks(ddks_ctx *ctx, const float *P, int64_t n_p, const float *Q, int64_t n_q, int32_t d,
+              uint32_t flags, ddks_result *out, uint64_t *corner_nums);
+
 /* ---------------------------------------------------------------- serving */
 
 typedef struct ddks_request {

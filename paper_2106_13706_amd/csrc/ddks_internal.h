@@ -142,6 +142,24 @@ hipError_t launch_perm(int path, int d, int pb, const void *Z, int64_t N, int64_
                        const uint64_t *inc, int B, const uint32_t *obs_counts,
                        unsigned long long *nums, hipStream_t s);
 
+// Sorts each column m < C of X (N x C fp32, finite, -0 already +0): the pairs
+// (order-preserving key of X[i][m]) << 32 | i ascending in S[m * N + p],
+// S = *S_out inside scratch (sort_columns_scratch_bytes(N, C) bytes).
+size_t sort_columns_scratch_bytes(int64_t N, int C);
+hipError_t launch_sort_columns(const float *X, int64_t N, int C, void *scratch, uint64_t **S_out,
+                               hipStream_t s);
+
+// ---------------------------------------------------------------- rdKS
+
+// Scratch bytes of launch_rdks for N points in d dimensions.
+size_t rdks_scratch_bytes(int64_t N, int d);
+
+// rdKS of Z (N x d, first n_p rows the first sample, -0 already +0): per
+// corner numerators in corner_num[d + 1], and *out = (the largest, the lowest
+// maximising corner, code 0, *flags), *flags cleared.
+hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scratch,
+                       unsigned long long *corner_num, uint32_t *flags, ResultDev *out, hipStream_t s);
+
 // ---------------------------------------------------------------- vdKS
 
 // Slots of the voxel hash table for N points (a power of two >= 2 N).

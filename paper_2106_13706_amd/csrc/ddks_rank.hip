@@ -328,6 +328,28 @@ size_t rank16_scratch_bytes(int64_t N, int d)
     return a + s + c + 256;
 }
 
+size_t sort_columns_scratch_bytes(int64_t N, int C)
+{
+    return (size_t)C * tiles_of(N) * TILE * sizeof(uint64_t) + (size_t)C * N * sizeof(uint64_t) + 256;
+}
+
+hipError_t launch_sort_columns(const float *X, int64_t N, int C, void *scratch, uint64_t **S_out,
+                               hipStream_t st)
+{
+    if (N < 1 || C < 1 || C > 65535 || N > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int64_t tiles = tiles_of(N);
+    uint64_t *A = (uint64_t *)scratch;
+    uint64_t *S = A + (size_t)C * tiles * TILE;
+    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)tiles, C), dim3(TILE_THREADS), 0, st, X, N, C, tiles,
+                       A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)std::min<int64_t>((tiles * TILE + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_rank_place, dim3(blocks, C), dim3(256), 0, st, A, N, tiles, S);
+    *S_out = S;
+    return hipGetLastError();
+}
+
 hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch, uint32_t *ctl,
                          hipStream_t st)
 {

@@ -40,7 +40,7 @@ EXPORTS = (
     "ddks_default_options", "ddks_create", "ddks_destroy", "ddks_distance",
     "ddks_permutation_batch", "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
     "ddks_serve_stats_get", "ddks_profile_get", "ddks_status_string", "ddks_last_error",
-    "ddks_version", "ddks_vdks",
+    "ddks_version", "ddks_vdks", "ddks_rdks",
 )
 
 
@@ -141,6 +141,7 @@ def load(path: str = LIB_PATH):
     lib.ddks_serve_stats_get.argtypes = [vp, ctypes.POINTER(_ServeStats), i32]
     lib.ddks_vdks.argtypes = [vp, vp, i64, vp, i64, i32, i32, u32, ctypes.POINTER(_Result),
                               ctypes.POINTER(i64)]
+    lib.ddks_rdks.argtypes = [vp, vp, i64, vp, i64, i32, u32, ctypes.POINTER(_Result), vp]
     lib.ddks_profile_get.argtypes = [vp, ctypes.POINTER(_Profile), i32]
     lib.ddks_status_string.argtypes = [ctypes.c_int]
     lib.ddks_status_string.restype = ctypes.c_char_p
@@ -304,6 +305,23 @@ class Context:
                                  ctypes.byref(nf))
         self._check(st, "ddks_vdks")
         return Result._from(r), nf.value
+
+    def rdks(self, P, Q, *, flags: int = 0):
+        """rdKS (Alg. 2) of P and Q: (Result, per-corner numerators[d + 1]);
+        Result.argmax_origin is the lowest maximising corner."""
+        pp, n_p, d, kp, dev_p = _points(P)
+        qp, n_q, dq, kq, dev_q = _points(Q)
+        if d != dq:
+            raise ValueError("P and Q must have the same number of columns")
+        if dev_p != dev_q:
+            raise ValueError("P and Q must both be host arrays or both device tensors")
+        if dev_p:
+            flags |= DDKS_DEVICE_PTRS
+        r = _Result()
+        per = np.zeros(d + 1, dtype=np.uint64)
+        st = self._lib.ddks_rdks(self._h, pp, n_p, qp, n_q, d, flags, ctypes.byref(r), per.ctypes.data)
+        self._check(st, "ddks_rdks")
+        return Result._from(r), per
 
     def significance(self, counts, n_p: int, n_q: int, d: int, num: int, *, flags: int = 0):
         if _is_torch(counts) and counts.is_cuda:
