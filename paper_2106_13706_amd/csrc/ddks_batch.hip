@@ -88,11 +88,11 @@ __global__ void k_zero_u64(uint64_t *p, int64_t n)
         p[i] = 0;
 }
 
-template <int D, int PATH, int PB>
-__global__ __launch_bounds__(64) void k_perm(const void *__restrict__ Zv, int64_t N, int64_t n_p,
-                                             int64_t n_q, const uint64_t *__restrict__ inc, int B,
-                                             const uint32_t *__restrict__ obs_counts,
-                                             unsigned long long *__restrict__ nums)
+template <int D, int PATH, int PB, int W>
+__global__ __launch_bounds__(W * 64) void k_perm(const void *__restrict__ Zv, int64_t N, int64_t n_p,
+                                                 int64_t n_q, const uint64_t *__restrict__ inc, int B,
+                                                 const uint32_t *__restrict__ obs_counts,
+                                                 unsigned long long *__restrict__ nums)
 {
     typedef typename Layout<PATH, D>::T T;
     constexpr int BINS = Geo<D>::BINS;
@@ -103,21 +103,30 @@ __global__ __launch_bounds__(64) void k_perm(const void *__restrict__ Zv, int64_
     constexpr uint32_t SLOT = BINS * 64 * 8;      // bytes of one word-slot over all bins
     extern __shared__ uint64_t smem64[];
     const T *__restrict__ Z = static_cast<const T *>(Zv);
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t group = blockIdx.x;
     const int64_t q = blockIdx.y;
 
-    for (int i = lane; i < NS * BINS * 64; i += 64) smem64[i] = 0;
+    // The W waves share the 64 origins and the counters (each counts points of
+    // a first sample, at most n_p <= 65535) and split the points.
+    for (int i = threadIdx.x; i < NS * BINS * 64; i += W * 64) smem64[i] = 0;
     const int64_t k = group * 64 + lane;
     Origin<PATH, D> org;
     org.load(Z, k < N ? k : N - 1);
     __syncthreads();
+    const int64_t per = (N + W - 1) / W;
+    int64_t i0 = (int64_t)w * per, i1 = i0 + per;
+    i0 = i0 < N ? i0 : N;
+    i1 = i1 < N ? i1 : N;
+    i0 = __builtin_amdgcn_readfirstlane((int)i0);
+    i1 = __builtin_amdgcn_readfirstlane((int)i1);
 
     const uint32_t base = (uint32_t)(uintptr_t)(lds_u64 *)(smem64 + Geo<D>::KOFF * 64 + lane);
     const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
     const uint64_t *__restrict__ incq = inc + q * N * NS;
-    int64_t i = 0;
-    for (; i + U <= N; i += U) {
+    int64_t i = i0;
+    for (; i + U <= i1; i += U) {
         T buf[U * PW];
         uint64_t iv[U * NS];
 #pragma unroll
@@ -139,7 +148,7 @@ __global__ __launch_bounds__(64) void k_perm(const void *__restrict__ Zv, int64_
 #pragma unroll
             for (int s = 0; s < NS; ++s) lds_add64(a[u] + s * SLOT, iv[u * NS + s]);
     }
-    for (; i < N; ++i) {
+    for (; i < i1; ++i) {
         T buf[PW];
 #pragma unroll
         for (int e = 0; e < PW; ++e) buf[e] = Z[i * PW + e];
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(64) void k_perm(const void *__restrict__ Zv, int64_
     uint64_t best[PB];
 #pragma unroll
     for (int t = 0; t < PB; ++t) best[t] = 0;
-    for (int j = 0; j < BINS; ++j) {
+    for (int j = w; j < BINS; j += W) {  // this wave's share of the bins
         const int code = j ^ Geo<D>::FLIP;
         uint32_t call = 0;
         if (valid) {
@@ -213,6 +222,9 @@ hipError_t launch_count_ge(const unsigned long long *nums, int B, ResultDev *res
     return hipGetLastError();
 }
 
+// Waves per block of the permutation kernel (they share one set of counters).
+static constexpr int PERM_WAVES = 4;
+
 size_t perm_lds_bytes(int d, int pb) { return (size_t)(pb / 4) * ((size_t)1 << d) * 64 * 8; }
 
 int perm_max_group(int d)
@@ -252,14 +264,14 @@ static hipError_t launch_perm_t(const void *Z, int64_t N, int64_t n_p, const uin
     const size_t lds = perm_lds_bytes(D, PB);
     static bool attr = false;
     if (!attr && lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void *)k_perm<D, PATH, PB>,
+        if (hipFuncSetAttribute((const void *)k_perm<D, PATH, PB, PERM_WAVES>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             (void)hipGetLastError();
         attr = true;
     }
     dim3 grid((unsigned)((N + 63) / 64), (unsigned)((B + PB - 1) / PB));
-    hipLaunchKernelGGL((k_perm<D, PATH, PB>), grid, dim3(64), lds, s, Z, N, n_p, N - n_p, inc, B,
-                       obs, nums);
+    hipLaunchKernelGGL((k_perm<D, PATH, PB, PERM_WAVES>), grid, dim3(PERM_WAVES * 64), lds, s, Z, N, n_p,
+                       N - n_p, inc, B, obs, nums);
     return hipGetLastError();
 }
 
