@@ -223,7 +223,7 @@ hipError_t launch_count_ge(const unsigned long long *nums, int B, ResultDev *res
 }
 
 // Waves per block of the permutation kernel (they share one set of counters).
-static constexpr int PERM_WAVES = 4;
+static constexpr int PERM_WAVES = 8;
 
 size_t perm_lds_bytes(int d, int pb) { return (size_t)(pb / 4) * ((size_t)1 << d) * 64 * 8; }
 
