@@ -156,6 +156,28 @@ def bench_rdks(ctx, torch, dev, reps=5):
     return out
 
 
+def bench_power(ctx_factory):
+    """Sec. 4.2's power study on the synthetic datasets: the smallest sample
+    size per sample, and the smallest parameter difference at 50 points per
+    sample, at which each statistic's permutation test (100 relabellings)
+    rejects H0 at alpha = 0.05, by bisection."""
+    from paper_2106_13706_amd import power, workloads
+    out = {"alpha": 0.05, "relabellings": 100, "d": 3, "min_n": {}, "min_gap_at_n50": {}}
+    t0 = time.perf_counter()
+    with ctx_factory() as ctx:
+        for method in ("ddks", "vdks", "rdks"):
+            out["min_n"][method] = {}
+            out["min_gap_at_n50"][method] = {}
+            for name in workloads.POWER_DATASETS:
+                n, _ = power.min_sample_size(ctx, name, method=method, n_hi=512)
+                out["min_n"][method][name] = n
+                if workloads.POWER_DEFAULT_DELTA[name] is not None:
+                    gap, _ = power.min_parameter_gap(ctx, name, method=method, n=50)
+                    out["min_gap_at_n50"][method][name] = gap
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def bench_batch(ctx, torch, dev, reps=5):
     """Permutation batch (d=5, pooled 2x4096, 1024 relabellings): one call =
     observed split + all relabellings, replayed from a captured graph; against
@@ -374,6 +396,8 @@ def main():
         extras["vdks"] = bench_vdks(ctx, torch, dev)
         _log("[bench] extra: rdKS")
         extras["rdks"] = bench_rdks(ctx, torch, dev)
+        _log("[bench] extra: power study")
+        extras["power"] = bench_power(lambda: native.Context(flags=native.DDKS_NO_AUTOTUNE))
         _log("[bench] extra: permutation batch")
         extras["permutation_batch"] = bench_batch(ctx, torch, dev)
         _log(f"[bench] extra: serving ({args.serve_requests} requests)")

@@ -157,6 +157,52 @@ def materialize(r: Request):
     return P, Q
 
 
+# ---------------------------------------------------------------- power-study datasets
+# Sec. 4.1's synthetic datasets (LS needs a trained network and images, so it
+# is left out).  The paper gives no parameters; these are the stated ones,
+# with sigma = 1 and the means placed symmetrically about the origin:
+#   GVM   P ~ N(-delta/2 1, I), Q ~ N(+delta/2 1, I)                 (delta 0.5)
+#   GVS   P ~ N(0, I), Q ~ N(0, (1 + delta)^2 I)                      (delta 0.5)
+#   DVU   P uniform on the diagonal from 0 to 1, Q uniform on [0, 1]^d (no parameter)
+#   Skew  P ~ Exp(1)^d, Q ~ Exp(1 + delta)^d (rates)                 (delta 0.5)
+#   MM    GVM with the first round(noise n) points of each sample replaced by
+#         draws uniform on [-3 sigma, 3 sigma]^d                      (delta 0.5, noise 0.5)
+POWER_DATASETS = ("GVM", "GVS", "DVU", "Skew", "MM")
+POWER_DEFAULT_DELTA = {"GVM": 0.5, "GVS": 0.5, "DVU": None, "Skew": 0.5, "MM": 0.5}
+
+
+def power_dataset(name: str, n: int, d: int = 3, delta: float | None = None, noise: float = 0.5,
+                  seed: int = SEED_BASE + 6):
+    """Two samples of n points each from one of the power-study datasets."""
+    g = _rng(seed)
+    if name not in POWER_DEFAULT_DELTA:
+        raise ValueError(f"unknown dataset {name}")
+    delta = POWER_DEFAULT_DELTA[name] if delta is None else delta
+    if name == "GVM" or name == "MM":
+        P = g.standard_normal((n, d)) - delta / 2
+        Q = g.standard_normal((n, d)) + delta / 2
+        if name == "MM":
+            k = int(round(noise * n))
+            for X in (P, Q):
+                X[:k] = g.uniform(-3.0, 3.0, size=(k, d))
+    elif name == "GVS":
+        P = g.standard_normal((n, d))
+        Q = g.standard_normal((n, d)) * (1.0 + delta)
+    elif name == "DVU":
+        t = g.uniform(0.0, 1.0, size=(n, 1))
+        P = np.repeat(t, d, axis=1)
+        Q = g.uniform(0.0, 1.0, size=(n, d))
+    else:  # Skew
+        P = g.exponential(1.0, size=(n, d))
+        Q = g.exponential(1.0 / (1.0 + delta), size=(n, d))
+    return P.astype(np.float32), Q.astype(np.float32)
+
+
+def relabel_rows(n_total: int, n_p: int, B: int, seed: int) -> np.ndarray:
+    """B seeded relabellings of a pooled sample (label_rows with its own seed)."""
+    return label_rows(n_total, n_p, B, seed)
+
+
 # The five workloads by name, as (callable, description).
 WORKLOADS = {
     "gaussian_shift_d3_500": (gaussian_shift,
