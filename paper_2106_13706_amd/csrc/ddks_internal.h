@@ -170,9 +170,11 @@ size_t vdks_best_bytes(int64_t M);
 // Per-dimension extent of Z (N x d, -0 already mapped to +0), each point's
 // voxel key sum_m v_m V^m merged into the table (slots entries: keys, then 2
 // counts each), and the filled voxels compacted into keys[] and inc[]
-// (c_P | c_Q << 32), their number in *counter.  mm: 2 d words of scratch.
+// (c_P | c_Q << 32), their number in *counter.  mm: 2 d words of scratch;
+// part: VOX_EXTENT_ROWS x 2 d words of scratch (per-block extents).
+constexpr int VOX_EXTENT_ROWS = 256;
 hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V, uint32_t *mm,
-                            uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots, uint32_t *counter,
+                            uint32_t *part, uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots, uint32_t *counter,
                             uint64_t *keys, uint64_t *inc, hipStream_t s);
 
 // The weighted sweep over the M filled voxels (R: M x point_words(R16, d)

@@ -18,7 +18,8 @@
 //                     tiles: the number of pooled values below it, which fits
 //                     16 bits since N <= 65536.
 // N > 65536:
-//   1. k_rank_tiles   sorts tiles of (key, index) pairs in LDS (bitonic);
+//   1. k_rank_tiles   sorts tiles of (key, index) pairs (bitonic, in
+//                     registers, wave shuffles and LDS);
 //   2. k_rank_place   places each pair at its sorted position,
 //      k_rank_flags   counts first occurrences per segment,
 //      k_rank_dense   dense rank = number of distinct values below, from the
@@ -34,7 +35,6 @@
 namespace ddks {
 
 static constexpr int TILE = 4096;      // pairs per sorted tile (32 KB of LDS)
-static constexpr int TILE_THREADS = 1024;
 static constexpr int SEG = 4096;       // positions per flag segment
 static constexpr int SEG_THREADS = 1024;
 
@@ -173,35 +173,83 @@ __global__ void k_rank_sum(const uint16_t *__restrict__ part, int64_t N, int d, 
 
 // ------------------------------------------------------------ N > 65536
 
-__global__ __launch_bounds__(TILE_THREADS) void k_rank_tiles(const float *__restrict__ Z, int64_t N,
-                                                             int d, int64_t tiles,
-                                                             uint64_t *__restrict__ A)
+// Sorts (order key << 32 | index) pairs of column m = blockIdx.y, tile t =
+// blockIdx.x, T = 256, 1024 or 4096 pairs per tile (~0 past N).  The same
+// fully unrolled bitonic network as k_rank_sort32 on 64-bit pairs: a thread
+// holds four pairs, partners within a wave go through shuffles and only the
+// stages across waves (T > 256) through double-buffered LDS.  Single-tile
+// sorts (T >= N) write the N sorted pairs straight to S + m * N; otherwise
+// the tile goes to A + (m * tiles + t) * T.
+struct Pair4 {
+    uint64_t v[4];
+};
+
+template <int T>
+__global__ __launch_bounds__(T / 4) void k_rank_tiles(const float *__restrict__ Z, int64_t N, int d,
+                                                      int64_t tiles, uint64_t *__restrict__ A,
+                                                      uint64_t *__restrict__ S)
 {
-    __shared__ uint64_t s[TILE];
+    constexpr int THREADS = T / 4;
+    constexpr int LOG_T = T == 256 ? 8 : (T == 1024 ? 10 : 12);
+    static_assert(T == 256 || T == 1024 || T == 4096, "tile sizes");
+    __shared__ Pair4 buf[2][T > 256 ? THREADS : 1];
     const int m = blockIdx.y;
     const int64_t t = blockIdx.x;
-    for (int e = threadIdx.x; e < TILE; e += TILE_THREADS) {
-        int64_t i = t * TILE + e;
-        s[e] = i < N ? ((uint64_t)order_key(Z[i * d + m]) << 32) | (uint64_t)i : ~0ull;
+    const int tid = threadIdx.x;
+    const int e0 = 4 * tid;
+    uint64_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = t * T + e0 + r;
+        v[r] = i < N ? ((uint64_t)order_key(Z[i * d + m]) << 32) | (uint64_t)i : ~0ull;
     }
-    __syncthreads();
-    for (int k = 2; k <= TILE; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int p = threadIdx.x; p < TILE / 2; p += TILE_THREADS) {
-                int i = 2 * j * (p / j) + (p % j);
-                int l = i + j;
-                bool up = (i & k) == 0;
-                uint64_t a = s[i], b = s[l];
-                if ((a > b) == up) {
-                    s[i] = b;
-                    s[l] = a;
+    int cur = 0;
+#pragma unroll
+    for (int lk = 1; lk <= LOG_T; ++lk) {
+        const int k = 1 << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
+            if (j >= 4) {
+                const bool keep_min = ((e0 & j) == 0) == ((e0 & k) == 0);
+                uint64_t pv[4];
+                if (j >= 256) {
+                    if constexpr (T > 256) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) buf[cur][tid].v[r] = v[r];
+                        __syncthreads();
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) pv[r] = buf[cur][tid ^ (j >> 2)].v[r];
+                        cur ^= 1;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) pv[r] = __shfl_xor(v[r], j >> 2, 64);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = keep_min ? min(v[r], pv[r]) : max(v[r], pv[r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r & j) continue;
+                    const bool up = (((e0 + r) & k) == 0);
+                    const uint64_t lo = min(v[r], v[r | j]), hi = max(v[r], v[r | j]);
+                    v[r] = up ? lo : hi;
+                    v[r | j] = up ? hi : lo;
                 }
             }
-            __syncthreads();
         }
     }
-    uint64_t *out = A + (size_t)m * tiles * TILE + t * TILE;
-    for (int e = threadIdx.x; e < TILE; e += TILE_THREADS) out[e] = s[e];
+    if (S) {
+        uint64_t *out = S + (size_t)m * N;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (e0 + r < N) out[e0 + r] = v[r];
+    } else {
+        uint64_t *out = A + ((size_t)m * tiles + t) * T;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[e0 + r] = v[r];
+    }
 }
 
 // Number of entries of the sorted tile below v.
@@ -340,8 +388,18 @@ hipError_t launch_sort_columns(const float *X, int64_t N, int C, void *scratch, 
     const int64_t tiles = tiles_of(N);
     uint64_t *A = (uint64_t *)scratch;
     uint64_t *S = A + (size_t)C * tiles * TILE;
-    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)tiles, C), dim3(TILE_THREADS), 0, st, X, N, C, tiles,
-                       A);
+    if (tiles == 1) {  // one tile: the sorted tile is the sorted column
+        if (N <= 256)
+            hipLaunchKernelGGL(k_rank_tiles<256>, dim3(1, C), dim3(64), 0, st, X, N, C, tiles, A, S);
+        else if (N <= 1024)
+            hipLaunchKernelGGL(k_rank_tiles<1024>, dim3(1, C), dim3(256), 0, st, X, N, C, tiles, A, S);
+        else
+            hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3(1, C), dim3(TILE / 4), 0, st, X, N, C, tiles, A, S);
+        *S_out = S;
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3((unsigned)tiles, C), dim3(TILE / 4), 0, st, X, N, C, tiles,
+                       A, (uint64_t *)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)std::min<int64_t>((tiles * TILE + 255) / 256, 4096);
@@ -371,8 +429,8 @@ hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *sc
         return hipGetLastError();
     }
     uint64_t *A = (uint64_t *)scratch;
-    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)tiles, d), dim3(TILE_THREADS), 0, st, Z, N, d,
-                       tiles, A);
+    hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3((unsigned)tiles, d), dim3(TILE / 4), 0, st, Z, N, d,
+                       tiles, A, (uint64_t *)nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t items = tiles * TILE;
     unsigned blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 4096);

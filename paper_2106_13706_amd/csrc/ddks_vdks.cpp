@@ -32,7 +32,8 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     const size_t r16 = (size_t)N * point_words(PATH_R16, d) * sizeof(uint32_t);
     const size_t best = vdks_best_bytes(N);
     int st = ensure(c, c->z, pts, "points");
-    if (!st) st = ensure(c, c->vox, table + list + 128, "voxel table");  // + counter and extents
+    const size_t extents = 128 + (size_t)VOX_EXTENT_ROWS * 2 * d * sizeof(uint32_t);
+    if (!st) st = ensure(c, c->vox, table + list + extents, "voxel table");  // + counter and extents
     if (!st) st = ensure(c, c->zr, r16, "voxel encoding");
     if (!st) st = ensure(c, c->block_best, best, "block results");
     if (st) return st;
@@ -42,7 +43,8 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     uint64_t *keys = (uint64_t *)(tab_cnt + 2 * slots);
     uint64_t *inc = keys + N;
     uint32_t *counter = (uint32_t *)(inc + N);
-    uint32_t *mm = counter + 4;  // 2 d words
+    uint32_t *mm = counter + 4;     // 2 d words
+    uint32_t *part = counter + 32;  // VOX_EXTENT_ROWS x 2 d words
 
     const float *srcP = P, *srcQ = Q;
     if (!dev) {
@@ -53,7 +55,7 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
         srcQ = Z + n_p * d;
     }
     st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
-    if (!st) st = hip_check(c, launch_vox_front(Z, N, n_p, d, V, mm, tab_key, tab_cnt, slots, counter, keys,
+    if (!st) st = hip_check(c, launch_vox_front(Z, N, n_p, d, V, mm, part, tab_key, tab_cnt, slots, counter, keys,
                                                 inc, s), "voxel launch");
     // the number of filled voxels sizes the sweep
     if (!st) st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, counter, sizeof(uint32_t),

@@ -60,10 +60,15 @@ __global__ void k_vox_init(uint32_t *__restrict__ mm, int d, uint64_t *__restric
     if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
 }
 
+// Per-dimension extents in two steps, with no atomics (thousands of waves
+// updating the same few words serialise): every block writes the minimum and
+// maximum order keys of its share of the points to part[block][2 D], then one
+// block combines the rows into mm.
 template <int D>
 __global__ __launch_bounds__(256) void k_vox_minmax(const float *__restrict__ Z, int64_t N,
-                                                    uint32_t *__restrict__ mm)
+                                                    uint32_t *__restrict__ part)
 {
+    __shared__ uint32_t red[4][2 * D];
     uint32_t lo[D], hi[D];
 #pragma unroll
     for (int m = 0; m < D; ++m) {
@@ -79,6 +84,7 @@ __global__ __launch_bounds__(256) void k_vox_minmax(const float *__restrict__ Z,
             hi[m] = max(hi[m], k);
         }
     }
+    const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int m = 0; m < D; ++m) {
         for (int off = 32; off >= 1; off >>= 1) {
@@ -86,9 +92,42 @@ __global__ __launch_bounds__(256) void k_vox_minmax(const float *__restrict__ Z,
             hi[m] = max(hi[m], (uint32_t)__shfl_xor((int)hi[m], off, 64));
         }
         if ((threadIdx.x & 63) == 0) {
-            atomicMin(&mm[2 * m], lo[m]);
-            atomicMax(&mm[2 * m + 1], hi[m]);
+            red[w][2 * m] = lo[m];
+            red[w][2 * m + 1] = hi[m];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * D) {
+        const int j = threadIdx.x;
+        uint32_t v = red[0][j];
+        for (int x = 1; x < 4; ++x) v = (j & 1) ? max(v, red[x][j]) : min(v, red[x][j]);
+        part[(size_t)blockIdx.x * (2 * D) + j] = v;
+    }
+}
+
+// mm[2 m] / mm[2 m + 1] = smallest / largest order key of dimension m over
+// the rows part[0 .. rows) (one block of 256 threads, rows <= 256).
+template <int D>
+__global__ __launch_bounds__(256) void k_vox_minmax_final(const uint32_t *__restrict__ part, int rows,
+                                                          uint32_t *__restrict__ mm)
+{
+    __shared__ uint32_t red[4][2 * D];
+    const int r = threadIdx.x, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 2 * D; ++j) {
+        uint32_t v = r < rows ? part[(size_t)r * (2 * D) + j] : ((j & 1) ? 0u : 0xffffffffu);
+        for (int off = 32; off >= 1; off >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)v, off, 64);
+            v = (j & 1) ? max(v, o) : min(v, o);
+        }
+        if ((threadIdx.x & 63) == 0) red[w][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * D) {
+        const int j = threadIdx.x;
+        uint32_t v = red[0][j];
+        for (int x = 1; x < 4; ++x) v = (j & 1) ? max(v, red[x][j]) : min(v, red[x][j]);
+        mm[j] = v;
     }
 }
 
@@ -383,12 +422,14 @@ size_t vdks_table_slots(int64_t N)
 
 template <int D>
 static hipError_t launch_vox_front_d(const float *Z, int64_t N, int64_t n_p, int V, uint32_t *mm,
-                                     uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots,
+                                     uint32_t *part, uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots,
                                      uint32_t *counter, uint64_t *keys, uint64_t *inc, hipStream_t s)
 {
     hipLaunchKernelGGL(k_vox_init, dim3(grid_for(slots)), dim3(256), 0, s, mm, D, tab_key, tab_cnt,
                        slots, counter);
-    hipLaunchKernelGGL(k_vox_minmax<D>, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s, Z, N, mm);
+    const unsigned rows = grid_for(N, 256, VOX_EXTENT_ROWS);
+    hipLaunchKernelGGL(k_vox_minmax<D>, dim3(rows), dim3(256), 0, s, Z, N, part);
+    hipLaunchKernelGGL(k_vox_minmax_final<D>, dim3(1), dim3(256), 0, s, part, (int)rows, mm);
     hipLaunchKernelGGL(k_vox_insert<D>, dim3(grid_for(N)), dim3(256), 0, s, Z, N, n_p, V, mm, tab_key,
                        tab_cnt, (uint64_t)(slots - 1));
     hipLaunchKernelGGL(k_vox_compact, dim3(grid_for(slots)), dim3(256), 0, s, tab_key, tab_cnt, slots,
@@ -397,13 +438,13 @@ static hipError_t launch_vox_front_d(const float *Z, int64_t N, int64_t n_p, int
 }
 
 hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V, uint32_t *mm,
-                            uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots, uint32_t *counter,
+                            uint32_t *part, uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots, uint32_t *counter,
                             uint64_t *keys, uint64_t *inc, hipStream_t s)
 {
     if (slots < 2 * N || (slots & (slots - 1))) return hipErrorInvalidValue;
     switch (d) {
 #define DDKS_VF(DD) \
-    case DD: return launch_vox_front_d<DD>(Z, N, n_p, V, mm, tab_key, tab_cnt, slots, counter, keys, inc, s);
+    case DD: return launch_vox_front_d<DD>(Z, N, n_p, V, mm, part, tab_key, tab_cnt, slots, counter, keys, inc, s);
         DDKS_VF(1) DDKS_VF(2) DDKS_VF(3) DDKS_VF(4) DDKS_VF(5) DDKS_VF(6) DDKS_VF(7) DDKS_VF(8)
 #undef DDKS_VF
     default: return hipErrorInvalidValue;

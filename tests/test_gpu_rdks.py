@@ -54,6 +54,17 @@ def test_many_tiles_and_segments(ctx, oracle_mod, n_p, n_q, d):
     check(ctx, oracle_mod, P, Q)
 
 
+@pytest.mark.parametrize("N", [64, 255, 256, 257, 1023, 1024, 1025, 3500, 4095, 4096, 4097, 8192])
+def test_sort_tile_boundaries(ctx, oracle_mod, N):
+    """Column sorts of one 256-, 1024- or 4096-pair tile (written straight to
+    the sorted columns) and of several tiles, around each size limit, with
+    ties (values on a coarse grid)."""
+    g = np.random.default_rng(N)
+    n_p = N // 3 + 1
+    Z = (np.rint(g.standard_normal((N, 3)) * 8) / 8).astype(np.float32)
+    check(ctx, oracle_mod, Z[:n_p], Z[n_p:])
+
+
 def test_high_dimension(ctx, oracle_mod):
     """The paper's latent-space case: 100 points per sample in 1000 dimensions."""
     g = np.random.default_rng(1000)
