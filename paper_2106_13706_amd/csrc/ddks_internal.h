@@ -178,10 +178,12 @@ hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V
                             uint64_t *keys, uint64_t *inc, hipStream_t s);
 
 // The weighted sweep over the M filled voxels (R: M x point_words(R16, d)
-// scratch, bb: vdks_best_bytes(M)); *out = (num, lowest maximising voxel key,
+// scratch, bb: vdks_best_bytes(M), partial: vsweep_partial_bytes(M, d) of
+// scratch, null when that is 0); *out = (num, lowest maximising voxel key,
 // its lowest code, *flags), *flags cleared.
+size_t vsweep_partial_bytes(int64_t M, int d);
 hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
-                         int64_t n_q, uint32_t *R, void *bb, uint32_t *flags, ResultDev *out,
+                         int64_t n_q, uint32_t *R, void *bb, void *partial, uint32_t *flags, ResultDev *out,
                          hipStream_t s);
 
 // ---------------------------------------------------------------- significance

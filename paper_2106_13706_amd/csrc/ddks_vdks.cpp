@@ -64,8 +64,11 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     if (st) return st;
     const int64_t M = *c->rank_distinct_host;
     if (M < 1 || M > N) return fail(c, DDKS_E_DEVICE, "voxel compaction produced an invalid count");
+    const size_t pb = vsweep_partial_bytes(M, d);
+    if (pb && (st = ensure(c, c->partial, pb, "voxel partial counts"))) return st;
     st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, (uint32_t *)c->zr.ptr, c->block_best.ptr,
-                                    c->flags_dev, c->result_host, s), "voxel sweep launch");
+                                    pb ? c->partial.ptr : nullptr, c->flags_dev, c->result_host, s),
+                   "voxel sweep launch");
     if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
     if (st) return st;
     const ResultDev r = *c->result_host;

@@ -228,14 +228,90 @@ __device__ __forceinline__ bool vbetter(uint64_t an, uint64_t ak, int32_t ac, ui
     return ac < bc;
 }
 
-// Block (group): the 64 filled voxels group*64 + lane as origins, every filled
-// voxel as a weighted point, split over the W waves, one shared histogram of
-// 64-bit bins (lane-minor: bin*64 + lane).
+// Scores the 64 origins of a group from their lane-minor 64-bit counts cnt
+// (bin*64 + lane; LDS or global) and writes the group's best (largest
+// numerator, then lowest voxel key, then lowest code) to bb[group].  red: LDS
+// of W * 64 * 12 bytes, which may alias cnt (it is written only after every
+// wave has read its bins).
+template <int D, int W>
+__device__ __forceinline__ void vfinish(const uint64_t *cnt, uint64_t *red, const uint64_t *__restrict__ keys,
+                                        int64_t M, int64_t n_p, int64_t n_q, int64_t group,
+                                        VBest *__restrict__ bb)
+{
+    constexpr int BINS = Geo<D>::BINS;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t k = group * 64 + lane;
+    const bool valid = k < M;
+    uint64_t best = 0;
+    int32_t bcode = 0x7fffffff;
+    if (valid) {
+        for (int j = w; j < BINS; j += W) {  // this wave's share of the bins
+            const uint64_t c = cnt[j * 64 + lane];
+            const int64_t cp = (int64_t)(uint32_t)c, cq = (int64_t)(c >> 32);
+            const int64_t sd = cp * n_q - cq * n_p;
+            const uint64_t s = (uint64_t)(sd < 0 ? -sd : sd);
+            const int32_t code = j ^ Geo<D>::FLIP;
+            if (s > best || (s == best && code < bcode)) {
+                best = s;
+                bcode = code;
+            }
+        }
+    }
+    __syncthreads();
+    uint64_t *sn = red;
+    int32_t *sc = reinterpret_cast<int32_t *>(red + W * 64);
+    sn[w * 64 + lane] = best;
+    sc[w * 64 + lane] = bcode;
+    __syncthreads();
+    if (w == 0) {
+        for (int v = 1; v < W; ++v) {
+            const uint64_t n2 = sn[v * 64 + lane];
+            const int32_t c2 = sc[v * 64 + lane];
+            if (n2 > best || (n2 == best && c2 < bcode)) {
+                best = n2;
+                bcode = c2;
+            }
+        }
+        uint64_t key = valid ? keys[k] : VOX_EMPTY;
+        if (!valid) {
+            best = 0;
+            bcode = 0x7fffffff;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const uint64_t n2 = __shfl_xor(best, off, 64);
+            const uint64_t k2 = __shfl_xor(key, off, 64);
+            const int32_t c2 = __shfl_xor(bcode, off, 64);
+            if (vbetter(n2, k2, c2, best, key, bcode)) {
+                best = n2;
+                key = k2;
+                bcode = c2;
+            }
+        }
+        if (lane == 0) {
+            VBest r;
+            r.num = best;
+            r.key = key;
+            r.code = bcode;
+            r.pad = 0;
+            bb[group] = r;
+        }
+    }
+}
+
+// Block (group, chunk): the 64 filled voxels group*64 + lane as origins, the
+// filled voxels of chunk blockIdx.y (of gridDim.y) as weighted points, split
+// over the W waves, one shared histogram of 64-bit bins (lane-minor:
+// bin*64 + lane).  With one chunk the block scores its origins itself;
+// otherwise it adds its counts into G[group][BINS][64] (zeroed beforehand)
+// and k_vscore scores them.
 template <int D, int W>
 __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ R,
                                                    const uint64_t *__restrict__ inc,
                                                    const uint64_t *__restrict__ keys, int64_t M,
-                                                   int64_t n_p, int64_t n_q, VBest *__restrict__ bb)
+                                                   int64_t n_p, int64_t n_q, unsigned long long *__restrict__ G,
+                                                   VBest *__restrict__ bb)
 {
     constexpr int BINS = Geo<D>::BINS;
     constexpr int PW = Layout<PATH_R16, D>::PW;
@@ -252,10 +328,11 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
     org.load(R, k < M ? k : M - 1);
     __syncthreads();
 
-    const int64_t per = (M + W - 1) / W;
-    int64_t a = (int64_t)w * per, b = a + per;
-    a = a < M ? a : M;
-    b = b < M ? b : M;
+    const int64_t c0 = M * (int64_t)blockIdx.y / gridDim.y, c1 = M * ((int64_t)blockIdx.y + 1) / gridDim.y;
+    const int64_t per = (c1 - c0 + W - 1) / W;
+    int64_t a = c0 + (int64_t)w * per, b = a + per;
+    a = a < c1 ? a : c1;
+    b = b < c1 ? b : c1;
     a = __builtin_amdgcn_readfirstlane((int)a);
     b = __builtin_amdgcn_readfirstlane((int)b);
 
@@ -296,64 +373,34 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
+    if (gridDim.y > 1) {
+        unsigned long long *g = G + (size_t)group * BINS * 64;
+        for (int e = threadIdx.x; e < BINS * 64; e += W * 64) {
+            const uint64_t v = h64[e];
+            if (v) atomicAdd(g + e, (unsigned long long)v);
+        }
+        return;
+    }
+    vfinish<D, W>(h64, h64, keys, M, n_p, n_q, group, bb);
+}
 
-    // scores of this lane's origin over the bins j = w, w + W, ...
-    const bool valid = k < M;
-    uint64_t best = 0;
-    int32_t bcode = 0x7fffffff;
-    if (valid) {
-        for (int j = w; j < BINS; j += W) {
-            const uint64_t c = h64[j * 64 + lane];
-            const int64_t cp = (int64_t)(uint32_t)c, cq = (int64_t)(c >> 32);
-            const int64_t sd = cp * n_q - cq * n_p;
-            const uint64_t s = (uint64_t)(sd < 0 ? -sd : sd);
-            const int32_t code = j ^ Geo<D>::FLIP;
-            if (s > best || (s == best && code < bcode)) {
-                best = s;
-                bcode = code;
-            }
-        }
-    }
-    __syncthreads();  // the histogram has been read; its LDS is reused below
-    uint64_t *sn = h64;
-    int32_t *sc = reinterpret_cast<int32_t *>(h64 + W * 64);
-    sn[w * 64 + lane] = best;
-    sc[w * 64 + lane] = bcode;
-    __syncthreads();
-    if (w == 0) {
-        for (int v = 1; v < W; ++v) {
-            const uint64_t n2 = sn[v * 64 + lane];
-            const int32_t c2 = sc[v * 64 + lane];
-            if (n2 > best || (n2 == best && c2 < bcode)) {
-                best = n2;
-                bcode = c2;
-            }
-        }
-        uint64_t key = valid ? keys[k] : VOX_EMPTY;
-        if (!valid) {
-            best = 0;
-            bcode = 0x7fffffff;
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const uint64_t n2 = __shfl_xor(best, off, 64);
-            const uint64_t k2 = __shfl_xor(key, off, 64);
-            const int32_t c2 = __shfl_xor(bcode, off, 64);
-            if (vbetter(n2, k2, c2, best, key, bcode)) {
-                best = n2;
-                key = k2;
-                bcode = c2;
-            }
-        }
-        if (lane == 0) {
-            VBest r;
-            r.num = best;
-            r.key = key;
-            r.code = bcode;
-            r.pad = 0;
-            bb[group] = r;
-        }
-    }
+// Scores group blockIdx.x from the counts the chunks added into G.
+template <int D, int W>
+__global__ __launch_bounds__(W * 64) void k_vscore(const unsigned long long *__restrict__ G,
+                                                   const uint64_t *__restrict__ keys, int64_t M,
+                                                   int64_t n_p, int64_t n_q, VBest *__restrict__ bb)
+{
+    __shared__ uint64_t red[W * 64 * 12 / 8];
+    const int64_t group = blockIdx.x;
+    vfinish<D, W>(reinterpret_cast<const uint64_t *>(G) + (size_t)group * Geo<D>::BINS * 64, red, keys, M,
+                  n_p, n_q, group, bb);
+}
+
+__global__ void k_vzero(unsigned long long *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 __global__ __launch_bounds__(1024) void k_vreduce(const VBest *__restrict__ bb, int64_t n,
@@ -460,10 +507,27 @@ size_t vsweep_lds_bytes(int d)
     return std::max(hist, fin);
 }
 
+// Point chunks of the weighted sweep: enough blocks to fill the chip (about
+// four per CU) when the filled voxels are few, each chunk at least 512 points.
+int vsweep_chunks(int64_t M)
+{
+    const int64_t groups = (M + 63) / 64;
+    if (groups >= 1024) return 1;
+    int64_t c = (1024 + groups - 1) / groups;
+    c = std::min<int64_t>(c, std::max<int64_t>(1, M / 512));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(c, 16));
+}
+
+size_t vsweep_partial_bytes(int64_t M, int d)
+{
+    if (vsweep_chunks(M) == 1) return 0;
+    return (size_t)((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint64_t);
+}
+
 template <int D>
 static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int64_t M, int V,
-                                  int64_t n_p, int64_t n_q, uint32_t *R, void *bb, uint32_t *flags,
-                                  ResultDev *out, hipStream_t s)
+                                  int64_t n_p, int64_t n_q, uint32_t *R, void *bb, void *partial,
+                                  uint32_t *flags, ResultDev *out, hipStream_t s)
 {
     constexpr int W = VSWEEP_WAVES;
     hipLaunchKernelGGL(k_vox_encode<D>, dim3(grid_for(M)), dim3(256), 0, s, keys, M, V, R);
@@ -476,8 +540,18 @@ static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int
         attr = true;
     }
     const int64_t groups = (M + 63) / 64;
-    hipLaunchKernelGGL((k_vsweep<D, W>), dim3((unsigned)groups), dim3(W * 64), lds, s, R, inc, keys, M,
-                       n_p, n_q, (VBest *)bb);
+    const int chunks = vsweep_chunks(M);
+    unsigned long long *G = (unsigned long long *)partial;
+    if (chunks > 1) {
+        if (!G) return hipErrorInvalidValue;
+        const int64_t n = groups * Geo<D>::BINS * 64;
+        hipLaunchKernelGGL(k_vzero, dim3(grid_for(n)), dim3(256), 0, s, G, n);
+    }
+    hipLaunchKernelGGL((k_vsweep<D, W>), dim3((unsigned)groups, (unsigned)chunks), dim3(W * 64), lds, s, R,
+                       inc, keys, M, n_p, n_q, G, (VBest *)bb);
+    if (chunks > 1)
+        hipLaunchKernelGGL((k_vscore<D, W>), dim3((unsigned)groups), dim3(W * 64), 0, s, G, keys, M, n_p,
+                           n_q, (VBest *)bb);
     hipLaunchKernelGGL(k_vreduce, dim3(1), dim3(1024), 0, s, (const VBest *)bb, groups, flags, out);
     return hipGetLastError();
 }
@@ -485,12 +559,12 @@ static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int
 size_t vdks_best_bytes(int64_t M) { return (size_t)((M + 63) / 64) * sizeof(VBest); }
 
 hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
-                         int64_t n_q, uint32_t *R, void *bb, uint32_t *flags, ResultDev *out,
+                         int64_t n_q, uint32_t *R, void *bb, void *partial, uint32_t *flags, ResultDev *out,
                          hipStream_t s)
 {
     if (M < 1 || M > 0x7fffffff) return hipErrorInvalidValue;
     switch (d) {
-#define DDKS_VS(DD) case DD: return launch_vsweep_d<DD>(keys, inc, M, V, n_p, n_q, R, bb, flags, out, s);
+#define DDKS_VS(DD) case DD: return launch_vsweep_d<DD>(keys, inc, M, V, n_p, n_q, R, bb, partial, flags, out, s);
         DDKS_VS(1) DDKS_VS(2) DDKS_VS(3) DDKS_VS(4) DDKS_VS(5) DDKS_VS(6) DDKS_VS(7) DDKS_VS(8)
 #undef DDKS_VS
     default: return hipErrorInvalidValue;
