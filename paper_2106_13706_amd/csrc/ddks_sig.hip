@@ -157,24 +157,196 @@ __device__ double block_sum(double v, double *sh)
     return r;
 }
 
+// One sample's side of a tail: n trials, pmf parameters, summation window [lo, hi].
+struct SigSide {
+    int64_t n, lo, hi;
+    double lmu, mu;
+};
+
+template <int MODEL>
+__device__ __forceinline__ double pmf(const double *L, const SigSide &s, int64_t k, double ll, double l1m)
+{
+    return exp(log_pmf<MODEL>(L, s.n, k, ll, l1m, s.lmu, s.mu));
+}
+
+// sum of the pmf of side s over [k0, k1), one wave.
+template <int MODEL>
+__device__ double range_sum(const double *L, const SigSide &s, int64_t k0, int64_t k1, double ll, double l1m)
+{
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+    for (int64_t k = k0 + lane; k < k1; k += 64) v += pmf<MODEL>(L, s, k, ll, l1m);
+    return wave_sum(v);
+}
+
+__device__ __forceinline__ double wave_excl_prefix(double v)  // sum over lanes below
+{
+    const double incl = wave_scan(v);
+    const double e = __shfl_up(incl, 1, 64);
+    return (threadIdx.x & 63) ? e : 0.0;
+}
+
+__device__ __forceinline__ double wave_excl_suffix(double v)  // sum over lanes above
+{
+    const int lane = threadIdx.x & 63;
+    const double r = wave_scan(__shfl(v, 63 - lane, 64));  // prefix over reversed lanes
+    const double e = __shfl(r, (62 - lane) & 63, 64);
+    return lane < 63 ? e : 0.0;
+}
+
+// (q, r) with x = q n + r, 0 <= r < n (n > 0).
+struct QR {
+    int64_t q, r;
+};
+__device__ __forceinline__ QR divmod_floor(int64_t x, int64_t n)
+{
+    int64_t q = floor_div(x, n);
+    return QR{q, x - q * n};
+}
+__device__ __forceinline__ void qr_add(QR &v, const QR &d, int64_t n)
+{
+    v.q += d.q;
+    v.r += d.r;
+    if (v.r >= n) {
+        v.r -= n;
+        v.q += 1;
+    }
+}
+__device__ __forceinline__ void qr_sub(QR &v, const QR &d, int64_t n)
+{
+    v.q -= d.q;
+    v.r -= d.r;
+    if (v.r < 0) {
+        v.r += n;
+        v.q -= 1;
+    }
+}
+
+// tail = sum over the outer count o in [O.lo, O.hi] of pmf_O(o) times the
+// inner mass outside the admissible window of o, |o I.n - i O.n| <= num,
+// i.e. i in [lo(o), hi(o)] with lo(o) = ceil((o I.n - num)/O.n) and
+// hi(o) = floor((o I.n + num)/O.n), both nondecreasing in o.  The inner mass
+// below lo(o) and the mass above hi(o) are summed in two passes (ascending and
+// descending o), so that neither is a difference of probabilities.  Lane l of
+// a chunk owns the R consecutive outer counts o = O0 + l R + r; it sums the
+// inner pmf over its own span of targets, and one wave scan per chunk adds the
+// spans of the lanes below it (above it, in the descending pass).  An o with
+// no admissible i counts its whole inner mass (inner_tot) once.
+template <int MODEL, int R>
+__device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide &I, int64_t num, double ll,
+                                double l1m)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int64_t SPAN = 64 * R;
+    const QR step = divmod_floor(I.n, O.n);           // x and y grow by I.n per outer count
+    const QR cstep = divmod_floor(SPAN * I.n, O.n);   // ... and by SPAN I.n per chunk
+    auto lo_of = [&](const QR &x) { return x.q + (x.r > 0 ? 1 : 0); };
+    auto tgt_lo = [&](int64_t lo) { return lo < I.lo ? I.lo : (lo > I.hi + 1 ? I.hi + 1 : lo); };
+    auto tgt_hi = [&](int64_t hi) { return hi + 1 < I.lo ? I.lo : (hi + 1 > I.hi + 1 ? I.hi + 1 : hi + 1); };
+    const QR xtop = divmod_floor(O.hi * I.n - num, O.n), ytop = divmod_floor(O.hi * I.n + num, O.n);
+    const int64_t T_top = tgt_lo(lo_of(xtop)), U_top = tgt_hi(ytop.q);
+    const int64_t nch = (O.hi - O.lo + SPAN) / SPAN;
+
+    double acc_tail = 0.0, p_empty = 0.0;
+    // ---- ascending pass: mass below lo(o)
+    {
+        const int64_t o0 = O.lo + lane * R;
+        QR x = divmod_floor(o0 * I.n - num, O.n), y = divmod_floor(o0 * I.n + num, O.n);
+        double carry = range_sum<MODEL>(L, I, I.lo, tgt_lo(lo_of(divmod_floor(O.lo * I.n - num, O.n))), ll, l1m);
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t of = O.lo + c * SPAN + lane * R;
+            int64_t T[R + 1];
+            bool empty[R];
+            QR xs = x, ys = y;
+#pragma unroll
+            for (int r = 0; r <= R; ++r) {
+                const int64_t o = of + r;
+                const int64_t lo = lo_of(xs), hi = ys.q;
+                T[r] = o <= O.hi ? tgt_lo(lo) : T_top;
+                if (r < R) empty[r] = (lo < 0 ? 0 : lo) > (hi > I.n ? I.n : hi);
+                qr_add(xs, step, O.n);
+                qr_add(ys, step, O.n);
+            }
+            double part[R], acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                part[r] = acc;
+                for (int64_t i = T[r]; i < T[r + 1]; ++i) acc += pmf<MODEL>(L, I, i, ll, l1m);
+            }
+            const double pre = wave_excl_prefix(acc);
+            const double tot = wave_sum(acc);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t o = of + r;
+                if (o <= O.hi) {
+                    const double po = pmf<MODEL>(L, O, o, ll, l1m);
+                    if (empty[r])
+                        p_empty += po;
+                    else
+                        acc_tail += po * (carry + pre + part[r]);
+                }
+            }
+            carry += tot;
+            qr_add(x, cstep, O.n);
+            qr_add(y, cstep, O.n);
+        }
+        double inner_tot = 1.0;  // the whole binomial mass
+        if constexpr (MODEL == SIG_POISSON) inner_tot = carry + range_sum<MODEL>(L, I, T_top, I.hi + 1, ll, l1m);
+        acc_tail += p_empty * inner_tot;
+    }
+    // ---- descending pass: mass above hi(o)
+    {
+        const int64_t o0 = O.lo + (nch - 1) * SPAN + lane * R;
+        QR x = divmod_floor(o0 * I.n - num, O.n), y = divmod_floor(o0 * I.n + num, O.n);
+        double carry = range_sum<MODEL>(L, I, U_top, I.hi + 1, ll, l1m);
+        for (int64_t c = nch - 1; c >= 0; --c) {
+            const int64_t of = O.lo + c * SPAN + lane * R;
+            int64_t U[R + 1];
+            bool empty[R];
+            QR xs = x, ys = y;
+#pragma unroll
+            for (int r = 0; r <= R; ++r) {
+                const int64_t o = of + r;
+                const int64_t lo = lo_of(xs), hi = ys.q;
+                U[r] = o <= O.hi ? tgt_hi(hi) : U_top;
+                if (r < R) empty[r] = (lo < 0 ? 0 : lo) > (hi > I.n ? I.n : hi);
+                qr_add(xs, step, O.n);
+                qr_add(ys, step, O.n);
+            }
+            double sfx[R], acc = 0.0;
+#pragma unroll
+            for (int r = R - 1; r >= 0; --r) {
+                for (int64_t i = U[r + 1] - 1; i >= U[r]; --i) acc += pmf<MODEL>(L, I, i, ll, l1m);
+                sfx[r] = acc;
+            }
+            const double suf = wave_excl_suffix(acc);
+            const double tot = wave_sum(acc);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t o = of + r;
+                if (o <= O.hi && !empty[r])
+                    acc_tail += pmf<MODEL>(L, O, o, ll, l1m) * (carry + suf + sfx[r]);
+            }
+            carry += tot;
+            qr_sub(x, cstep, O.n);
+            qr_sub(y, cstep, O.n);
+        }
+    }
+    return wave_sum(acc_tail);
+}
+
 // One wave per value t of c_T (grid-stride over waves):
 //   terms[t] = hist[t] * log1p(-tail_t).
-// rows: per wave 2 * wmax doubles: lower[i] = sum of the pmf of b over
-// [b_lo, b_lo + i), upper[i] = sum over (b_lo + i, b_hi], on the window
-// [b_lo, b_hi] around b's mean.
 template <int MODEL>
 __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restrict__ L,
                                                           const unsigned long long *__restrict__ hist,
                                                           int64_t n_p, int64_t n_q, uint64_t num_imm,
                                                           const uint64_t *__restrict__ num_dev,
-                                                          int64_t wmax, double *__restrict__ rows,
                                                           double *__restrict__ terms)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    double *lower = rows + (size_t)wave * 2 * wmax;
-    double *upper = lower + wmax;
     const int64_t num = (int64_t)(num_dev ? *num_dev : num_imm);
     for (int64_t t = wave; t <= n_q; t += nwaves) {
         const unsigned long long h = hist[t];
@@ -185,53 +357,27 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
         const double lam = ((double)t + 1.0) / ((double)n_q + 2.0);
         const double ll = log(lam), l1m = log1p(-lam);
         const double muq = (double)n_q * lam, mup = (double)n_p * lam;
-        const double lmuq = log(muq), lmup = log(mup);
         const double sq = MODEL == SIG_POISSON ? sqrt(muq) : sqrt(muq * (1.0 - lam));
         const double sp = MODEL == SIG_POISSON ? sqrt(mup) : sqrt(mup * (1.0 - lam));
         const int64_t wq = window_halfwidth(sq), wp = window_halfwidth(sp);
-        const int64_t b_lo = max((int64_t)0, (int64_t)floor(muq) - wq);
-        const int64_t b_hi = min(n_q, (int64_t)ceil(muq) + wq);
-        const int64_t a_lo = max((int64_t)0, (int64_t)floor(mup) - wp);
-        const int64_t a_hi = min(n_p, (int64_t)ceil(mup) + wp);
-        const int64_t nb = b_hi - b_lo + 1;  // <= wmax - 1
-
-        double carry = 0.0;
-        for (int64_t c0 = 0; c0 < nb; c0 += 64) {
-            const int64_t i = c0 + lane;
-            const double p = i < nb ? exp(log_pmf<MODEL>(L, n_q, b_lo + i, ll, l1m, lmuq, muq)) : 0.0;
-            const double incl = wave_scan(p);
-            if (i < nb) lower[i + 1] = carry + incl;
-            carry += __shfl(incl, 63, 64);
-        }
-        if (lane == 0) lower[0] = 0.0;
-        const double tot_b = carry;
-        carry = 0.0;
-        for (int64_t c0 = 0; c0 < nb; c0 += 64) {
-            const int64_t i = nb - 1 - (c0 + lane);  // descending
-            const double p = i >= 0 ? exp(log_pmf<MODEL>(L, n_q, b_lo + i, ll, l1m, lmuq, muq)) : 0.0;
-            const double incl = wave_scan(p);         // over b >= b_lo + i within the chunk
-            if (i >= 0) upper[i] = carry + incl - p;  // strictly above b_lo + i
-            carry += __shfl(incl, 63, 64);
-        }
-        __threadfence_block();  // the rows are read back by other lanes of the wave
-
-        double part = 0.0;
-        for (int64_t a = a_lo + lane; a <= a_hi; a += 64) {
-            const int64_t lo = -floor_div(num - a * n_q, n_p);  // ceil((a n_q - num)/n_p)
-            const int64_t hi = floor_div(a * n_q + num, n_p);
-            const int64_t lo_c = lo < 0 ? 0 : lo;
-            const int64_t hi_c = hi > n_q ? n_q : hi;
-            double excl;
-            if (lo_c > hi_c) {
-                excl = MODEL == SIG_POISSON ? tot_b : 1.0;  // every b is excluded
-            } else {
-                const double below = lo_c <= b_lo ? 0.0 : (lo_c > b_hi ? tot_b : lower[lo_c - b_lo]);
-                const double above = hi_c >= b_hi ? 0.0 : (hi_c < b_lo ? tot_b : upper[hi_c - b_lo]);
-                excl = below + above;
-            }
-            part += exp(log_pmf<MODEL>(L, n_p, a, ll, l1m, lmup, mup)) * excl;
-        }
-        double tail = wave_sum(part);
+        SigSide A, B;
+        A.n = n_p;
+        A.mu = mup;
+        A.lmu = log(mup);
+        A.lo = max((int64_t)0, (int64_t)floor(mup) - wp);
+        A.hi = min(n_p, (int64_t)ceil(mup) + wp);
+        B.n = n_q;
+        B.mu = muq;
+        B.lmu = log(muq);
+        B.lo = max((int64_t)0, (int64_t)floor(muq) - wq);
+        B.hi = min(n_q, (int64_t)ceil(muq) + wq);
+        // the larger window is the outer one, so that the lanes stay busy
+        // (the condition |a n_q - b n_p| > num is symmetric in the two sides)
+        const bool a_outer = (A.hi - A.lo) >= (B.hi - B.lo);
+        const SigSide &O = a_outer ? A : B;
+        const SigSide &I = a_outer ? B : A;
+        double tail = (O.hi - O.lo + 1 >= 8 * 64) ? tail_two_pass<MODEL, 8>(L, O, I, num, ll, l1m)
+                                                  : tail_two_pass<MODEL, 1>(L, O, I, num, ll, l1m);
         if constexpr (MODEL == SIG_POISSON) {
             // mass of either Poisson count beyond its sample size
             const double ua = pois_upper_wave(L, n_p, mup, wp), ub = pois_upper_wave(L, n_q, muq, wq);
@@ -241,7 +387,6 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
             tail = tail < 0.0 ? 0.0 : (tail > 1.0 ? 1.0 : tail);
             terms[t] = (double)h * log1p(-tail);
         }
-        __threadfence_block();  // this wave's rows are rewritten for its next value
     }
 }
 
@@ -259,19 +404,12 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_final(const double *__restr
 // Largest summation window (entries of b) for n_q trials over every rate,
 // plus the two ends: sigma^2 = n_q lambda (1 - lambda) <= n_q / 4 for the
 // binomial, n_q lambda < n_q for the Poisson model.
-static int64_t sig_wmax(int64_t n_q, int model)
-{
-    const double sig = model == SIG_POISSON ? sqrt((double)n_q) : 0.5 * sqrt((double)n_q);
-    const int64_t w = window_halfwidth(sig);
-    return std::min<int64_t>(n_q + 1, 2 * w + 3) + 2;
-}
-
 int significance_rows(int64_t n_q, int model)
 {
-    // one pair of window rows per wave in flight (at most 8192 waves and
-    // 384 MB of rows), a multiple of the four waves of a block
-    const int64_t per = 16 * sig_wmax(n_q, model);
-    const int64_t r = std::min<int64_t>({(int64_t)(384ull << 20) / per, n_q + 4, 8192});
+    // waves in flight: one per value of c_T up to 8192, a multiple of the four
+    // waves of a block
+    (void)model;
+    const int64_t r = std::min<int64_t>(n_q + 4, 8192);
     return (int)std::max<int64_t>(4, r / 4 * 4);
 }
 
@@ -285,8 +423,9 @@ static int64_t sig_lmax(int64_t n_p, int64_t n_q)
 
 size_t significance_scratch_bytes(int64_t n_p, int64_t n_q, int rows, int model)
 {
-    return (size_t)(sig_lmax(n_p, n_q) + 1) * 8 + (size_t)(n_q + 1) * 8 * 2 +
-           (size_t)rows * 2 * sig_wmax(n_q, model) * 8 + 64;
+    (void)rows;
+    (void)model;
+    return (size_t)(sig_lmax(n_p, n_q) + 1) * 8 + (size_t)(n_q + 1) * 8 * 2 + 64;
 }
 
 hipError_t launch_significance(const uint32_t *counts, int64_t N, int d, int64_t n_p, int64_t n_q,
@@ -297,9 +436,7 @@ hipError_t launch_significance(const uint32_t *counts, int64_t N, int d, int64_t
     double *L = (double *)scratch;
     unsigned long long *hist = (unsigned long long *)(L + lmax + 1);
     double *terms = (double *)(hist + n_q + 1);
-    double *rowbuf = terms + n_q + 1;
     const int64_t entries = N << d;
-    const int64_t wmax = sig_wmax(n_q, model);
     auto blocks = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); };
     if (rows < 4 || rows % 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sig_lgamma, dim3(blocks(lmax + 1)), dim3(256), 0, s, L, lmax);
@@ -325,10 +462,10 @@ hipError_t launch_significance(const uint32_t *counts, int64_t N, int d, int64_t
     const unsigned tb = (unsigned)(rows / 4);  // four waves per block
     if (model == SIG_POISSON)
         hipLaunchKernelGGL(k_sig_tail<SIG_POISSON>, dim3(tb), dim3(SIG_THREADS), 0, s, L, hist, n_p,
-                           n_q, num, num_dev, wmax, rowbuf, terms);
+                           n_q, num, num_dev, terms);
     else
         hipLaunchKernelGGL(k_sig_tail<SIG_BINOMIAL>, dim3(tb), dim3(SIG_THREADS), 0, s, L, hist, n_p,
-                           n_q, num, num_dev, wmax, rowbuf, terms);
+                           n_q, num, num_dev, terms);
     hipLaunchKernelGGL(k_sig_final, dim3(1), dim3(SIG_THREADS), 0, s, terms, n_q + 1, S);
     return hipGetLastError();
 }
