@@ -156,6 +156,9 @@ def bench_rdks(ctx, torch, dev, reps=5):
     return out
 
 
+EXTRAS = ("mixture", "significance", "vdks", "rdks", "power", "permutation", "serving")
+
+
 def bench_power(ctx_factory):
     """Sec. 4.2's power study on the synthetic datasets: the smallest sample
     size per sample, and the smallest parameter difference at 50 points per
@@ -311,6 +314,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated subset of: " + ",".join(EXTRAS))
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (lets profiled runs skip tuning launches)")
@@ -376,7 +381,13 @@ def main():
         line["cpu_baseline"] = cb
 
     extras = {}
-    if not args.no_extras:
+    want = set(EXTRAS) if args.extras == "all" else set(args.extras.split(","))
+    if args.no_extras:
+        want = set()
+    unknown = want - set(EXTRAS)
+    if unknown:
+        raise SystemExit(f"unknown extras: {sorted(unknown)} (known: {', '.join(EXTRAS)})")
+    if "mixture" in want:
         _log("[bench] extra: mixture_grid_d6_100000")
         P3, Q3 = workloads.mixture_grid()
         P3t = torch.from_numpy(P3).to(dev)
@@ -390,16 +401,22 @@ def main():
             "kernel_avg_ms": k3 * 1e3, "frac": (c3 / k3) / VALU_COMPARE_PEAK,
             "num": r3.num, "den": r3.den}
         del P3t, Q3t
+    if "significance" in want:
         _log("[bench] extra: analytic significance")
         extras["significance"] = bench_significance(ctx, native, torch, Pt, Qt, workload)
+    if "vdks" in want:
         _log("[bench] extra: vdKS")
         extras["vdks"] = bench_vdks(ctx, torch, dev)
+    if "rdks" in want:
         _log("[bench] extra: rdKS")
         extras["rdks"] = bench_rdks(ctx, torch, dev)
+    if "power" in want:
         _log("[bench] extra: power study")
         extras["power"] = bench_power(lambda: native.Context(flags=native.DDKS_NO_AUTOTUNE))
+    if "permutation" in want:
         _log("[bench] extra: permutation batch")
         extras["permutation_batch"] = bench_batch(ctx, torch, dev)
+    if "serving" in want:
         _log(f"[bench] extra: serving ({args.serve_requests} requests)")
         extras["serving"] = bench_serving(
             lambda: native.Context(flags=native.DDKS_NO_AUTOTUNE), args.serve_requests)

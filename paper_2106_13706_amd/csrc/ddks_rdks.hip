@@ -11,7 +11,7 @@
 // lists, |c_P(r) n_Q - c_Q(r) n_P| at the largest, over the distinct
 // distances r; D is the largest over the corners.
 //
-// Device work: extents (one block per dimension), normalised coordinates,
+// Device work: extents (order-key minima and maxima per dimension), normalised coordinates,
 // the N x (d + 1) distance matrix (one thread per point and corner), each
 // column sorted as (key, index) pairs, then per corner a segmented scan of
 // first-sample labels along the sorted order that scores the end of every
@@ -28,21 +28,44 @@ namespace ddks {
 static constexpr int RD_SEG = 4096;       // sorted positions per scan segment
 static constexpr int RD_THREADS = 1024;   // four positions per thread
 
-// Per-dimension minimum and maximum (block m, reduction over the points).
-__global__ __launch_bounds__(256) void k_rd_extent(const float *__restrict__ Z, int64_t N, int d,
-                                                   float *__restrict__ lohi)
+// Order-preserving image of a finite fp32 value (-0 is mapped to +0
+// upstream): unsigned comparison of images == fp32 comparison.
+__device__ __forceinline__ uint32_t rd_key(float f)
 {
-    __shared__ float slo[4], shi[4];
-    const int m = blockIdx.x;
-    float lo = INFINITY, hi = -INFINITY;
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-        const float v = Z[i * d + m];
-        lo = fminf(lo, v);
-        hi = fmaxf(hi, v);
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float rd_from_key(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+__global__ void k_rd_extent_init(uint32_t *__restrict__ key, int d)
+{
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < d; m += gridDim.x * blockDim.x) {
+        key[2 * m] = 0xffffffffu;  // running minimum
+        key[2 * m + 1] = 0u;       // running maximum
+    }
+}
+
+// Per-dimension extents as order keys: block (chunk, m) reduces its share of
+// dimension m's values and folds them in with one atomic pair (at most
+// RD_EXTENT_CHUNKS updates per word).
+static constexpr int RD_EXTENT_CHUNKS = 32;
+__global__ __launch_bounds__(256) void k_rd_extent(const float *__restrict__ Z, int64_t N, int d,
+                                                   uint32_t *__restrict__ key)
+{
+    __shared__ uint32_t slo[4], shi[4];
+    const int m = blockIdx.y;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = rd_key(Z[i * d + m]);
+        lo = min(lo, k);
+        hi = max(hi, k);
     }
     for (int off = 32; off >= 1; off >>= 1) {
-        lo = fminf(lo, __shfl_xor(lo, off, 64));
-        hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
@@ -52,24 +75,24 @@ __global__ __launch_bounds__(256) void k_rd_extent(const float *__restrict__ Z, 
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int v = 1; v < 4; ++v) {
-            lo = fminf(lo, slo[v]);
-            hi = fmaxf(hi, shi[v]);
+            lo = min(lo, slo[v]);
+            hi = max(hi, shi[v]);
         }
-        lohi[2 * m] = lo;
-        lohi[2 * m + 1] = hi;
+        atomicMin(&key[2 * m], lo);
+        atomicMax(&key[2 * m + 1], hi);
     }
 }
 
 // Normalised coordinates u (N x d), each value (x - lo) / (hi - lo) rounded once
 // per operation.
-__global__ void k_rd_norm(const float *__restrict__ Z, int64_t N, int d, const float *__restrict__ lohi,
+__global__ void k_rd_norm(const float *__restrict__ Z, int64_t N, int d, const uint32_t *__restrict__ lohi,
                           float *__restrict__ U)
 {
     const int64_t total = N * d;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int m = (int)(e % d);
-        const float lo = lohi[2 * m], hi = lohi[2 * m + 1];
+        const float lo = rd_from_key(lohi[2 * m]), hi = rd_from_key(lohi[2 * m + 1]);
         U[e] = hi > lo ? __fdiv_rn(__fsub_rn(Z[e], lo), __fsub_rn(hi, lo)) : 0.0f;
     }
 }
@@ -90,6 +113,30 @@ __global__ void k_rd_dist(const float *__restrict__ U, int64_t N, int d, float *
             acc = __fadd_rn(acc, __fmul_rn(t, t));
         }
         Dist[e] = acc;
+    }
+}
+
+// The same distances for many dimensions: block per point (grid-stride), the
+// point's normalised row staged in LDS (d <= 4096 floats), one thread per
+// corner; the operations and their order are those of k_rd_dist.
+__global__ __launch_bounds__(256) void k_rd_dist_rows(const float *__restrict__ U, int64_t N, int d,
+                                                      float *__restrict__ Dist)
+{
+    extern __shared__ float urow[];
+    const int C = d + 1;
+    for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
+        __syncthreads();  // the previous row has been used
+        for (int m = threadIdx.x; m < d; m += blockDim.x) urow[m] = U[i * d + m];
+        __syncthreads();
+        for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            float acc = 0.0f;
+#pragma unroll 4
+            for (int m = 0; m < d; ++m) {
+                const float t = __fsub_rn(urow[m], c == m + 1 ? 1.0f : 0.0f);
+                acc = __fadd_rn(acc, __fmul_rn(t, t));
+            }
+            Dist[i * C + c] = acc;
+        }
     }
 }
 
@@ -175,26 +222,53 @@ __global__ __launch_bounds__(RD_THREADS) void k_rd_score(const uint64_t *__restr
     if (threadIdx.x == 0 && bmax > 0ull) atomicMax(&corner_num[m], bmax);
 }
 
-__global__ void k_rd_final(const unsigned long long *__restrict__ corner_num, int C,
-                           uint32_t *__restrict__ flags, ResultDev *__restrict__ out)
+// D = the largest corner numerator; ties go to the lowest corner (one block).
+__global__ __launch_bounds__(1024) void k_rd_final(const unsigned long long *__restrict__ corner_num, int C,
+                                                   uint32_t *__restrict__ flags, ResultDev *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    unsigned long long best = corner_num[0];
-    int bc = 0;
-    for (int c = 1; c < C; ++c)
-        if (corner_num[c] > best) {
-            best = corner_num[c];
+    __shared__ unsigned long long sn[16];
+    __shared__ int sc[16];
+    unsigned long long best = 0ull;
+    int bc = 0x7fffffff;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const unsigned long long v = corner_num[c];
+        if (v > best || (v == best && c < bc)) {
+            best = v;
             bc = c;
         }
-    out->num = best;
-    out->origin = bc;
-    out->code = 0;
-    out->flags = *flags;
-    out->ge = 0;
-    *flags = 0u;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long v = __shfl_xor(best, off, 64);
+        const int c = __shfl_xor(bc, off, 64);
+        if (v > best || (v == best && c < bc)) {
+            best = v;
+            bc = c;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sn[w] = best;
+        sc[w] = bc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x >> 6); ++v)
+            if (sn[v] > best || (sn[v] == best && sc[v] < bc)) {
+                best = sn[v];
+                bc = sc[v];
+            }
+        out->num = best;
+        out->origin = bc;
+        out->code = 0;
+        out->flags = *flags;
+        out->ge = 0;
+        *flags = 0u;
+    }
 }
 
 // ---------------------------------------------------------------- host side
+
+static constexpr int RD_ROWS_MIN_D = 32;  // from here on, distances with the row in LDS
 
 static int64_t rd_segs(int64_t N) { return (N + RD_SEG - 1) / RD_SEG; }
 
@@ -202,7 +276,7 @@ size_t rdks_scratch_bytes(int64_t N, int d)
 {
     const int C = d + 1;
     size_t b = 0;
-    b += (size_t)2 * d * sizeof(float);         // extents
+    b += (size_t)2 * d * sizeof(uint32_t);      // extents (order keys)
     b += (size_t)N * d * sizeof(float);         // U
     b += (size_t)N * C * sizeof(float);         // Dist
     b += (size_t)C * rd_segs(N) * sizeof(uint32_t) + 256;
@@ -216,8 +290,8 @@ hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scra
     const int C = d + 1;
     if (N < 1 || d < 1 || C > 65535) return hipErrorInvalidValue;
     char *base = (char *)scratch;
-    float *lohi = (float *)base;
-    base += ((size_t)2 * d * sizeof(float) + 255) & ~(size_t)255;
+    uint32_t *lohi = (uint32_t *)base;
+    base += ((size_t)2 * d * sizeof(uint32_t) + 255) & ~(size_t)255;
     float *U = (float *)base;
     base += ((size_t)N * d * sizeof(float) + 255) & ~(size_t)255;
     float *Dist = (float *)base;
@@ -226,9 +300,15 @@ hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scra
     const int64_t segs = rd_segs(N);
     base += ((size_t)C * segs * sizeof(uint32_t) + 255) & ~(size_t)255;
     auto grid = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); };
-    hipLaunchKernelGGL(k_rd_extent, dim3((unsigned)d), dim3(256), 0, s, Z, N, d, lohi);
+    hipLaunchKernelGGL(k_rd_extent_init, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, lohi, d);
+    const unsigned chunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 4095) / 4096, RD_EXTENT_CHUNKS));
+    hipLaunchKernelGGL(k_rd_extent, dim3(chunks, (unsigned)d), dim3(256), 0, s, Z, N, d, lohi);
     hipLaunchKernelGGL(k_rd_norm, dim3(grid(N * d)), dim3(256), 0, s, Z, N, d, lohi, U);
-    hipLaunchKernelGGL(k_rd_dist, dim3(grid(N * C)), dim3(256), 0, s, U, N, d, Dist);
+    if (d >= RD_ROWS_MIN_D)
+        hipLaunchKernelGGL(k_rd_dist_rows, dim3((unsigned)std::min<int64_t>(N, 4096)), dim3(256),
+                           (size_t)d * sizeof(float), s, U, N, d, Dist);
+    else
+        hipLaunchKernelGGL(k_rd_dist, dim3(grid(N * C)), dim3(256), 0, s, U, N, d, Dist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint64_t *S = nullptr;
@@ -237,7 +317,7 @@ hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scra
     hipLaunchKernelGGL(k_rd_seg, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p, cnt);
     hipLaunchKernelGGL(k_rd_score, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p,
                        N - n_p, cnt, corner_num);
-    hipLaunchKernelGGL(k_rd_final, dim3(1), dim3(64), 0, s, corner_num, C, flags, out);
+    hipLaunchKernelGGL(k_rd_final, dim3(1), dim3(1024), 0, s, corner_num, C, flags, out);
     return hipGetLastError();
 }
 

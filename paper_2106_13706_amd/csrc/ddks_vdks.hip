@@ -179,13 +179,24 @@ __global__ void k_vox_compact(const uint64_t *__restrict__ tab_key, const uint32
                               int64_t slots, uint32_t *__restrict__ counter, uint64_t *__restrict__ keys,
                               uint64_t *__restrict__ inc)
 {
-    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < slots;
-         h += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = tab_key[h];
-        if (k == VOX_EMPTY) continue;
-        const uint32_t at = atomicAdd(counter, 1u);
-        keys[at] = k;
-        inc[at] = (uint64_t)tab_cnt[2 * h] | ((uint64_t)tab_cnt[2 * h + 1] << 32);
+    // one counter update per wave (a single word updated once per filled slot
+    // would serialise): the lanes holding a filled slot take consecutive places
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t h0 = (int64_t)blockIdx.x * blockDim.x; h0 < slots; h0 += stride) {
+        const int64_t h = h0 + threadIdx.x;
+        const uint64_t k = h < slots ? tab_key[h] : VOX_EMPTY;
+        const bool filled = k != VOX_EMPTY;
+        const uint64_t mask = __ballot(filled);
+        if (!mask) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+        base = __shfl(base, 0, 64);
+        if (filled) {
+            const uint32_t at = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            keys[at] = k;
+            inc[at] = (uint64_t)tab_cnt[2 * h] | ((uint64_t)tab_cnt[2 * h + 1] << 32);
+        }
     }
 }
 

@@ -65,6 +65,16 @@ def test_sort_tile_boundaries(ctx, oracle_mod, N):
     check(ctx, oracle_mod, Z[:n_p], Z[n_p:])
 
 
+@pytest.mark.parametrize("d,n", [(31, 300), (32, 300), (257, 150), (4096, 12)])
+def test_distance_kernel_paths(ctx, oracle_mod, d, n):
+    """Both distance kernels (one thread per point and corner below 32
+    dimensions, the point's row staged in LDS from 32 on, up to the 4096 limit)."""
+    g = np.random.default_rng(d)
+    P = g.standard_normal((n, d)).astype(np.float32)
+    Q = (g.standard_normal((n + 3, d)) * 1.3).astype(np.float32)
+    check(ctx, oracle_mod, P, Q)
+
+
 def test_high_dimension(ctx, oracle_mod):
     """The paper's latent-space case: 100 points per sample in 1000 dimensions."""
     g = np.random.default_rng(1000)
