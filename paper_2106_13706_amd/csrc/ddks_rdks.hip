@@ -116,25 +116,34 @@ __global__ void k_rd_dist(const float *__restrict__ U, int64_t N, int d, float *
     }
 }
 
-// The same distances for many dimensions: block per point (grid-stride), the
-// point's normalised row staged in LDS (d <= 4096 floats), one thread per
-// corner; the operations and their order are those of k_rd_dist.
-__global__ __launch_bounds__(256) void k_rd_dist_rows(const float *__restrict__ U, int64_t N, int d,
-                                                      float *__restrict__ Dist)
+// The same distances for many dimensions: block per point (grid-stride), one
+// thread per corner.  Since u - 0 == u exactly, corner c's sum is the
+// ascending sum of the rounded squares u_m^2 with the term m = c - 1 replaced
+// by the rounded (u_m - 1)^2, so both squares are formed once per point and
+// staged in LDS (2 d <= 8192 floats); the operations and their order are
+// those of k_rd_dist.
+__global__ __launch_bounds__(1024) void k_rd_dist_rows(const float *__restrict__ U, int64_t N, int d,
+                                                       float *__restrict__ Dist)
 {
-    extern __shared__ float urow[];
+    extern __shared__ float sq[];  // sq[m] = u_m^2, sq[d + m] = (u_m - 1)^2
     const int C = d + 1;
     for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
-        __syncthreads();  // the previous row has been used
-        for (int m = threadIdx.x; m < d; m += blockDim.x) urow[m] = U[i * d + m];
+        __syncthreads();  // the previous point's squares have been used
+        for (int m = threadIdx.x; m < d; m += blockDim.x) {
+            const float u = U[i * d + m];
+            const float t = __fsub_rn(u, 1.0f);
+            sq[m] = __fmul_rn(u, u);
+            sq[d + m] = __fmul_rn(t, t);
+        }
         __syncthreads();
         for (int c = threadIdx.x; c < C; c += blockDim.x) {
             float acc = 0.0f;
-#pragma unroll 4
-            for (int m = 0; m < d; ++m) {
-                const float t = __fsub_rn(urow[m], c == m + 1 ? 1.0f : 0.0f);
-                acc = __fadd_rn(acc, __fmul_rn(t, t));
-            }
+            const int j = c - 1;  // the replaced term (none for the origin corner)
+#pragma unroll 8
+            for (int m = 0; m < j; ++m) acc = __fadd_rn(acc, sq[m]);
+            if (j >= 0) acc = __fadd_rn(acc, sq[d + j]);
+#pragma unroll 8
+            for (int m = j + 1; m < d; ++m) acc = __fadd_rn(acc, sq[m]);
             Dist[i * C + c] = acc;
         }
     }
@@ -305,8 +314,8 @@ hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scra
     hipLaunchKernelGGL(k_rd_extent, dim3(chunks, (unsigned)d), dim3(256), 0, s, Z, N, d, lohi);
     hipLaunchKernelGGL(k_rd_norm, dim3(grid(N * d)), dim3(256), 0, s, Z, N, d, lohi, U);
     if (d >= RD_ROWS_MIN_D)
-        hipLaunchKernelGGL(k_rd_dist_rows, dim3((unsigned)std::min<int64_t>(N, 4096)), dim3(256),
-                           (size_t)d * sizeof(float), s, U, N, d, Dist);
+        hipLaunchKernelGGL(k_rd_dist_rows, dim3((unsigned)std::min<int64_t>(N, 4096)), dim3(1024),
+                           (size_t)2 * d * sizeof(float), s, U, N, d, Dist);
     else
         hipLaunchKernelGGL(k_rd_dist, dim3(grid(N * C)), dim3(256), 0, s, U, N, d, Dist);
     hipError_t e = hipGetLastError();

@@ -175,28 +175,43 @@ __global__ __launch_bounds__(256) void k_vox_insert(const float *__restrict__ Z,
 }
 
 // Filled slots to a list: key, and the 64-bit increment c_P | c_Q << 32.
-__global__ void k_vox_compact(const uint64_t *__restrict__ tab_key, const uint32_t *__restrict__ tab_cnt,
-                              int64_t slots, uint32_t *__restrict__ counter, uint64_t *__restrict__ keys,
-                              uint64_t *__restrict__ inc)
+// One counter update per block of 1024 slots (a single word updated by
+// every wave or slot serialises across the chip): the filled slots of a
+// block take consecutive places, in slot order within the block.
+static constexpr int COMPACT_THREADS = 1024;
+__global__ __launch_bounds__(COMPACT_THREADS) void k_vox_compact(const uint64_t *__restrict__ tab_key,
+                                                                 const uint32_t *__restrict__ tab_cnt,
+                                                                 int64_t slots, uint32_t *__restrict__ counter,
+                                                                 uint64_t *__restrict__ keys,
+                                                                 uint64_t *__restrict__ inc)
 {
-    // one counter update per wave (a single word updated once per filled slot
-    // would serialise): the lanes holding a filled slot take consecutive places
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t h0 = (int64_t)blockIdx.x * blockDim.x; h0 < slots; h0 += stride) {
+    __shared__ uint32_t wbase[COMPACT_THREADS / 64];
+    __shared__ uint32_t bbase;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t stride = (int64_t)gridDim.x * COMPACT_THREADS;
+    for (int64_t h0 = (int64_t)blockIdx.x * COMPACT_THREADS; h0 < slots; h0 += stride) {
         const int64_t h = h0 + threadIdx.x;
         const uint64_t k = h < slots ? tab_key[h] : VOX_EMPTY;
         const bool filled = k != VOX_EMPTY;
         const uint64_t mask = __ballot(filled);
-        if (!mask) continue;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-        base = __shfl(base, 0, 64);
+        if (lane == 0) wbase[w] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int v = 0; v < COMPACT_THREADS / 64; ++v) {
+                const uint32_t c = wbase[v];
+                wbase[v] = tot;
+                tot += c;
+            }
+            bbase = tot ? atomicAdd(counter, tot) : 0u;
+        }
+        __syncthreads();
         if (filled) {
-            const uint32_t at = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint32_t at = bbase + wbase[w] + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
             keys[at] = k;
             inc[at] = (uint64_t)tab_cnt[2 * h] | ((uint64_t)tab_cnt[2 * h + 1] << 32);
         }
+        __syncthreads();  // wbase and bbase are rewritten for the next slots
     }
 }
 
@@ -490,8 +505,8 @@ static hipError_t launch_vox_front_d(const float *Z, int64_t N, int64_t n_p, int
     hipLaunchKernelGGL(k_vox_minmax_final<D>, dim3(1), dim3(256), 0, s, part, (int)rows, mm);
     hipLaunchKernelGGL(k_vox_insert<D>, dim3(grid_for(N)), dim3(256), 0, s, Z, N, n_p, V, mm, tab_key,
                        tab_cnt, (uint64_t)(slots - 1));
-    hipLaunchKernelGGL(k_vox_compact, dim3(grid_for(slots)), dim3(256), 0, s, tab_key, tab_cnt, slots,
-                       counter, keys, inc);
+    hipLaunchKernelGGL(k_vox_compact, dim3(grid_for(slots, COMPACT_THREADS, 256)), dim3(COMPACT_THREADS), 0, s,
+                       tab_key, tab_cnt, slots, counter, keys, inc);
     return hipGetLastError();
 }
 
