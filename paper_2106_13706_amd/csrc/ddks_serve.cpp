@@ -10,6 +10,10 @@
 //           one launch whose blocks are (test, origin group) work items, on
 //           one of several streams, so launches overlap on the device and
 //           requests that arrive while others run join the next launch;
+//           large tests (SERVE_SOLO_MIN <= N) are swept on their own with
+//           the point-chunked plan of a plain call instead: a packed block
+//           sweeps all N points for its 64 origins, too coarse a unit to keep
+//           every CU busy to the end of a large test;
 //           mid-size tests (SERVE_R16_MIN <= N <= 65536) are first rank
 //           encoded on the device for the 16-bit compare path (at most N
 //           distinct values per dimension, so the ranks always fit);
@@ -78,12 +82,19 @@ struct Arena {
 // launches cost about what the 16-bit compares save.
 static constexpr int64_t SERVE_R16_MIN = 16384;
 
+// Smallest test swept on its own with a chunked plan, and the per-slot
+// buffer for the partial counts of its chunks (they grow with 2^d).
+static constexpr int64_t SERVE_SOLO_MIN = 16384;
+static constexpr size_t SERVE_SOLO_PARTIAL = 128ull << 20;
+
 struct Req {
     uint64_t ticket = 0;
     int d = 0;
     int64_t n_p = 0, n_q = 0, N = 0;
     int hists = 1;            // LDS histograms per block of its packed sweep
     int path = PATH_F32;      // compare path of its sweep
+    bool solo = false;        // swept on its own with `plan` (not packed)
+    SweepPlan plan;
     std::vector<float> data;  // P then Q
     // arena layout: fp32 points | rank-encoded points (PATH_R16) | block results
     size_t pts_bytes = 0, r16_bytes = 0, bytes = 0;
@@ -109,6 +120,9 @@ struct Slot {
     // rank encoding of this slot's requests, one after another on its stream
     void *rank_scratch = nullptr;
     uint32_t *rank_ctl = nullptr;  // launch_rank16 control block
+    // partial counts and the (always zero) flags word of solo sweeps
+    uint2 *partial = nullptr;
+    uint32_t *flags_d = nullptr;
 };
 
 struct Serve {
@@ -124,6 +138,7 @@ struct Serve {
     void *arena_base = nullptr;
     size_t slot_bytes = 0;  // per-slot device scratch charged to the budget
     bool use_r16 = false;   // rank-encoded path available (set once at start)
+    bool use_solo = false;  // chunked solo sweeps available (set once at start)
     std::vector<Slot> slots;
     std::thread th;
     bool stop = false;
@@ -180,11 +195,17 @@ int Serve::grow_slot(Slot &s, size_t tests, size_t items)
 // dimension present, then the per-test reductions and the result copy.
 bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
 {
+    // packed tests first (sorted by dimension and path), then the solo ones
     std::stable_sort(batch.begin(), batch.end(), [](const Req *a, const Req *b) {
+        if (a->solo != b->solo) return !a->solo;
         return a->d != b->d ? a->d < b->d : a->path < b->path;
     });
-    size_t nitems = 0;
-    for (Req *r : batch) nitems += (size_t)((r->N + 63) / 64);
+    size_t nitems = 0, npacked = 0;
+    for (Req *r : batch)
+        if (!r->solo) {
+            nitems += (size_t)((r->N + 63) / 64);
+            ++npacked;
+        }
     if (grow_slot(s, batch.size(), nitems) != DDKS_OK) {
         error = "serving buffer allocation failed";
         return false;
@@ -208,7 +229,8 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         t.bb_offset = (int64_t)((r->off + r->pts_bytes + r->r16_bytes) / sizeof(BlockBest));
         t.hists = r->hists;
         t.path = r->path;
-        for (int64_t g = 0; g < t.groups; ++g) s.items_h[it++] = make_int2((int)i, (int)g);
+        if (!r->solo)
+            for (int64_t g = 0; g < t.groups; ++g) s.items_h[it++] = make_int2((int)i, (int)g);
         if (hipMemcpyAsync(zf, r->data.data(), r->data.size() * sizeof(float),
                            hipMemcpyHostToDevice, s.stream) != hipSuccess) {
             error = "H2D request copy failed";
@@ -221,19 +243,20 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
             return false;
         }
     }
-    if (hipMemcpyAsync(s.tests_d, s.tests_h, batch.size() * sizeof(PackedTest),
-                       hipMemcpyHostToDevice, s.stream) != hipSuccess ||
-        hipMemcpyAsync(s.items_d, s.items_h, nitems * sizeof(int2), hipMemcpyHostToDevice,
-                       s.stream) != hipSuccess) {
+    if (npacked &&
+        (hipMemcpyAsync(s.tests_d, s.tests_h, npacked * sizeof(PackedTest), hipMemcpyHostToDevice,
+                        s.stream) != hipSuccess ||
+         hipMemcpyAsync(s.items_d, s.items_h, nitems * sizeof(int2), hipMemcpyHostToDevice,
+                        s.stream) != hipSuccess)) {
         error = "H2D table copy failed";
         return false;
     }
     // one launch per run of equal dimension and path (the batch is sorted so)
     size_t i0 = 0, item0 = 0;
-    while (i0 < batch.size()) {
+    while (i0 < npacked) {
         size_t i1 = i0, items = 0;
         int max_hists = 1;
-        while (i1 < batch.size() && batch[i1]->d == batch[i0]->d && batch[i1]->path == batch[i0]->path) {
+        while (i1 < npacked && batch[i1]->d == batch[i0]->d && batch[i1]->path == batch[i0]->path) {
             items += (size_t)((batch[i1]->N + 63) / 64);
             max_hists = std::max(max_hists, batch[i1]->hists);
             ++i1;
@@ -246,8 +269,24 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         item0 += items;
         i0 = i1;
     }
-    if (launch_reduce_packed(s.tests_d, (int64_t)batch.size(), bb, s.res_d, s.stream) != hipSuccess ||
-        hipMemcpyAsync(s.res_h, s.res_d, batch.size() * sizeof(ResultDev), hipMemcpyDeviceToHost,
+    if (npacked && launch_reduce_packed(s.tests_d, (int64_t)npacked, bb, s.res_d, s.stream) != hipSuccess) {
+        error = "packed reduction launch failed";
+        return false;
+    }
+    // solo tests: sweep (+ score of the chunks' partial counts) + reduce
+    for (size_t i = npacked; i < batch.size(); ++i) {
+        Req *r = batch[i];
+        const PackedTest &t = s.tests_h[i];
+        BlockBest *tbb = bb + t.bb_offset;
+        uint2 *part = r->plan.chunks > 1 ? s.partial : nullptr;
+        if (launch_sweep(r->plan, t.Z, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess ||
+            (part && launch_score(r->plan, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess) ||
+            launch_reduce(tbb, r->plan.groups, s.flags_d, s.res_d + i, s.stream) != hipSuccess) {
+            error = "solo sweep launch failed";
+            return false;
+        }
+    }
+    if (hipMemcpyAsync(s.res_h, s.res_d, batch.size() * sizeof(ResultDev), hipMemcpyDeviceToHost,
                        s.stream) != hipSuccess ||
         hipEventRecord(s.t1, s.stream) != hipSuccess ||
         hipEventRecord(s.done, s.stream) != hipSuccess) {
@@ -409,6 +448,26 @@ int serve_start(ddks_ctx *c)
         c->used += rank_bytes;
         sv->slot_bytes += rank_bytes;
     }
+    // Per-slot buffers of the solo sweeps, likewise only when the budget
+    // still leaves a 64 MB arena.
+    {
+        const uint64_t used = c->used.load();
+        const uint64_t per = SERVE_SOLO_PARTIAL + 256;
+        const uint64_t need = (uint64_t)sv->slots.size() * per + (64ull << 20);
+        sv->use_solo = c->budget > used && c->budget - used >= need;
+    }
+    for (Slot &s : sv->slots) {
+        if (!sv->use_solo) break;
+        if (hipMalloc((void **)&s.partial, SERVE_SOLO_PARTIAL) != hipSuccess ||
+            hipMalloc((void **)&s.flags_d, 256) != hipSuccess || hipMemset(s.flags_d, 0, 256) != hipSuccess) {
+            (void)hipGetLastError();
+            c->serve = sv;
+            serve_stop(c);
+            return fail(c, DDKS_E_NOMEM, "serving scratch allocation failed");
+        }
+        c->used += SERVE_SOLO_PARTIAL + 256;
+        sv->slot_bytes += SERVE_SOLO_PARTIAL + 256;
+    }
     uint64_t left = c->budget > c->used.load() ? c->budget - c->used.load() : 0;
     uint64_t arena = std::min<uint64_t>(left, 8ull << 30);
     arena &= ~(uint64_t)255;
@@ -469,6 +528,8 @@ void serve_stop(ddks_ctx *c)
         if (s.res_d) (void)hipFree(s.res_d);
         if (s.rank_scratch) (void)hipFree(s.rank_scratch);
         if (s.rank_ctl) (void)hipFree(s.rank_ctl);
+        if (s.partial) (void)hipFree(s.partial);
+        if (s.flags_d) (void)hipFree(s.flags_d);
     }
     c->used -= sv->slot_bytes;
     if (sv->arena_base) {
@@ -541,6 +602,24 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
         return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
     }
     r->path = (sv->use_r16 && N >= SERVE_R16_MIN && N <= 65536) ? PATH_R16 : PATH_F32;
+    if (sv->use_solo && N >= SERVE_SOLO_MIN) {
+        // the launch heuristics of a plain call (not the tuner's entries,
+        // which the calling threads may be updating), with no more chunks than
+        // the slot's partial-count buffer holds; a single chunk takes 16 waves
+        // per block, to fill the CUs where LDS admits few blocks
+        SweepPlan p = plan_for(nullptr, r->path, req->d, N, req->n_p);
+        const size_t per_chunk = (size_t)p.groups * ((size_t)1 << p.d) * 64 * sizeof(uint2);
+        if (p.chunks > 1 && (size_t)p.chunks * per_chunk > SERVE_SOLO_PARTIAL) {
+            p.chunks = std::max<int64_t>(1, (int64_t)(SERVE_SOLO_PARTIAL / per_chunk));
+            if (p.chunks == 1) p.waves = 16;
+            if (!plan_complete(p, N, req->n_p)) p.hists = 0;
+        }
+        const size_t pb = p.chunks > 1 ? (size_t)p.chunks * per_chunk : 0;
+        if (p.hists > 0 && pb <= SERVE_SOLO_PARTIAL) {
+            r->solo = true;
+            r->plan = p;
+        }
+    }
     r->pts_bytes = align256((np_el + nq_el) * sizeof(float));
     r->r16_bytes = r->path == PATH_R16
                        ? align256((size_t)N * point_words(PATH_R16, req->d) * sizeof(uint32_t))
