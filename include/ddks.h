@@ -205,10 +205,10 @@ typedef struct ddks_request {
 
 typedef struct ddks_serve_stats {
     uint64_t submitted, completed, rejected_again, rejected_nomem;
-    uint64_t launches;         /* packed launches issued */
+    uint64_t launches;         /* launches issued (each packs one or more tests) */
     double p50_latency_us;     /* submit -> result ready, over completed requests */
     double p99_latency_us;
-    double mean_batch;         /* tests per packed launch */
+    double mean_batch;         /* tests per launch */
     uint64_t resident_bytes;   /* device bytes currently held by admitted requests */
     double busy_us;            /* device time covered by at least one retired launch
                                   (copies, encodings, sweeps, reductions) */
@@ -217,8 +217,14 @@ typedef struct ddks_serve_stats {
 /*
  * Submits one test to the context's serving loop (continuous batching:
  * requests that arrive while others run are admitted as device memory and
- * queue slots free up, and packed into shared launches).  The library
- * copies P and Q before returning; the caller may free them at once.
+ * queue slots free up; tests below 16384 points are packed into shared
+ * launches, larger ones are swept with the point-chunked plan of a plain
+ * call on one of the serve_streams streams).  The library copies P and Q
+ * before returning; the caller may free them at once.  The first submit
+ * starts the loop: per stream it holds a 16-bit rank-encoding scratch and a
+ * 128 MB partial-count buffer, each only if the budget leaves a 64 MB
+ * arena beside it (otherwise that path is not used), and an arena of what
+ * the budget then leaves, up to 8 GB, for the admitted requests.
  * Thread-safe.  *ticket identifies the request for ddks_serve_poll.
  * Each test is swept by one block shape whose 16-bit per-sample counters
  * bound a sample to about 8 * 65535 points (4 * 65535 at d = 7, 2 * 65535
