@@ -49,6 +49,36 @@ __host__ __device__ constexpr uint32_t dot_wts(int D, int q)
     return w;
 }
 
+// Pair histograms (d <= 4).  Consecutive points p, p' of a wave's range are
+// counted together in one bin of a BINS x BINS table, bin (code(p) * BINS +
+// code(p')), so one LDS atomic serves two points; a per-orthant count is then
+// its row sum plus its column sum (plus the single-point bins of a range's
+// leftover points).  The pair index comes from the same v_dot4 chain as a
+// point of 2d dimensions: the first point's dimensions weighted 2^m * BINS,
+// the second's 2^m.  At d = 4 the first point's weight 128 does not fit a
+// signed byte and is given -128, which flips bit 7 of the table index (as
+// dimension 7 does at d = 8).
+template <int D>
+struct PairGeo {
+    static constexpr bool ON = D <= 4;
+    static constexpr int BINS = 1 << D;
+    static constexpr int PBINS = BINS * BINS;
+    static constexpr int PFLIP = (D == 4) ? 0x80 : 0;
+    static constexpr int PKOFF = (D == 4) ? 127 : (PBINS - 1);  // table index = dot-sum + PKOFF
+    static constexpr int SLOTS = PBINS + BINS;                 // table, then single-point bins
+};
+
+// Signed-byte weights of a pair's first point: 2^m * BINS, -128 for 128.
+__host__ __device__ constexpr uint32_t pair_wts_hi(int D)
+{
+    uint32_t w = 0;
+    for (int m = 0; m < D && m < 4; ++m) {
+        uint32_t b = (uint32_t)(1u << m) << D;
+        w |= (b & 0xffu) << (8 * m);
+    }
+    return w;
+}
+
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 // ---------------------------------------------------------------------------
@@ -227,6 +257,78 @@ __device__ __forceinline__ void block_addrs(const typename Layout<PATH, D>::T *b
     }
 }
 
+// Pair-table addresses of U/2 pairs of consecutive points held in buf (U a
+// multiple of 8): the dot chain of two 4-dimension groups, first point's
+// bytes against pair_wts_hi, second point's against dot_wts.
+template <int PATH, int D, int U>
+__device__ __forceinline__ void block_pair_addrs(const typename Layout<PATH, D>::T *buf,
+                                                 const Origin<PATH, D> &org, uint32_t pbase,
+                                                 uint32_t (&a)[U / 2])
+{
+    static_assert(PairGeo<D>::ON && U % 8 == 0, "pairs of four per chain");
+    constexpr int PW = Layout<PATH, D>::PW;
+    const uint32_t wh = pair_wts_hi(D), wl = dot_wts(D, 0);
+#pragma unroll
+    for (int g = 0; g < U / 2; g += 4) {
+        uint32_t R[2][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t r0[Geo<D>::NREG], r1[Geo<D>::NREG];
+            signs<PATH, D>(buf + (2 * (g + u)) * PW, org, r0);
+            signs<PATH, D>(buf + (2 * (g + u) + 1) * PW, org, r1);
+            R[0][u] = group_bytes<D>(r0, 0);
+            R[1][u] = group_bytes<D>(r1, 0);
+        }
+        uint32_t q[4];
+        addr4<2>(R, pbase, q, wh, wl);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[g + u] = q[u];
+    }
+}
+
+// d <= 2: a point has at most two sign bits (bits 15 and 31 of its one sign
+// register), so one v_perm_b32 gathers both points of a pair: bytes 0, 1 the
+// first point's dimensions, bytes 2, 3 the second's, and one v_dot4 against
+// the weights (2^m * BINS for the first point, 2^m for the second) gives the
+// table index.
+__host__ __device__ constexpr uint32_t pair_wts_merged(int D)
+{
+    uint32_t w = 0;
+    for (int m = 0; m < D && m < 2; ++m) {
+        w |= ((uint32_t)(1u << m) << D) << (8 * m);  // first point
+        w |= (uint32_t)(1u << m) << (8 * (m + 2));     // second point
+    }
+    return w;
+}
+
+template <int PATH, int D, int U>
+__device__ __forceinline__ void block_pair_addrs_merged(const typename Layout<PATH, D>::T *buf,
+                                                        const Origin<PATH, D> &org, uint32_t pbase,
+                                                        uint32_t (&a)[U / 2])
+{
+    static_assert(D <= 2 && U % 8 == 0, "pairs of four per chain");
+    constexpr int PW = Layout<PATH, D>::PW;
+    // selector 8/9: bit 15/31 of src1 (first point), 10/11: of src0 (second)
+    constexpr uint32_t SEL = 0x0b0a0908u;
+    const uint32_t w = pair_wts_merged(D);
+#pragma unroll
+    for (int g = 0; g < U / 2; g += 4) {
+        uint32_t R[2][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t r0[Geo<D>::NREG], r1[Geo<D>::NREG];
+            signs<PATH, D>(buf + (2 * (g + u)) * PW, org, r0);
+            signs<PATH, D>(buf + (2 * (g + u) + 1) * PW, org, r1);
+            R[0][u] = __builtin_amdgcn_perm(r1[0], r0[0], SEL);
+            R[1][u] = 0u;
+        }
+        uint32_t q[4];
+        addr4<1>(R, pbase, q, w, 0u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[g + u] = q[u];
+    }
+}
+
 // Waits for every outstanding LDS and scalar-memory operation of the wave
 // (lgkmcnt = 0; vector-memory and export counters left alone).
 __device__ __forceinline__ void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xc07f); }
@@ -302,6 +404,77 @@ __device__ __forceinline__ void sweep_range(const typename Layout<PATH, D>::T *_
         uint32_t R0 = group_bytes<D>(r, 0);
         uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
         lds_add(addr1<NP>(R0, R1, base, w0, w1), inc);
+    }
+}
+
+template <int PATH, int D, int U>
+__device__ __forceinline__ void pair_addrs(const typename Layout<PATH, D>::T *buf, const Origin<PATH, D> &org,
+                                           uint32_t pbase, uint32_t (&a)[U / 2])
+{
+    if constexpr (D <= 2)
+        block_pair_addrs_merged<PATH, D, U>(buf, org, pbase, a);
+    else
+        block_pair_addrs<PATH, D, U>(buf, org, pbase, a);
+}
+
+// sweep_range with pair histograms (d <= 4): the same software pipeline over
+// blocks of U points, each block adding U/2 pairs into the table at pbase (the
+// LDS byte address of table index PKOFF of this lane); leftover points of the
+// range go one by one to the single-point bins at sbase (bin KOFF).
+template <int PATH, int D>
+__device__ __forceinline__ void sweep_range_pairs(const typename Layout<PATH, D>::T *__restrict__ Z,
+                                                  int64_t lo, int64_t hi, const Origin<PATH, D> &org,
+                                                  uint32_t pbase, uint32_t sbase, uint32_t inc)
+{
+    typedef typename Layout<PATH, D>::T T;
+    constexpr int PW = Layout<PATH, D>::PW;
+    constexpr int U0 = Unroll<PATH, D>::U;
+    constexpr int U = U0 < 8 ? 8 : U0 / 8 * 8;
+    int64_t i = lo;
+    int64_t nblk = hi > lo ? (hi - lo) / U : 0;
+    if (nblk & 1) {
+        T buf[U * PW];
+#pragma unroll
+        for (int e = 0; e < U * PW; ++e) buf[e] = Z[i * PW + e];
+        uint32_t a[U / 2];
+        pair_addrs<PATH, D, U>(buf, org, pbase, a);
+#pragma unroll
+        for (int u = 0; u < U / 2; ++u) lds_add(a[u], inc);
+        i += U;
+        --nblk;
+    }
+    if (nblk > 0) {
+        const int64_t last = hi - U;
+        T bufA[U * PW], bufB[U * PW];
+#pragma unroll
+        for (int e = 0; e < U * PW; ++e) bufA[e] = Z[i * PW + e];
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int64_t t = 0; t < nblk; t += 2) {
+#pragma unroll
+            for (int e = 0; e < U * PW; ++e) bufB[e] = Z[(i + U) * PW + e];
+            uint32_t a[U / 2];
+            pair_addrs<PATH, D, U>(bufA, org, pbase, a);
+            wait_lgkm();
+#pragma unroll
+            for (int u = 0; u < U / 2; ++u) lds_add(a[u], inc);
+            const int64_t na = (i + 2 * U < last) ? i + 2 * U : last;
+#pragma unroll
+            for (int e = 0; e < U * PW; ++e) bufA[e] = Z[na * PW + e];
+            pair_addrs<PATH, D, U>(bufB, org, pbase, a);
+            wait_lgkm();
+#pragma unroll
+            for (int u = 0; u < U / 2; ++u) lds_add(a[u], inc);
+            i += 2 * U;
+        }
+    }
+    const uint32_t w0 = dot_wts(D, 0);
+    for (; i < hi; ++i) {
+        T buf[PW];
+#pragma unroll
+        for (int e = 0; e < PW; ++e) buf[e] = Z[i * PW + e];
+        uint32_t r[Geo<D>::NREG];
+        signs<PATH, D>(buf, org, r);
+        lds_add(addr1<1>(group_bytes<D>(r, 0), 0u, sbase, w0, 0u), inc);
     }
 }
 

@@ -116,7 +116,9 @@ __device__ __forceinline__ void sweep_block(const void *__restrict__ Zv, int64_t
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int H = __builtin_amdgcn_readfirstlane(hists);
 
-    for (int i = threadIdx.x; i < H * BINS * 64; i += W * 64) smem[i] = 0;
+    constexpr bool PAIRS = PairGeo<D>::ON;
+    constexpr int SLOTS = PAIRS ? PairGeo<D>::SLOTS : BINS;  // 32-bit words per lane per histogram
+    for (int i = threadIdx.x; i < H * SLOTS * 64; i += W * 64) smem[i] = 0;
 
     int64_t k = group * 64 + lane;
     Origin<PATH, D> org;
@@ -144,18 +146,44 @@ __device__ __forceinline__ void sweep_block(const void *__restrict__ Zv, int64_t
     qb = __builtin_amdgcn_readfirstlane((int)qb) + q0;
 
     const int hist = w & (H - 1);
-    const uint32_t base =
-        (uint32_t)(uintptr_t)(lds_u32 *)(smem + (hist * BINS + Geo<D>::KOFF) * 64 + lane);
-    sweep_range<PATH, D>(Z, pa, pb, org, base, 1u);
-    sweep_range<PATH, D>(Z, qa, qb, org, base, 0x10000u);
+    if constexpr (PAIRS) {
+        const uint32_t pbase =
+            (uint32_t)(uintptr_t)(lds_u32 *)(smem + (hist * SLOTS + PairGeo<D>::PKOFF) * 64 + lane);
+        const uint32_t sbase = (uint32_t)(uintptr_t)(lds_u32 *)(
+            smem + (hist * SLOTS + PairGeo<D>::PBINS + Geo<D>::KOFF) * 64 + lane);
+        sweep_range_pairs<PATH, D>(Z, pa, pb, org, pbase, sbase, 1u);
+        sweep_range_pairs<PATH, D>(Z, qa, qb, org, pbase, sbase, 0x10000u);
+    } else {
+        const uint32_t base =
+            (uint32_t)(uintptr_t)(lds_u32 *)(smem + (hist * BINS + Geo<D>::KOFF) * 64 + lane);
+        sweep_range<PATH, D>(Z, pa, pb, org, base, 1u);
+        sweep_range<PATH, D>(Z, qa, qb, org, base, 0x10000u);
+    }
     __syncthreads();
 
+    // (c_P, c_Q) of orthant j: with pair tables, the row of j (j first in the
+    // pair), its column (j second; the diagonal bin counts two points of j),
+    // and the single-point bin.
     auto get = [&](int j) {
         uint32_t cp = 0, cq = 0;
         for (int v = 0; v < H; ++v) {
-            uint32_t h = smem[(v * BINS + j) * 64 + lane];
-            cp += h & 0xffffu;
-            cq += h >> 16;
+            if constexpr (PAIRS) {
+                constexpr int F = PairGeo<D>::PFLIP;
+                const uint32_t *t = smem + v * SLOTS * 64 + lane;
+#pragma unroll
+                for (int k = 0; k < BINS; ++k) {
+                    const uint32_t r = t[((j * BINS + k) ^ F) * 64], c = t[((k * BINS + j) ^ F) * 64];
+                    cp += (r & 0xffffu) + (c & 0xffffu);
+                    cq += (r >> 16) + (c >> 16);
+                }
+                const uint32_t h = t[(PairGeo<D>::PBINS + j) * 64];
+                cp += h & 0xffffu;
+                cq += h >> 16;
+            } else {
+                uint32_t h = smem[(v * BINS + j) * 64 + lane];
+                cp += h & 0xffffu;
+                cq += h >> 16;
+            }
         }
         return make_uint2(cp, cq);
     };
@@ -325,7 +353,13 @@ int point_words(int path, int d)
     return d <= 2 ? 1 : (d <= 4 ? 2 : 4);
 }
 
-size_t hist_lds_bytes(int d, int hists) { return (size_t)hists * ((size_t)1 << d) * 64 * 4; }
+size_t hist_lds_bytes(int d, int hists)
+{
+    // d <= 4: a BINS x BINS pair table and BINS single-point bins per histogram
+    const size_t bins = (size_t)1 << d;
+    const size_t slots = d <= 4 ? bins * bins + bins : bins;
+    return (size_t)hists * slots * 64 * 4;
+}
 
 size_t sweep_lds_bytes(const SweepPlan &p)
 {
