@@ -136,6 +136,22 @@ __device__ __forceinline__ void addr4(const uint32_t (&R)[2][4], uint32_t base, 
     }
 }
 
+// addr4<2> with the second group's weight alternating between points: points
+// 0, 2 take w1e and points 1, 3 take w1o (two points whose second groups share
+// one register).
+template <int SH = 8>
+__device__ __forceinline__ void addr4_w2(const uint32_t (&R)[2][4], uint32_t base, uint32_t (&a)[4],
+                                         uint32_t w0, uint32_t w1e, uint32_t w1o)
+{
+    asm(DOT0("%0", "%4", "%12") DOT0("%1", "%5", "%12") DOT0("%2", "%6", "%12")
+            DOT0("%3", "%7", "%12") DOTC("%0", "%8", "%13") DOTC("%1", "%9", "%14")
+                DOTC("%2", "%10", "%13") DOTC("%3", "%11", "%14") ADDR("%0", "%15")
+                    ADDR("%1", "%15") ADDR("%2", "%15") ADDR("%3", "%15")
+        : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3])
+        : "v"(R[0][0]), "v"(R[0][1]), "v"(R[0][2]), "v"(R[0][3]), "v"(R[1][0]), "v"(R[1][1]),
+          "v"(R[1][2]), "v"(R[1][3]), "s"(w0), "s"(w1e), "s"(w1o), "v"(base), [sh] "i"(SH));
+}
+
 // The same for a single point, with the wait states written out.
 template <int NPERM, int SH = 8>
 __device__ __forceinline__ uint32_t addr1(uint32_t R0, uint32_t R1, uint32_t base, uint32_t w0,
@@ -243,15 +259,31 @@ __device__ __forceinline__ void block_addrs(const typename Layout<PATH, D>::T *b
 #pragma unroll
     for (int g = 0; g < U; g += 4) {
         uint32_t R[2][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            uint32_t r[Geo<D>::NREG];
-            signs<PATH, D>(buf + (g + u) * PW, org, r);
-            R[0][u] = group_bytes<D>(r, 0);
-            R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-        }
         uint32_t q[4];
-        addr4<NP>(R, base, q, w0, w1);
+        if constexpr (D == 5 || D == 6) {
+            // The second group holds dimensions 4 (and 5) only: one v_perm
+            // serves two points, bytes 0-1 the first's, bytes 2-3 the second's.
+            constexpr uint32_t SEL = D == 6 ? 0x0b0a0908u : 0x0c0a0c08u;
+#pragma unroll
+            for (int u = 0; u < 4; u += 2) {
+                uint32_t r0[Geo<D>::NREG], r1[Geo<D>::NREG];
+                signs<PATH, D>(buf + (g + u) * PW, org, r0);
+                signs<PATH, D>(buf + (g + u + 1) * PW, org, r1);
+                R[0][u] = group_bytes<D>(r0, 0);
+                R[0][u + 1] = group_bytes<D>(r1, 0);
+                R[1][u] = R[1][u + 1] = __builtin_amdgcn_perm(r1[2], r0[2], SEL);
+            }
+            addr4_w2(R, base, q, w0, w1, w1 << 16);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint32_t r[Geo<D>::NREG];
+                signs<PATH, D>(buf + (g + u) * PW, org, r);
+                R[0][u] = group_bytes<D>(r, 0);
+                R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+            }
+            addr4<NP>(R, base, q, w0, w1);
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) a[g + u] = q[u];
     }
