@@ -118,12 +118,15 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Half-width x of the summation window around the mean.  By Bernstein's
 // inequality a count x or more away from its mean has probability at most
-// exp(-x^2 / (2 (sigma^2 + x/3))); with x = 700/3 + sqrt((700/3)^2 +
-// 1400 sigma^2) that is exp(-700) ~ 1e-304, so every term left out is far
-// below the precision S is computed to.
-__host__ __device__ __forceinline__ int64_t window_halfwidth(double sigma)
+// exp(-x^2 / (2 (sigma^2 + x/3))); with x = K/3 + sqrt(K^2/9 + 2 K sigma^2)
+// that is exp(-K).  K = 700 (~1e-304) leaves out nothing S could show; the
+// tail kernel first sums with K = SIG_K_NARROW and keeps that result when the
+// tail is large enough for the left-out mass to be negligible beside it.
+static constexpr double SIG_K_FULL = 700.0, SIG_K_NARROW = 100.0;
+static constexpr double SIG_NARROW_MIN_TAIL = 1e-30;  // e^-100 ~ 4e-44 left out, < 1e-13 relative
+__host__ __device__ __forceinline__ int64_t window_halfwidth(double sigma, double K = SIG_K_FULL)
 {
-    return (int64_t)ceil(700.0 / 3.0 + sqrt(700.0 * 700.0 / 9.0 + 1400.0 * sigma * sigma)) + 1;
+    return (int64_t)ceil(K / 3.0 + sqrt(K * K / 9.0 + 2.0 * K * sigma * sigma)) + 1;
 }
 
 // P(X > m), X ~ Poisson(mu), summed directly 64 terms at a time over
@@ -359,25 +362,31 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
         const double muq = (double)n_q * lam, mup = (double)n_p * lam;
         const double sq = MODEL == SIG_POISSON ? sqrt(muq) : sqrt(muq * (1.0 - lam));
         const double sp = MODEL == SIG_POISSON ? sqrt(mup) : sqrt(mup * (1.0 - lam));
+        // the tail over windows of width K around both means
+        auto tail_k = [&](double K) {
+            const int64_t wq = window_halfwidth(sq, K), wp = window_halfwidth(sp, K);
+            SigSide A, B;
+            A.n = n_p;
+            A.mu = mup;
+            A.lmu = log(mup);
+            A.lo = max((int64_t)0, (int64_t)floor(mup) - wp);
+            A.hi = min(n_p, (int64_t)ceil(mup) + wp);
+            B.n = n_q;
+            B.mu = muq;
+            B.lmu = log(muq);
+            B.lo = max((int64_t)0, (int64_t)floor(muq) - wq);
+            B.hi = min(n_q, (int64_t)ceil(muq) + wq);
+            // the larger window is the outer one, so that the lanes stay busy
+            // (the condition |a n_q - b n_p| > num is symmetric in the two sides)
+            const bool a_outer = (A.hi - A.lo) >= (B.hi - B.lo);
+            const SigSide &O = a_outer ? A : B;
+            const SigSide &I = a_outer ? B : A;
+            return (O.hi - O.lo + 1 >= 8 * 64) ? tail_two_pass<MODEL, 8>(L, O, I, num, ll, l1m)
+                                               : tail_two_pass<MODEL, 1>(L, O, I, num, ll, l1m);
+        };
+        double tail = tail_k(SIG_K_NARROW);
+        if (!(tail >= SIG_NARROW_MIN_TAIL)) tail = tail_k(SIG_K_FULL);  // wave-uniform
         const int64_t wq = window_halfwidth(sq), wp = window_halfwidth(sp);
-        SigSide A, B;
-        A.n = n_p;
-        A.mu = mup;
-        A.lmu = log(mup);
-        A.lo = max((int64_t)0, (int64_t)floor(mup) - wp);
-        A.hi = min(n_p, (int64_t)ceil(mup) + wp);
-        B.n = n_q;
-        B.mu = muq;
-        B.lmu = log(muq);
-        B.lo = max((int64_t)0, (int64_t)floor(muq) - wq);
-        B.hi = min(n_q, (int64_t)ceil(muq) + wq);
-        // the larger window is the outer one, so that the lanes stay busy
-        // (the condition |a n_q - b n_p| > num is symmetric in the two sides)
-        const bool a_outer = (A.hi - A.lo) >= (B.hi - B.lo);
-        const SigSide &O = a_outer ? A : B;
-        const SigSide &I = a_outer ? B : A;
-        double tail = (O.hi - O.lo + 1 >= 8 * 64) ? tail_two_pass<MODEL, 8>(L, O, I, num, ll, l1m)
-                                                  : tail_two_pass<MODEL, 1>(L, O, I, num, ll, l1m);
         if constexpr (MODEL == SIG_POISSON) {
             // mass of either Poisson count beyond its sample size
             const double ua = pois_upper_wave(L, n_p, mup, wp), ub = pois_upper_wave(L, n_q, muq, wq);
