@@ -100,7 +100,8 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p)
         p.d = d;
         if (plan_complete(p, N, n_p)) return p;
     }
-    p.waves = 4;
+    // 4 waves per block; 8 at d = 4, whose 68 KB pair table admits two blocks per CU
+    p.waves = d == 4 ? 8 : 4;
     if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 ||
               c->force_waves == 8 || c->force_waves == 16))
         p.waves = c->force_waves;
