@@ -114,14 +114,19 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__rest
     out[tid] = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-// Number of entries of the sorted LDS tile below key (branchless; 0..TILE).
+// The sorted tile in LDS is skewed by one word every 64 entries: the probes
+// of one step of the binary search sit at multiples of TILE/2^k minus one,
+// which without the skew all fall in the same LDS bank.
+__device__ __forceinline__ int skew(int e) { return e + (e >> 6); }
+
+// Number of entries of the sorted, skewed LDS tile below key (branchless; 0..TILE).
 __device__ __forceinline__ int count_below(const uint32_t *tile, uint32_t key)
 {
     int p = 0;
 #pragma unroll
     for (int step = TILE / 2; step >= 1; step >>= 1)
-        if (tile[p + step - 1] < key) p += step;
-    return p + (tile[p] < key ? 1 : 0);
+        if (tile[skew(p + step - 1)] < key) p += step;
+    return p + (tile[skew(p)] < key ? 1 : 0);
 }
 
 // Writes the biased 16-bit rank of dimension m of point i.
@@ -137,12 +142,19 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restr
                                                             const uint32_t *__restrict__ K,
                                                             uint16_t *__restrict__ part)
 {
-    __shared__ uint32_t tile[TILE];
+    __shared__ uint32_t tile[TILE + TILE / 64 + 1];
     const int m = blockIdx.y;
     const int64_t t = blockIdx.x, u = blockIdx.z;
     const int tid = threadIdx.x;
     const uint4 *src = reinterpret_cast<const uint4 *>(K + ((size_t)m * tiles + u) * TILE);
-    reinterpret_cast<uint4 *>(tile)[tid] = src[tid];
+    {
+        const uint4 v = src[tid];  // entries 4 tid .. 4 tid + 3, all in one 64-entry row
+        const int e = skew(4 * tid);
+        tile[e] = v.x;
+        tile[e + 1] = v.y;
+        tile[e + 2] = v.z;
+        tile[e + 3] = v.w;
+    }
     uint32_t key[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
