@@ -106,6 +106,10 @@ int ddks_destroy(ddks_ctx *ctx);
  * significance of the result (as ddks_significance, DDKS_SIG_POISSON for the
  * Poisson model), computed on the device from counts that stay there;
  * otherwise out->S = -1.
+ * Compares: from N = n_p + n_q = 8192 up to N = 2^22 on 16-bit codes of each
+ * dimension's value order (a dimension with more than 65536 distinct values
+ * is coded coarsely and corrected exactly after the sweep), else on fp32;
+ * the result is the same either way.
  * Limits: 1 <= n_p, n_q; n_p + n_q <= 2^31 - 1; 1 <= d <= 8.
  * Errors: DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOMEM, DDKS_E_DEVICE.
  */
@@ -258,12 +262,15 @@ typedef struct ddks_profile {
     uint64_t compares;    /* origin*point*dim compares those sweeps evaluated */
     uint64_t batches;     /* permutation batches timed */
     uint64_t graph_calls; /* ddks_distance calls run as a replayed captured graph */
+    uint64_t shifted_calls; /* ddks_distance calls swept on shifted 16-bit codes plus
+                               corrections (a dimension with more than 65536 distinct values) */
 } ddks_profile;
 
 /*
  * Device-time counters, recorded with HIP events on the context's stream
  * around each kernel launch when the context was created with
- * DDKS_PROFILE_KERNELS (all zero otherwise).  reset != 0 clears them after
+ * DDKS_PROFILE_KERNELS (all zero otherwise; shifted_calls is counted either
+ * way).  reset != 0 clears them after
  * reading.  Errors: DDKS_E_INVALID_ARG.
  */
 int ddks_profile_get(ddks_ctx *ctx, ddks_profile *out, int32_t reset);

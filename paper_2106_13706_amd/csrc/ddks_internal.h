@@ -85,10 +85,36 @@ constexpr int RANK_CTL_WORDS = 16;
 // point, into R.  scratch: rank16_scratch_bytes(N, d) bytes.  ctl: a device
 // block of RANK_CTL_WORDS words.  For N <= 65536 the ranks always fit; for
 // larger N, ctl[0] receives the largest per-dimension count of distinct values
-// and the encoding is valid only when it is <= 65536.
+// and ctl[1 + m] dimension m's, and the encoding is valid only when all are
+// <= 65536 (otherwise see launch_rank16_shift).
 hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch,
                          uint32_t *ctl, hipStream_t s);
 size_t rank16_scratch_bytes(int64_t N, int d);
+
+// N > 65536, after launch_rank16: tables in its scratch.  S: per dimension the
+// N (order key << 32 | index) pairs in sorted order; R32: N x d full dense
+// ranks; RS: per dimension the first sorted position of each rank (d x
+// (N + 1), entry [distinct] = N).
+struct RankTables {
+    const uint64_t *S = nullptr;
+    uint32_t *R32 = nullptr, *RS = nullptr;
+};
+RankTables rank16_tables(void *scratch, int64_t N, int d);
+
+// For each dimension m with more than 65536 distinct values and N <= 65536 <<
+// shift_m (shift_m = 4-bit field m of `shifts`, 0 for the other dimensions):
+// replaces the rank in the tables' R32 by F, the first sorted position of the
+// point's value, and its 16-bit code in R by F >> shift_m.  Compares on the
+// codes are exact up to the points that launch_rank_fixups corrects.
+hipError_t launch_rank16_shift(int64_t N, int d, uint32_t *R, void *scratch, uint32_t shifts, hipStream_t s);
+
+// After a sweep of the shifted encoding with plan.chunks >= 2 (before
+// launch_score): for every origin o, each point x with o's code and a smaller
+// value in some shifted dimension was counted in the orthant of the code
+// compares; moves it to its exact orthant in chunk 0's partial counts (at
+// most 2^shift_m - 1 points per origin and dimension).
+hipError_t launch_rank_fixups(int d, const RankTables &t, int64_t N, int64_t n_p, uint32_t shifts,
+                              uint2 *partial, hipStream_t s);
 
 // The O(2^d N^2) sweep.  With plan.chunks == 1 the epilogue scores in place and
 // writes block_best[group]; otherwise it writes per-chunk partial counts

@@ -328,7 +328,9 @@ __global__ __launch_bounds__(SEG_THREADS) void k_rank_dense(const uint64_t *__re
                                                             int64_t N, int d, int pw, int64_t segs,
                                                             const uint32_t *__restrict__ C,
                                                             uint16_t *__restrict__ R16,
-                                                            uint32_t *__restrict__ distinct_max)
+                                                            uint32_t *__restrict__ distinct_max,
+                                                            uint32_t *__restrict__ R32,
+                                                            uint32_t *__restrict__ RS)
 {
     constexpr int PER = SEG / SEG_THREADS;  // consecutive positions per thread
     __shared__ uint32_t scan[SEG_THREADS];
@@ -340,7 +342,12 @@ __global__ __launch_bounds__(SEG_THREADS) void k_rank_dense(const uint64_t *__re
         uint32_t b = 0;
         for (int64_t h = 0; h < g; ++h) b += C[(size_t)m * segs + h];
         before = b;
-        if (g == segs - 1) atomicMax(distinct_max, b + C[(size_t)m * segs + g]);
+        if (g == segs - 1) {
+            const uint32_t total = b + C[(size_t)m * segs + g];
+            atomicMax(distinct_max, total);
+            distinct_max[1 + m] = total;  // this dimension's count of distinct values
+            RS[(size_t)m * (N + 1) + total] = (uint32_t)N;  // end of the last run
+        }
     }
     uint32_t flags[PER];
     uint32_t c = 0;
@@ -367,8 +374,34 @@ __global__ __launch_bounds__(SEG_THREADS) void k_rank_dense(const uint64_t *__re
         const int64_t i = (int64_t)(uint32_t)Sm[p];
         const int64_t rank = (int64_t)run - 1;
         if (rank < 65536) put_rank(R16, i, pw, m, rank);
+        R32[i * d + m] = (uint32_t)rank;
+        if (flags[e]) RS[(size_t)m * (N + 1) + rank] = (uint32_t)p;  // first sorted position of the rank
         if (m == 0)
             for (int mm = d; mm < 2 * pw; ++mm) R16[(i * pw) * 2 + mm] = 0;
+    }
+}
+
+// A dimension m with more than 65536 distinct values (shift s = 4-bit field m
+// of `shifts`, 0 for the other dimensions): each point's value is identified
+// by F, the first sorted position of that value, which replaces its rank in
+// R32, and its 16-bit code is F >> s (biased).  F is strictly increasing in
+// the value, so compares on the codes are exact except between a point and an
+// origin with the same code and a smaller F, which launch_rank_fixups corrects
+// after the sweep: there are fewer than 2^s of them, ties or not, since they
+// occupy sorted positions [(F_o >> s) << s, F_o).
+__global__ void k_rank_shift(uint32_t *__restrict__ R32, const uint32_t *__restrict__ RS, int64_t N, int d,
+                             int pw, uint32_t shifts, uint16_t *__restrict__ R16)
+{
+    const int64_t total = N * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / d;
+        const int m = (int)(e - i * d);
+        const uint32_t s = (shifts >> (4 * m)) & 15u;
+        if (s == 0) continue;  // the dense rank already fits
+        const uint32_t f = RS[(size_t)m * (N + 1) + R32[e]];
+        R32[e] = f;
+        put_rank(R16, i, pw, m, (int64_t)(f >> s));
     }
 }
 
@@ -385,7 +418,31 @@ size_t rank16_scratch_bytes(int64_t N, int d)
     size_t a = (size_t)d * tiles * TILE * sizeof(uint64_t);
     size_t s = (size_t)d * N * sizeof(uint64_t);
     size_t c = (size_t)d * ((N + SEG - 1) / SEG) * sizeof(uint32_t);
-    return a + s + c + 256;
+    size_t r32 = (size_t)N * d * sizeof(uint32_t);          // full ranks
+    size_t rs = (size_t)d * (N + 1) * sizeof(uint32_t);     // first sorted position per rank
+    return a + s + c + r32 + rs + 256;
+}
+
+RankTables rank16_tables(void *scratch, int64_t N, int d)
+{
+    RankTables t;
+    const int64_t tiles = tiles_of(N);
+    uint64_t *A = (uint64_t *)scratch;
+    t.S = A + (size_t)d * tiles * TILE;
+    uint32_t *C = (uint32_t *)(t.S + (size_t)d * N);
+    t.R32 = C + (size_t)d * ((N + SEG - 1) / SEG);
+    t.RS = t.R32 + (size_t)N * d;
+    return t;
+}
+
+hipError_t launch_rank16_shift(int64_t N, int d, uint32_t *R, void *scratch, uint32_t shifts, hipStream_t st)
+{
+    if (N <= 65536 || shifts == 0) return hipErrorInvalidValue;
+    const RankTables t = rank16_tables(scratch, N, d);
+    const unsigned blocks = (unsigned)std::min<int64_t>((N * d + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_rank_shift, dim3(blocks), dim3(256), 0, st, t.R32, t.RS, N, d,
+                       point_words(PATH_R16, d), shifts, (uint16_t *)R);
+    return hipGetLastError();
 }
 
 size_t sort_columns_scratch_bytes(int64_t N, int C)
@@ -449,13 +506,14 @@ hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *sc
     uint64_t *S = A + (size_t)d * tiles * TILE;
     uint32_t *C = (uint32_t *)(S + (size_t)d * N);
     const int64_t segs = (N + SEG - 1) / SEG;
+    const RankTables tabs = rank16_tables(scratch, N, d);
     hipLaunchKernelGGL(k_rank_place, dim3(blocks, d), dim3(256), 0, st, A, N, tiles, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_flags, dim3((unsigned)segs, d), dim3(SEG_THREADS), 0, st, S, N, segs, C,
                        ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_dense, dim3((unsigned)segs, d), dim3(SEG_THREADS), 0, st, S, N, d, pw,
-                       segs, C, R16, ctl);
+                       segs, C, R16, ctl, tabs.R32, tabs.RS);
     return hipGetLastError();
 }
 

@@ -127,9 +127,10 @@ int choose_path(ddks_ctx * /*c*/, int /*d*/, int64_t N, uint32_t flags)
     return N >= 8192 ? PATH_R16 : PATH_F32;
 }
 
-int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok)
+int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok, uint32_t *shifts)
 {
     *ok = false;
+    *shifts = 0;
     const int pw = point_words(PATH_R16, d);
     int st = ensure(c, c->zr, (size_t)N * pw * sizeof(uint32_t), "rank encoding");
     if (st) return st;
@@ -143,17 +144,33 @@ int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok)
         *ok = true;  // at most N distinct values per dimension
         return DDKS_OK;
     }
-    st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, c->rank_ctl_dev, sizeof(uint32_t),
-                                     hipMemcpyDeviceToHost, c->stream), "D2H distinct count");
+    st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, c->rank_ctl_dev, (size_t)(1 + d) * sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, c->stream), "D2H distinct counts");
     if (!st) st = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     if (st) return st;
-    *ok = *c->rank_distinct_host <= 65536u;
+    uint32_t packed = 0;
+    for (int m = 0; m < d; ++m) {
+        const uint64_t distinct = c->rank_distinct_host[1 + m];
+        int sh = 0;
+        if (distinct > 65536)
+            while (sh <= RANK_MAX_SHIFT && (uint64_t)N > (65536ull << sh)) ++sh;
+        if (sh > RANK_MAX_SHIFT) return DDKS_OK;  // fp32 compares
+        packed |= (uint32_t)sh << (4 * m);
+    }
+    if (packed) {
+        st = hip_check(c, launch_rank16_shift(N, d, (uint32_t *)c->zr.ptr, c->rank_scratch.ptr, packed, c->stream),
+                       "rank shift launch");
+        if (st) return st;
+    }
+    *ok = true;
+    *shifts = packed;
     return DDKS_OK;
 }
 
 int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
-              int64_t n_q, uint32_t *counts_dev, ResultDev *res, hipStream_t s)
+              int64_t n_q, uint32_t *counts_dev, ResultDev *res, hipStream_t s, uint32_t shifts)
 {
+    if (shifts && plan.chunks < 2) return fail(c, DDKS_E_DEVICE, "shifted ranks need a chunked plan");
     int st = ensure(c, c->block_best, (size_t)plan.groups * sizeof(BlockBest), "block results");
     if (st) return st;
     uint2 *partial = nullptr;
@@ -169,6 +186,12 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
     st = hip_check(c, launch_sweep(plan, zdata, N, n_p, n_q, partial, bb, counts_dev, s), "sweep launch");
     if (st) return st;
     if (prof) (void)hipEventRecord(c->ev[1], s);
+    if (shifts) {
+        st = hip_check(c, launch_rank_fixups(plan.d, rank16_tables(c->rank_scratch.ptr, N, plan.d), N, n_p, shifts,
+                                             partial, s),
+                       "rank fixup launch");
+        if (st) return st;
+    }
     if (plan.chunks > 1) {
         st = hip_check(c, launch_score(plan, N, n_p, n_q, partial, bb, counts_dev, s), "score launch");
         if (st) return st;
@@ -516,9 +539,10 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
     if (st) return st;
     const void *zdata = Z;
+    uint32_t shifts = 0;  // per-dimension shifts, 4 bits each
     if (path == PATH_R16) {
         bool ok = false;
-        st = encode_rank16(c, N, d, &ok);
+        st = encode_rank16(c, N, d, &ok, &shifts);
         if (st) return st;
         if (ok) zdata = c->zr.ptr;
         else path = PATH_F32;
@@ -526,7 +550,13 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     st = tune_sweep(c, path, d, N, n_p, n_q, zdata);
     if (st) return st;
     SweepPlan plan = plan_for(c, path, d, N, n_p);
-    st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, with_S ? c->result_dev : c->result_host, s);
+    if (shifts && plan.chunks < 2) {
+        // the corrections go into the chunks' partial counts
+        plan.chunks = 2;
+        if (!plan_complete(plan, N, n_p)) return fail(c, DDKS_E_DEVICE, "no launch shape for shifted codes");
+    }
+    if (shifts) c->prof.shifted_calls += 1;
+    st = run_sweep(c, plan, zdata, N, n_p, n_q, counts_dev, with_S ? c->result_dev : c->result_host, s, shifts);
     if (st) return st;
     if (with_S) {
         // S of the statistic just found: num is read on the device

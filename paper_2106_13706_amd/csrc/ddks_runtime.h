@@ -99,8 +99,11 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p);
 // Runs the sweep + score + reduce of one test whose points are already in a
 // device buffer (fp32 N x d at zf, and when path == PATH_R16 the rank
 // encoding at zr).  Leaves the result in c->result_dev; does not synchronise.
+// shifts != 0: zdata is the shifted rank encoding of c->rank_scratch's
+// tables (4-bit shift per dimension, plan.chunks >= 2); the rank-group
+// corrections run between sweep and score.
 int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
-              int64_t n_q, uint32_t *counts_dev, ddks::ResultDev *res, hipStream_t s);
+              int64_t n_q, uint32_t *counts_dev, ddks::ResultDev *res, hipStream_t s, uint32_t shifts = 0);
 
 // Folds the events recorded by the last run_sweep into c->prof (after the
 // stream has been synchronised).
@@ -109,10 +112,15 @@ void profile_collect(ddks_ctx *c);
 // Chooses the path for a test (fp32 or rank-16) given the caller's flags.
 int choose_path(ddks_ctx *c, int d, int64_t N, uint32_t flags);
 
-// Encodes the fp32 points in c->z (N x d) as int16 ranks into c->zr.  Returns
-// DDKS_OK and sets *ok = false when some dimension has more than 65536 distinct
-// values (the caller then falls back to the fp32 path).
-int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok);
+// Encodes the fp32 points in c->z (N x d) as int16 ranks into c->zr.  A
+// dimension with more than 65536 distinct values is coded by shifted first
+// sorted positions (F >> shift_m, the smallest shift_m with N <= 65536 <<
+// shift_m, packed 4 bits per dimension into *shifts) and the sweep needs the
+// corrections of launch_rank_fixups (run_sweep with shifts); past
+// N = 65536 << RANK_MAX_SHIFT, *ok = false and the caller falls back to the
+// fp32 path.
+constexpr int RANK_MAX_SHIFT = 6;
+int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok, uint32_t *shifts);
 
 // Serving lifecycle (ddks_serve.cpp).
 int serve_start(ddks_ctx *c);

@@ -86,7 +86,7 @@ class _Profile(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_uint64), ("sweep_ms", ctypes.c_double),
                 ("score_ms", ctypes.c_double), ("batch_ms", ctypes.c_double),
                 ("compares", ctypes.c_uint64), ("batches", ctypes.c_uint64),
-                ("graph_calls", ctypes.c_uint64)]
+                ("graph_calls", ctypes.c_uint64), ("shifted_calls", ctypes.c_uint64)]
 
 
 @dataclass
