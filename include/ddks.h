@@ -107,9 +107,9 @@ int ddks_destroy(ddks_ctx *ctx);
  * Poisson model), computed on the device from counts that stay there;
  * otherwise out->S = -1.
  * Compares: from N = n_p + n_q = 8192 up to N = 2^22 on 16-bit codes of each
- * dimension's value order (a dimension with more than 65536 distinct values
- * is coded coarsely and corrected exactly after the sweep), else on fp32;
- * the result is the same either way.
+ * dimension's value order (past 65536 distinct values, or past 65536 points
+ * in a call replayed as a graph, a dimension is coded coarsely and corrected
+ * exactly after the sweep), else on fp32; the result is the same either way.
  * Limits: 1 <= n_p, n_q; n_p + n_q <= 2^31 - 1; 1 <= d <= 8.
  * Errors: DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOMEM, DDKS_E_DEVICE.
  */
@@ -216,6 +216,8 @@ typedef struct ddks_serve_stats {
     uint64_t resident_bytes;   /* device bytes currently held by admitted requests */
     double busy_us;            /* device time covered by at least one retired launch
                                   (copies, encodings, sweeps, reductions) */
+    uint64_t shifted_tests;    /* launched tests swept on shifted 16-bit codes plus
+                                  corrections (more than 65536 points) */
 } ddks_serve_stats;
 
 /*
@@ -223,10 +225,11 @@ typedef struct ddks_serve_stats {
  * requests that arrive while others run are admitted as device memory and
  * queue slots free up; tests below 16384 points are packed into shared
  * launches, larger ones are swept with the point-chunked plan of a plain
- * call on one of the serve_streams streams).  The library copies P and Q
+ * call on one of the serve_streams streams; compares on 16-bit codes from
+ * 16384 up to 131072 points, else fp32).  The library copies P and Q
  * before returning; the caller may free them at once.  The first submit
  * starts the loop: per stream it holds a 16-bit rank-encoding scratch and a
- * 128 MB partial-count buffer, each only if the budget leaves a 64 MB
+ * 512 MB partial-count buffer, each only if the budget leaves a 64 MB
  * arena beside it (otherwise that path is not used), and an arena of what
  * the budget then leaves, up to 8 GB, for the admitted requests.
  * Thread-safe.  *ticket identifies the request for ddks_serve_poll.

@@ -127,6 +127,20 @@ int choose_path(ddks_ctx * /*c*/, int /*d*/, int64_t N, uint32_t flags)
     return N >= 8192 ? PATH_R16 : PATH_F32;
 }
 
+int rank_position_shift(int64_t N)
+{
+    int sh = 0;
+    while (sh <= RANK_MAX_SHIFT && (uint64_t)N > (65536ull << sh)) ++sh;
+    return sh <= RANK_MAX_SHIFT ? sh : -1;
+}
+
+uint32_t shifts_all(int shift, int d)
+{
+    uint32_t packed = 0;
+    for (int m = 0; m < d; ++m) packed |= (uint32_t)shift << (4 * m);
+    return packed;
+}
+
 int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok, uint32_t *shifts)
 {
     *ok = false;
@@ -148,13 +162,12 @@ int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok, uint32_t *shifts)
                                      hipMemcpyDeviceToHost, c->stream), "D2H distinct counts");
     if (!st) st = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     if (st) return st;
+    // a dimension whose dense ranks fit keeps them (nothing to correct there)
     uint32_t packed = 0;
     for (int m = 0; m < d; ++m) {
-        const uint64_t distinct = c->rank_distinct_host[1 + m];
-        int sh = 0;
-        if (distinct > 65536)
-            while (sh <= RANK_MAX_SHIFT && (uint64_t)N > (65536ull << sh)) ++sh;
-        if (sh > RANK_MAX_SHIFT) return DDKS_OK;  // fp32 compares
+        if (c->rank_distinct_host[1 + m] <= 65536u) continue;
+        const int sh = rank_position_shift(N);
+        if (sh < 0) return DDKS_OK;  // fp32 compares
         packed |= (uint32_t)sh << (4 * m);
     }
     if (packed) {
@@ -230,6 +243,7 @@ struct DistArgs {
     const float *P, *Q;
     int64_t n_p, n_q;
     int d, path;
+    uint32_t shifts;  // rank path past 65536 points: shifted codes in every dimension
     uint32_t *counts;
     SweepPlan plan;
 };
@@ -251,9 +265,9 @@ static int prepare_distance(ddks_ctx *c, const DistArgs &a)
     return st;
 }
 
-// Ingest, rank encoding (N <= 65536 only: no host decision) and, if
-// with_sweep, the sweep of device-resident P and Q; the result lands in the
-// pinned c->result_host.
+// Ingest, rank encoding (no host decision: past 65536 points every dimension
+// takes the shifted codes) and, if with_sweep, the sweep of device-resident P
+// and Q; the result lands in the pinned c->result_host.
 static int enqueue_distance(ddks_ctx *c, const DistArgs &a, hipStream_t s, bool with_sweep)
 {
     const int64_t N = a.n_p + a.n_q;
@@ -265,11 +279,14 @@ static int enqueue_distance(ddks_ctx *c, const DistArgs &a, hipStream_t s, bool 
     if (a.path == PATH_R16) {
         st = hip_check(c, launch_rank16(Z, N, a.d, (uint32_t *)c->zr.ptr, c->rank_scratch.ptr,
                                         c->rank_ctl_dev, s), "rank launch");
+        if (!st && a.shifts)
+            st = hip_check(c, launch_rank16_shift(N, a.d, (uint32_t *)c->zr.ptr, c->rank_scratch.ptr, a.shifts, s),
+                           "rank shift launch");
         if (st) return st;
         zdata = c->zr.ptr;
     }
     if (!with_sweep) return DDKS_OK;
-    return run_sweep(c, a.plan, zdata, N, a.n_p, a.n_q, a.counts, c->result_host, s);
+    return run_sweep(c, a.plan, zdata, N, a.n_p, a.n_q, a.counts, c->result_host, s, a.shifts);
 }
 
 // Waits for the call's work, copies host counts if asked, fills *out.
@@ -446,14 +463,15 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     int path = choose_path(c, d, N, flags);
     const bool with_S = (flags & DDKS_WITH_SIGNIFICANCE) != 0;
 
-    // Device-resident inputs and outputs, a launch shape already known and no
-    // decision on the host halfway (the rank encoding of more than 65536
-    // points checks its distinct counts on the host): the whole call is one
-    // captured graph, replayed while its key matches.  With kernel profiling
-    // the graph stops before the sweep, which is launched between timing
-    // events (events recorded inside a graph cannot be timed).
-    const bool graphable = c->dist_graphs && dev && !with_S && (path == PATH_F32 || N <= 65536) &&
-                           !tune_pending(c, path, d, N);
+    // Device-resident inputs and outputs and a launch shape already known:
+    // the whole call is one captured graph, replayed while its key matches.
+    // No decision may wait on the host halfway, so past 65536 points the rank
+    // path codes every dimension by shifted positions (an eager call reads the
+    // distinct counts first and keeps the dense ranks where they fit).  With
+    // kernel profiling the graph stops before the sweep, which is launched
+    // between timing events (events recorded inside a graph cannot be timed).
+    const bool graphable = c->dist_graphs && dev && !with_S &&
+                           (path == PATH_F32 || rank_position_shift(N) >= 0) && !tune_pending(c, path, d, N);
     if (graphable) {
         DistArgs a;
         a.P = P;
@@ -462,8 +480,13 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
         a.n_q = n_q;
         a.d = d;
         a.path = path;
+        a.shifts = path == PATH_R16 && N > 65536 ? shifts_all(rank_position_shift(N), d) : 0;
         a.counts = counts_dev;
         a.plan = plan_for(c, path, d, N, n_p);
+        if (a.shifts && a.plan.chunks < 2) {
+            a.plan.chunks = 2;  // the corrections go into the chunks' partial counts
+            if (!plan_complete(a.plan, N, n_p)) return fail(c, DDKS_E_DEVICE, "no launch shape for shifted codes");
+        }
         st = prepare_distance(c, a);
         if (st) return st;
         const std::vector<uint64_t> key = {
@@ -504,10 +527,11 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
         if (c->dist_exec) {
             st = hip_check(c, hipGraphLaunch(c->dist_exec, s), "graph launch");
             if (st) return st;
+            if (a.shifts) c->prof.shifted_calls += 1;
             if (c->profile) {
                 c->prof.graph_calls += 1;
                 const void *zdata = path == PATH_R16 ? c->zr.ptr : c->z.ptr;
-                st = run_sweep(c, a.plan, zdata, N, n_p, n_q, counts_dev, c->result_host, s);
+                st = run_sweep(c, a.plan, zdata, N, n_p, n_q, counts_dev, c->result_host, s, a.shifts);
                 if (st) return st;
             }
             return finish_distance(c, n_p, n_q, d, out, nullptr, nullptr, 0, false);

@@ -120,6 +120,12 @@ int choose_path(ddks_ctx *c, int d, int64_t N, uint32_t flags);
 // N = 65536 << RANK_MAX_SHIFT, *ok = false and the caller falls back to the
 // fp32 path.
 constexpr int RANK_MAX_SHIFT = 6;
+// The shift that codes N sorted positions in 16 bits: 0 for N <= 65536, -1
+// past 65536 << RANK_MAX_SHIFT.
+int rank_position_shift(int64_t N);
+// `shift` in the 4-bit fields of all d dimensions: the coding of calls that
+// cannot wait for the distinct counts (captured graphs, serving).
+uint32_t shifts_all(int shift, int d);
 int encode_rank16(ddks_ctx *c, int64_t N, int d, bool *ok, uint32_t *shifts);
 
 // Serving lifecycle (ddks_serve.cpp).

@@ -16,7 +16,11 @@
 //           every CU busy to the end of a large test;
 //           mid-size tests (SERVE_R16_MIN <= N <= 65536) are first rank
 //           encoded on the device for the 16-bit compare path (at most N
-//           distinct values per dimension, so the ranks always fit);
+//           distinct values per dimension, so the ranks always fit); larger
+//           solo tests up to SERVE_R16_MAX points take shifted position codes
+//           in every dimension, encoded, swept and corrected one after
+//           another on the slot's stream (the corrections read the slot's
+//           rank tables);
 //   retire  finished launches (HIP events) hand their results to the
 //           tickets, free their arena space and wake pollers.
 #include <string.h>
@@ -83,9 +87,13 @@ struct Arena {
 static constexpr int64_t SERVE_R16_MIN = 16384;
 
 // Smallest test swept on its own with a chunked plan, and the per-slot
-// buffer for the partial counts of its chunks (they grow with 2^d).
+// buffer for the partial counts of its chunks (they grow with 2^d; two chunks
+// of a d = 8 test of SERVE_R16_MAX points fill it).
 static constexpr int64_t SERVE_SOLO_MIN = 16384;
-static constexpr size_t SERVE_SOLO_PARTIAL = 128ull << 20;
+static constexpr size_t SERVE_SOLO_PARTIAL = 512ull << 20;
+// Largest test on the 16-bit compare path (the per-slot rank scratch is sized
+// for it); past 65536 points with shifted codes, solo sweeps only.
+static constexpr int64_t SERVE_R16_MAX = 131072;
 
 struct Req {
     uint64_t ticket = 0;
@@ -93,6 +101,7 @@ struct Req {
     int64_t n_p = 0, n_q = 0, N = 0;
     int hists = 1;            // LDS histograms per block of its packed sweep
     int path = PATH_F32;      // compare path of its sweep
+    uint32_t shifts = 0;      // shifted position codes (PATH_R16 past 65536 points)
     bool solo = false;        // swept on its own with `plan` (not packed)
     SweepPlan plan;
     std::vector<float> data;  // P then Q
@@ -146,7 +155,7 @@ struct Serve {
     std::string error;
     // stats
     uint64_t submitted = 0, completed = 0, rej_again = 0, rej_nomem = 0, launches = 0,
-             launched_tests = 0;
+             launched_tests = 0, shifted_tests = 0;
     std::vector<double> lat_us;
     // device time: [start, end) of every retired launch in ms after `ref`
     hipEvent_t ref = nullptr;
@@ -236,7 +245,7 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
             error = "H2D request copy failed";
             return false;
         }
-        if (r->path == PATH_R16 &&
+        if (r->path == PATH_R16 && !r->shifts &&
             launch_rank16((const float *)zf, r->N, r->d, (uint32_t *)zr, s.rank_scratch,
                           s.rank_ctl, s.stream) != hipSuccess) {
             error = "rank encoding launch failed";
@@ -273,13 +282,25 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         error = "packed reduction launch failed";
         return false;
     }
-    // solo tests: sweep (+ score of the chunks' partial counts) + reduce
+    // solo tests: (shifted encoding +) sweep (+ corrections) (+ score of the
+    // chunks' partial counts) + reduce
     for (size_t i = npacked; i < batch.size(); ++i) {
         Req *r = batch[i];
         const PackedTest &t = s.tests_h[i];
         BlockBest *tbb = bb + t.bb_offset;
         uint2 *part = r->plan.chunks > 1 ? s.partial : nullptr;
+        if (r->shifts) {
+            const float *zf = (const float *)(base + r->off);
+            if (launch_rank16(zf, r->N, r->d, (uint32_t *)t.Z, s.rank_scratch, s.rank_ctl, s.stream) != hipSuccess ||
+                launch_rank16_shift(r->N, r->d, (uint32_t *)t.Z, s.rank_scratch, r->shifts, s.stream) !=
+                    hipSuccess) {
+                error = "rank encoding launch failed";
+                return false;
+            }
+        }
         if (launch_sweep(r->plan, t.Z, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess ||
+            (r->shifts && launch_rank_fixups(r->d, rank16_tables(s.rank_scratch, r->N, r->d), r->N, r->n_p,
+                                             r->shifts, part, s.stream) != hipSuccess) ||
             (part && launch_score(r->plan, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess) ||
             launch_reduce(tbb, r->plan.groups, s.flags_d, s.res_d + i, s.stream) != hipSuccess) {
             error = "solo sweep launch failed";
@@ -297,6 +318,7 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
     s.busy = true;
     launches += 1;
     launched_tests += batch.size();
+    for (const Req *r : batch) shifted_tests += r->shifts ? 1 : 0;
     return true;
 }
 
@@ -429,7 +451,8 @@ int serve_start(ddks_ctx *c)
     // leaves a 64 MB arena; otherwise every test takes the fp32 path.  Then
     // the arena takes what the budget leaves, up to 8 GB.
     const size_t ctl_bytes = RANK_CTL_WORDS * sizeof(uint32_t);
-    const size_t rank_bytes = rank16_scratch_bytes(65536, 8) + ctl_bytes;
+    const size_t rank_bytes =
+        std::max(rank16_scratch_bytes(65536, 8), rank16_scratch_bytes(SERVE_R16_MAX, 8)) + ctl_bytes;
     {
         const uint64_t used = c->used.load();
         const uint64_t need = (uint64_t)sv->slots.size() * rank_bytes + (64ull << 20);
@@ -602,20 +625,34 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
         return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
     }
     r->path = (sv->use_r16 && N >= SERVE_R16_MIN && N <= 65536) ? PATH_R16 : PATH_F32;
-    if (sv->use_solo && N >= SERVE_SOLO_MIN) {
-        // the launch heuristics of a plain call (not the tuner's entries,
-        // which the calling threads may be updating), with no more chunks than
-        // the slot's partial-count buffer holds; a single chunk takes 16 waves
-        // per block, to fill the CUs where LDS admits few blocks
-        SweepPlan p = plan_for(nullptr, r->path, req->d, N, req->n_p);
+    // the launch heuristics of a plain call (not the tuner's entries, which
+    // the calling threads may be updating), with no more chunks than the
+    // slot's partial-count buffer holds; a single chunk takes 16 waves per
+    // block, to fill the CUs where LDS admits few blocks.  Shifted codes need
+    // two chunks at least (their corrections go into the partial counts).
+    auto solo_plan = [&](int path, bool shifted, SweepPlan *out) {
+        SweepPlan p = plan_for(nullptr, path, req->d, N, req->n_p);
         const size_t per_chunk = (size_t)p.groups * ((size_t)1 << p.d) * 64 * sizeof(uint2);
+        if (shifted && p.chunks < 2) p.chunks = 2;
         if (p.chunks > 1 && (size_t)p.chunks * per_chunk > SERVE_SOLO_PARTIAL) {
             p.chunks = std::max<int64_t>(1, (int64_t)(SERVE_SOLO_PARTIAL / per_chunk));
             if (p.chunks == 1) p.waves = 16;
-            if (!plan_complete(p, N, req->n_p)) p.hists = 0;
         }
+        if (shifted && p.chunks < 2) return false;
+        if (!plan_complete(p, N, req->n_p)) return false;
         const size_t pb = p.chunks > 1 ? (size_t)p.chunks * per_chunk : 0;
-        if (p.hists > 0 && pb <= SERVE_SOLO_PARTIAL) {
+        if (pb > SERVE_SOLO_PARTIAL) return false;
+        *out = p;
+        return true;
+    };
+    if (sv->use_solo && N >= SERVE_SOLO_MIN) {
+        SweepPlan p;
+        if (sv->use_r16 && N > 65536 && N <= SERVE_R16_MAX && solo_plan(PATH_R16, true, &p)) {
+            r->path = PATH_R16;
+            r->shifts = shifts_all(rank_position_shift(N), req->d);
+            r->solo = true;
+            r->plan = p;
+        } else if (solo_plan(r->path, false, &p)) {
             r->solo = true;
             r->plan = p;
         }
@@ -687,6 +724,7 @@ int ddks_serve_stats_get(ddks_ctx *c, ddks_serve_stats *out, int32_t reset)
     out->rejected_again = sv->rej_again;
     out->rejected_nomem = sv->rej_nomem;
     out->launches = sv->launches;
+    out->shifted_tests = sv->shifted_tests;
     out->mean_batch = sv->launches ? (double)sv->launched_tests / (double)sv->launches : 0.0;
     out->resident_bytes = sv->arena.size;
     for (auto &kv : sv->arena.free_) out->resident_bytes -= kv.second;
@@ -717,7 +755,7 @@ int ddks_serve_stats_get(ddks_ctx *c, ddks_serve_stats *out, int32_t reset)
     out->busy_us = busy * 1e3;
     if (reset) {
         sv->submitted = sv->completed = sv->rej_again = sv->rej_nomem = 0;
-        sv->launches = sv->launched_tests = 0;
+        sv->launches = sv->launched_tests = sv->shifted_tests = 0;
         sv->lat_us.clear();
         sv->spans.clear();
     }

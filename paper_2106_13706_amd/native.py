@@ -74,7 +74,8 @@ class _ServeStats(ctypes.Structure):
                 ("rejected_again", ctypes.c_uint64), ("rejected_nomem", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("p50_latency_us", ctypes.c_double),
                 ("p99_latency_us", ctypes.c_double), ("mean_batch", ctypes.c_double),
-                ("resident_bytes", ctypes.c_uint64), ("busy_us", ctypes.c_double)]
+                ("resident_bytes", ctypes.c_uint64), ("busy_us", ctypes.c_double),
+                ("shifted_tests", ctypes.c_uint64)]
 
 
 class _PermSummary(ctypes.Structure):

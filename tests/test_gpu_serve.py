@@ -144,8 +144,9 @@ def test_queue_full_and_errors():
 
 def test_rank_encoded_requests(oracle_mod):
     """Mid-size tests (16384 <= N <= 65536) are rank encoded on the device
-    and swept with 16-bit compares; smaller and larger ones keep fp32.  A mix
-    of both, with ties and signed zeros in some, against the oracle."""
+    and swept with 16-bit compares, larger ones up to 131072 points on
+    shifted codes; smaller ones keep fp32.  A mix of all three, with ties and
+    signed zeros in some, against the oracle."""
     from paper_2106_13706_amd import native
     g = np.random.default_rng(21)
     shapes = [(9000, 8000, 3), (20000, 15000, 5), (30000, 35000, 2), (12000, 5000, 8),

@@ -133,3 +133,61 @@ def test_largest_shift(ctx, oracle_mod):
     r1 = ctx.distance(P1, Q1)
     assert ctx.profile()["shifted_calls"] == before["shifted_calls"]
     assert key(ctx.distance(P1, Q1, flags=DDKS_FORCE_F32)) == key(r1)
+
+
+def test_graph_replays_shifted_codes(oracle_mod):
+    """Device-resident inputs past 65536 points run as a captured graph that
+    codes every dimension by shifted positions (no host read of the distinct
+    counts).  Replays over new contents of the same buffers, with eager calls
+    between them, each against the oracle; ties in every dimension included
+    (there an eager call would keep the dense ranks)."""
+    import torch
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(31)
+    n_p, n_q, d = 40000, 36000, 3
+    P = torch.empty((n_p, d), dtype=torch.float32, device="cuda")
+    Q = torch.empty((n_q, d), dtype=torch.float32, device="cuda")
+    with native.Context(flags=native.DDKS_NO_AUTOTUNE) as ctx:
+        for rep in range(3):
+            Ph = g.standard_normal((n_p, d)).astype(np.float32)
+            Qh = (g.standard_normal((n_q, d)) * 1.1).astype(np.float32)
+            if rep == 1:  # few distinct values in every dimension
+                Ph = (np.rint(Ph * 8) / 8).astype(np.float32)
+                Qh = (np.rint(Qh * 8) / 8).astype(np.float32)
+            P.copy_(torch.from_numpy(Ph))
+            Q.copy_(torch.from_numpy(Qh))
+            print(f"  graph replay {rep}", flush=True)
+            before = ctx.profile()["shifted_calls"]
+            r = ctx.distance(P, Q)
+            assert ctx.profile()["shifted_calls"] == before + 1
+            eager = ctx.distance(Ph, Qh)  # host inputs: the eager path
+            o = oracle_mod.distance(Ph, Qh, counts=False, threads=THREADS)
+            assert key(r) == key(eager) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+
+
+def test_serving_large_tests_on_shifted_codes(oracle_mod):
+    """Serving sweeps solo tests of 65537..131072 points on shifted codes
+    (encoded, swept and corrected back to back on the slot's stream), mixed
+    with packed and mid-size tests in the same batches; every result against
+    the oracle, and the stats count the shifted ones."""
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(41)
+    shapes = [(40000, 30000, 8), (50000, 50001, 2), (3000, 2000, 3), (45000, 40000, 5),
+              (20000, 20000, 4), (65537, 1, 1), (70000, 61072, 3)]
+    big = sum(1 for a, b, _ in shapes if a + b > 65536)
+    reqs = []
+    for i, (n_p, n_q, d) in enumerate(shapes):
+        P = g.standard_normal((n_p, d)).astype(np.float32)
+        Q = (g.standard_normal((n_q, d)) * 1.05 + 0.02).astype(np.float32)
+        if i % 3 == 1:
+            P[:, 0] = np.rint(P[:, 0] * 4) / 4  # heavy ties in one dimension
+        reqs.append((P, Q))
+    with native.Context(serve_streams=2) as ctx:
+        tickets = [ctx.serve_submit(P, Q) for P, Q in reqs]
+        got = [ctx.serve_poll(t, timeout_us=-1) for t in tickets]
+        st = ctx.serve_stats()
+    assert st["shifted_tests"] == big
+    for (P, Q), r in zip(reqs, got):
+        print(f"  served n_p={len(P)} n_q={len(Q)} d={P.shape[1]}", flush=True)
+        o = oracle_mod.distance(P, Q, counts=False, threads=THREADS)
+        assert key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
