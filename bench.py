@@ -87,6 +87,41 @@ def cpu_baseline(P, Q, compares):
                          f"{len(times)} run(s), {med:.2f} s each"}
 
 
+def bench_small(native, torch, dev, calls=300):
+    """The launch-bound small test (d = 3, 500 + 500): per-call latency with
+    host inputs (eager launches, H2D copy included) and with device-resident
+    inputs (one captured graph per call), each call timed on its own; and the
+    sweep kernel's device time from HIP events in a profiled context."""
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.gaussian_shift()
+    Pt, Qt = torch.from_numpy(P).to(dev), torch.from_numpy(Q).to(dev)
+    N = len(P) + len(Q)
+    out = {"workload": "gaussian_shift_d3_500", "compares": N * N * P.shape[1]}
+
+    def lat(ctx, a, b):
+        for _ in range(20):
+            r = ctx.distance(a, b)
+        ts = []
+        for _ in range(calls):
+            t0 = time.perf_counter()
+            r = ctx.distance(a, b)
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return r, {"p50_us": ts[len(ts) // 2] * 1e6, "p99_us": ts[int(0.99 * (len(ts) - 1))] * 1e6}
+
+    with native.Context() as ctx:
+        r_h, out["host_inputs"] = lat(ctx, P, Q)
+        r_d, out["device_inputs_graph"] = lat(ctx, Pt, Qt)
+    with native.Context(flags=native.DDKS_PROFILE_KERNELS) as ctx:
+        lat(ctx, Pt, Qt)
+        p = ctx.profile()
+    out["sweep_kernel_us"] = p["sweep_ms"] / max(1, p["sweeps"]) * 1e3
+    out["num"], out["den"] = r_d.num, r_d.den
+    if (r_h.num, r_h.argmax_origin) != (r_d.num, r_d.argmax_origin):
+        raise SystemExit("small workload: host and device inputs disagree")
+    return out
+
+
 def bench_significance(ctx, native, torch, Pt, Qt, workload, reps=5):
     """ddks_distance with the analytic significance of Sec. 3 computed on the
     device in the same call (binomial and Poisson models), against the plain
@@ -157,7 +192,7 @@ def bench_rdks(ctx, torch, dev, reps=5):
     return out
 
 
-EXTRAS = ("mixture", "significance", "vdks", "rdks", "power", "permutation", "serving")
+EXTRAS = ("small", "mixture", "significance", "vdks", "rdks", "power", "permutation", "serving")
 
 
 def bench_power(ctx_factory):
@@ -404,6 +439,9 @@ def main():
     unknown = want - set(EXTRAS)
     if unknown:
         raise SystemExit(f"unknown extras: {sorted(unknown)} (known: {', '.join(EXTRAS)})")
+    if "small" in want:
+        _log("[bench] extra: gaussian_shift_d3_500 latency")
+        extras["gaussian_shift_d3_500"] = bench_small(native, torch, dev)
     if "mixture" in want:
         _log("[bench] extra: mixture_grid_d6_100000")
         P3, Q3 = workloads.mixture_grid()

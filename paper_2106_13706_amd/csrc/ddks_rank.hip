@@ -20,7 +20,9 @@
 // N > 65536:
 //   1. k_rank_tiles   sorts tiles of (key, index) pairs (bitonic, in
 //                     registers, wave shuffles and LDS);
-//   2. k_rank_place   places each pair at its sorted position,
+//   2. k_rank_place_count adds up, per pair, the pairs below it in every
+//                     tile (binary searches in LDS-staged tiles), and
+//      k_rank_scatter writes each pair at that sorted position;
 //      k_rank_flags   counts first occurrences per segment,
 //      k_rank_dense   dense rank = number of distinct values below, from the
 //                     segment counts and a block scan; records the
@@ -196,10 +198,13 @@ struct Pair4 {
     uint64_t v[4];
 };
 
+// S != nullptr: one tile holds the whole column, written sorted to S.
+// Otherwise the sorted tile goes to A, and pos (the sorted positions that
+// k_rank_place_count accumulates) is cleared at the same entries.
 template <int T>
 __global__ __launch_bounds__(T / 4) void k_rank_tiles(const float *__restrict__ Z, int64_t N, int d,
                                                       int64_t tiles, uint64_t *__restrict__ A,
-                                                      uint64_t *__restrict__ S)
+                                                      uint64_t *__restrict__ S, uint32_t *__restrict__ pos)
 {
     constexpr int THREADS = T / 4;
     constexpr int LOG_T = T == 256 ? 8 : (T == 1024 ? 10 : 12);
@@ -258,43 +263,99 @@ __global__ __launch_bounds__(T / 4) void k_rank_tiles(const float *__restrict__ 
         for (int r = 0; r < 4; ++r)
             if (e0 + r < N) out[e0 + r] = v[r];
     } else {
-        uint64_t *out = A + ((size_t)m * tiles + t) * T;
+        const size_t base = ((size_t)m * tiles + t) * T;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[e0 + r] = v[r];
-    }
-}
-
-// Number of entries of the sorted tile below v.
-__device__ __forceinline__ int lower_bound_tile(const uint64_t *__restrict__ tile, uint64_t v)
-{
-    int lo = 0, n = TILE;
-    while (n > 0) {
-        int half = n >> 1;
-        if (tile[lo + half] < v) {
-            lo += half + 1;
-            n -= half + 1;
-        } else {
-            n = half;
+        for (int r = 0; r < 4; ++r) {
+            A[base + e0 + r] = v[r];
+            pos[base + e0 + r] = 0u;
         }
     }
-    return lo;
 }
 
+// Sorted position of every (key, index) pair of several sorted tiles: work
+// item w of column m is (tile t, span s) = (w mod tiles, w / tiles); its block
+// stages the tiles of span s in LDS one after another and adds, for each pair
+// of tile t, the number of entries below it (the pairs are all distinct, so
+// the sum over all tiles, its own included, is its sorted position).  The
+// tile is stored skewed by one entry every 32, so that the probes of one
+// search step, 4096 / 2^k entries apart, spread over the banks.
+static constexpr int PLACE_THREADS = TILE / 4;  // four pairs of tile t per thread
+__device__ __forceinline__ int place_skew(int e) { return e + (e >> 5); }
 
-__global__ void k_rank_place(const uint64_t *__restrict__ A, int64_t N, int64_t tiles,
-                             uint64_t *__restrict__ S)
+__global__ __launch_bounds__(PLACE_THREADS) void k_rank_place_count(const uint64_t *__restrict__ A,
+                                                                    int64_t tiles, int span,
+                                                                    uint32_t *__restrict__ pos)
+{
+    __shared__ uint64_t tile[TILE + TILE / 32];
+    const int m = blockIdx.y;
+    const int tid = threadIdx.x;
+    const uint64_t *Am = A + (size_t)m * tiles * TILE;
+    const int64_t spans = (tiles + span - 1) / span;
+    for (int64_t w = blockIdx.x; w < tiles * spans; w += gridDim.x) {
+        const int64_t t = w % tiles, u0 = (w / tiles) * span;
+        const int64_t u1 = std::min<int64_t>(tiles, u0 + span);
+        uint64_t item[4];
+        uint32_t cnt[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            item[r] = Am[t * TILE + r * PLACE_THREADS + tid];
+            cnt[r] = 0;
+        }
+        for (int64_t u = u0; u < u1; ++u) {
+            __syncthreads();  // the previous tile's searches are done
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = r * PLACE_THREADS + tid;
+                tile[place_skew(e)] = Am[u * TILE + e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // entries below item[r]: uniform binary search over TILE = 2^12
+                int lo = 0;
+#pragma unroll
+                for (int step = TILE / 2; step > 0; step >>= 1)
+                    lo += tile[place_skew(lo + step - 1)] < item[r] ? step : 0;
+                lo += tile[place_skew(lo)] < item[r] ? 1 : 0;
+                cnt[r] += (uint32_t)lo;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (item[r] != ~0ull) atomicAdd(&pos[((size_t)m * tiles + t) * TILE + r * PLACE_THREADS + tid], cnt[r]);
+        __syncthreads();  // before the next work item restages the tile
+    }
+}
+
+__global__ void k_rank_scatter(const uint64_t *__restrict__ A, const uint32_t *__restrict__ pos, int64_t N,
+                               int64_t tiles, uint64_t *__restrict__ S)
 {
     const int m = blockIdx.y;
     const uint64_t *Am = A + (size_t)m * tiles * TILE;
+    const uint32_t *Pm = pos + (size_t)m * tiles * TILE;
     uint64_t *Sm = S + (size_t)m * N;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tiles * TILE;
          q += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t item = Am[q];
-        if (item == ~0ull) continue;
-        int64_t pos = 0;
-        for (int64_t t = 0; t < tiles; ++t) pos += lower_bound_tile(Am + t * TILE, item);
-        Sm[pos] = item;
+        const uint64_t item = Am[q];
+        if (item != ~0ull) Sm[Pm[q]] = item;
     }
+}
+
+// The two launches above for C columns of `tiles` sorted tiles in A.
+static hipError_t launch_place(const uint64_t *A, int64_t N, int C, int64_t tiles, uint32_t *pos, uint64_t *S,
+                               hipStream_t st)
+{
+    // spans of several tiles once tiles^2 * C work items would far exceed the
+    // chip's block slots (fewer atomic adds); never more than 32 tiles
+    const int span = (int)std::max<int64_t>(1, std::min<int64_t>(32, tiles * tiles * C / 2048));
+    const int64_t items = tiles * ((tiles + span - 1) / span);
+    hipLaunchKernelGGL(k_rank_place_count, dim3((unsigned)std::min<int64_t>(items, 65536), C),
+                       dim3(PLACE_THREADS), 0, st, A, tiles, span, pos);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)std::min<int64_t>((tiles * TILE + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_rank_scatter, dim3(blocks, C), dim3(256), 0, st, A, pos, N, tiles, S);
+    return hipGetLastError();
 }
 
 __device__ __forceinline__ bool first_of_run(const uint64_t *Sm, int64_t p)
@@ -420,7 +481,8 @@ size_t rank16_scratch_bytes(int64_t N, int d)
     size_t c = (size_t)d * ((N + SEG - 1) / SEG) * sizeof(uint32_t);
     size_t r32 = (size_t)N * d * sizeof(uint32_t);          // full ranks
     size_t rs = (size_t)d * (N + 1) * sizeof(uint32_t);     // first sorted position per rank
-    return a + s + c + r32 + rs + 256;
+    size_t pos = (size_t)d * tiles * TILE * sizeof(uint32_t);  // sorted position per tile entry
+    return a + s + c + r32 + rs + pos + 256;
 }
 
 RankTables rank16_tables(void *scratch, int64_t N, int d)
@@ -447,7 +509,8 @@ hipError_t launch_rank16_shift(int64_t N, int d, uint32_t *R, void *scratch, uin
 
 size_t sort_columns_scratch_bytes(int64_t N, int C)
 {
-    return (size_t)C * tiles_of(N) * TILE * sizeof(uint64_t) + (size_t)C * N * sizeof(uint64_t) + 256;
+    return (size_t)C * tiles_of(N) * TILE * (sizeof(uint64_t) + sizeof(uint32_t)) +
+           (size_t)C * N * sizeof(uint64_t) + 256;
 }
 
 hipError_t launch_sort_columns(const float *X, int64_t N, int C, void *scratch, uint64_t **S_out,
@@ -457,24 +520,25 @@ hipError_t launch_sort_columns(const float *X, int64_t N, int C, void *scratch, 
     const int64_t tiles = tiles_of(N);
     uint64_t *A = (uint64_t *)scratch;
     uint64_t *S = A + (size_t)C * tiles * TILE;
+    uint32_t *pos = (uint32_t *)(S + (size_t)C * N);
     if (tiles == 1) {  // one tile: the sorted tile is the sorted column
         if (N <= 256)
-            hipLaunchKernelGGL(k_rank_tiles<256>, dim3(1, C), dim3(64), 0, st, X, N, C, tiles, A, S);
+            hipLaunchKernelGGL(k_rank_tiles<256>, dim3(1, C), dim3(64), 0, st, X, N, C, tiles, A, S, pos);
         else if (N <= 1024)
-            hipLaunchKernelGGL(k_rank_tiles<1024>, dim3(1, C), dim3(256), 0, st, X, N, C, tiles, A, S);
+            hipLaunchKernelGGL(k_rank_tiles<1024>, dim3(1, C), dim3(256), 0, st, X, N, C, tiles, A, S, pos);
         else
-            hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3(1, C), dim3(TILE / 4), 0, st, X, N, C, tiles, A, S);
+            hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3(1, C), dim3(TILE / 4), 0, st, X, N, C, tiles, A, S,
+                               pos);
         *S_out = S;
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3((unsigned)tiles, C), dim3(TILE / 4), 0, st, X, N, C, tiles,
-                       A, (uint64_t *)nullptr);
+                       A, (uint64_t *)nullptr, pos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned blocks = (unsigned)std::min<int64_t>((tiles * TILE + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_rank_place, dim3(blocks, C), dim3(256), 0, st, A, N, tiles, S);
+    e = launch_place(A, N, C, tiles, pos, S, st);
     *S_out = S;
-    return hipGetLastError();
+    return e;
 }
 
 hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch, uint32_t *ctl,
@@ -498,17 +562,15 @@ hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *sc
         return hipGetLastError();
     }
     uint64_t *A = (uint64_t *)scratch;
-    hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3((unsigned)tiles, d), dim3(TILE / 4), 0, st, Z, N, d,
-                       tiles, A, (uint64_t *)nullptr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t items = tiles * TILE;
-    unsigned blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 4096);
     uint64_t *S = A + (size_t)d * tiles * TILE;
     uint32_t *C = (uint32_t *)(S + (size_t)d * N);
     const int64_t segs = (N + SEG - 1) / SEG;
     const RankTables tabs = rank16_tables(scratch, N, d);
-    hipLaunchKernelGGL(k_rank_place, dim3(blocks, d), dim3(256), 0, st, A, N, tiles, S);
+    uint32_t *pos = tabs.RS + (size_t)d * (N + 1);
+    hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3((unsigned)tiles, d), dim3(TILE / 4), 0, st, Z, N, d,
+                       tiles, A, (uint64_t *)nullptr, pos);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_place(A, N, d, tiles, pos, S, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_flags, dim3((unsigned)segs, d), dim3(SEG_THREADS), 0, st, S, N, segs, C,
                        ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;

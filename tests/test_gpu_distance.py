@@ -281,8 +281,9 @@ def test_rank16_tile_edges(ctx, oracle_mod, n_p, n_q, d):
 
 def test_rank16_dense_path_and_fallback(ctx, oracle_mod):
     """More than 65536 points: with few distinct values the dense ranks fit
-    16 bits; with more than 65536 distinct values in a dimension the library
-    falls back to fp32 compares.  Both must match the oracle."""
+    16 bits; with more than 65536 distinct values in a dimension that
+    dimension is coded by shifted sorted positions and corrected after the
+    sweep.  Both must match the oracle."""
     g = np.random.default_rng(44)
     P = np.rint(g.standard_normal((40000, 2)) * 30).astype(np.float32)
     Q = np.rint(g.standard_normal((30001, 2)) * 30 + 3).astype(np.float32)
