@@ -106,10 +106,11 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p)
               c->force_waves == 8 || c->force_waves == 16))
         p.waves = c->force_waves;
     p.groups = cdiv(N, 64);
-    // about 8 waves per SIMD over the 1024 SIMDs, each sweeping >= 256 points
+    // about 8 waves per SIMD over the 1024 SIMDs, each sweeping >= 128 points
+    // (a longer chain of point blocks per wave is latency-bound at small N)
     const int64_t target_waves = 8192;
     int64_t chunks = cdiv(target_waves, p.groups * p.waves);
-    int64_t max_chunks = std::max<int64_t>(1, N / ((int64_t)p.waves * 256));
+    int64_t max_chunks = std::max<int64_t>(1, N / ((int64_t)p.waves * 128));
     chunks = std::min(chunks, max_chunks);
     if (c && c->force_chunks > 0) chunks = c->force_chunks;
     p.chunks = chunks;

@@ -364,14 +364,8 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
 
     const uint32_t base = (uint32_t)(uintptr_t)(lds_u64v *)(h64 + Geo<D>::KOFF * 64 + lane);
     const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
-    int64_t i = a;
-    for (; i + U <= b; i += U) {
-        uint32_t buf[U * PW];
-        uint64_t iv[U];
-#pragma unroll
-        for (int e = 0; e < U * PW; ++e) buf[e] = R[i * PW + e];
-#pragma unroll
-        for (int u = 0; u < U; ++u) iv[u] = inc[i + u];
+    // bin addresses of a block of U voxels, and their weighted increments
+    auto addrs = [&](const uint32_t (&buf)[U * PW], uint32_t (&ad)[U]) {
         uint32_t Rg[2][4];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -380,12 +374,53 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
             Rg[0][u] = group_bytes<D>(r, 0);
             Rg[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
         }
-        uint32_t ad[4];
         addr4<NP, 9>(Rg, base, ad, w0, w1);
+    };
+    auto adds = [&](const uint32_t (&ad)[U], const uint64_t (&iv)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
             __hip_atomic_fetch_add((lds_u64v *)(uintptr_t)ad[u], iv[u], __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    auto load = [&](int64_t at, uint32_t (&buf)[U * PW], uint64_t (&iv)[U]) {
+#pragma unroll
+        for (int e = 0; e < U * PW; ++e) buf[e] = R[at * PW + e];
+#pragma unroll
+        for (int u = 0; u < U; ++u) iv[u] = inc[at + u];
+    };
+    int64_t i = a;
+    int64_t nblk = b > a ? (b - a) / U : 0;
+    if (nblk & 1) {  // an odd block first, so the pipelined loop runs in pairs
+        uint32_t buf[U * PW], ad[U];
+        uint64_t iv[U];
+        load(i, buf, iv);
+        addrs(buf, ad);
+        adds(ad, iv);
+        i += U;
+        --nblk;
+    }
+    if (nblk > 0) {
+        // The same software pipeline as the exact sweep: the scalar loads of
+        // the next block go out before this block's addresses are computed,
+        // and one wait per block (scalar loads and LDS atomics share its
+        // counter) covers loads issued a whole block earlier.  The last
+        // trip's prefetch is clamped to the last full block (in bounds).
+        const int64_t last = b - U;
+        uint32_t bufA[U * PW], bufB[U * PW], ad[U];
+        uint64_t ivA[U], ivB[U];
+        load(i, bufA, ivA);
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int64_t t = 0; t < nblk; t += 2) {
+            load(i + U, bufB, ivB);
+            addrs(bufA, ad);
+            wait_lgkm();
+            adds(ad, ivA);
+            load((i + 2 * U < last) ? i + 2 * U : last, bufA, ivA);
+            addrs(bufB, ad);
+            wait_lgkm();
+            adds(ad, ivB);
+            i += 2 * U;
+        }
     }
     for (; i < b; ++i) {
         uint32_t buf[PW];
