@@ -94,9 +94,7 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
         if (!st) st = ensure(c, c->rank_scratch, rank16_scratch_bytes(n, d), "rank scratch");
     }
     if (!st) st = ensure(c, c->block_best, (size_t)a.plan.groups * sizeof(BlockBest), "block results");
-    if (!st && a.plan.chunks > 1)
-        st = ensure(c, c->partial, (size_t)a.plan.chunks * a.plan.groups * bins * 64 * sizeof(uint2),
-                    "partial counts");
+    if (!st && a.plan.chunks > 1) st = ensure(c, c->partial, partial_bytes(a.plan), "partial counts");
     if (st) return st;
 
     a.srcZ = dev ? Zin : (const float *)c->z.ptr;

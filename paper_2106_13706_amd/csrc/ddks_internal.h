@@ -50,6 +50,15 @@ struct SweepPlan {
     int64_t chunk_len = 0;  // points per chunk
 };
 
+// Partial counts of a multi-chunk plan, one entry per (chunk, group, bin,
+// lane): a uint32 with c_P in the low and c_Q in the high half when no chunk
+// holds more than 65535 points (each half then fits), else a uint2 (c_P, c_Q).
+inline bool partial_packed(const SweepPlan &p) { return p.chunk_len <= 65535; }
+inline size_t partial_bytes(const SweepPlan &p)
+{
+    return (size_t)p.chunks * p.groups * ((size_t)1 << p.d) * 64 * (partial_packed(p) ? 4 : 8);
+}
+
 // Words (4-byte) per point in the device point buffer.
 int point_words(int path, int d);
 
@@ -111,23 +120,24 @@ hipError_t launch_rank16_shift(int64_t N, int d, uint32_t *R, void *scratch, uin
 // After a sweep of the shifted encoding with plan.chunks >= 2 (before
 // launch_score): for every origin o, each point x with o's code and a smaller
 // value in some shifted dimension was counted in the orthant of the code
-// compares; moves it to its exact orthant in chunk 0's partial counts (at
-// most 2^shift_m - 1 points per origin and dimension).
-hipError_t launch_rank_fixups(int d, const RankTables &t, int64_t N, int64_t n_p, uint32_t shifts,
-                              uint2 *partial, hipStream_t s);
+// compares; moves it to its exact orthant in the partial counts of the chunk
+// that holds x (at most 2^shift_m - 1 points per origin and dimension).
+hipError_t launch_rank_fixups(const SweepPlan &plan, const RankTables &t, int64_t N, int64_t n_p,
+                              uint32_t shifts, void *partial, hipStream_t s);
 
 // The O(2^d N^2) sweep.  With plan.chunks == 1 the epilogue scores in place and
 // writes block_best[group]; otherwise it writes per-chunk partial counts
-// (uint2 [chunks][groups][2^d][64]) for launch_score.
+// ([chunks][groups][2^d][64] entries, see partial_packed; partial_bytes(plan)
+// bytes) for launch_score.
 // counts (nullable, device): [N][2^d][2] uint32, written when chunks == 1.
 hipError_t launch_sweep(const SweepPlan &plan, const void *Z, int64_t N, int64_t n_p,
-                        int64_t n_q, uint2 *partial, BlockBest *block_best, uint32_t *counts,
+                        int64_t n_q, void *partial, BlockBest *block_best, uint32_t *counts,
                         hipStream_t s);
 
 // Sums the partial counts of a multi-chunk sweep, scores, writes block_best
 // (and counts if non-null).
 hipError_t launch_score(const SweepPlan &plan, int64_t N, int64_t n_p, int64_t n_q,
-                        const uint2 *partial, BlockBest *block_best, uint32_t *counts,
+                        const void *partial, BlockBest *block_best, uint32_t *counts,
                         hipStream_t s);
 
 // Reduces block_best[0..nblocks) with the tie rule (num desc, origin asc,

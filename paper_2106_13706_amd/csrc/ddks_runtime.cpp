@@ -187,12 +187,11 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
     if (shifts && plan.chunks < 2) return fail(c, DDKS_E_DEVICE, "shifted ranks need a chunked plan");
     int st = ensure(c, c->block_best, (size_t)plan.groups * sizeof(BlockBest), "block results");
     if (st) return st;
-    uint2 *partial = nullptr;
+    void *partial = nullptr;
     if (plan.chunks > 1) {
-        size_t pb = (size_t)plan.chunks * plan.groups * ((size_t)1 << plan.d) * 64 * sizeof(uint2);
-        st = ensure(c, c->partial, pb, "partial counts");
+        st = ensure(c, c->partial, partial_bytes(plan), "partial counts");
         if (st) return st;
-        partial = (uint2 *)c->partial.ptr;
+        partial = c->partial.ptr;
     }
     BlockBest *bb = (BlockBest *)c->block_best.ptr;
     const bool prof = c->profile && s == c->stream && !c->batch_capturing;
@@ -201,7 +200,7 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
     if (st) return st;
     if (prof) (void)hipEventRecord(c->ev[1], s);
     if (shifts) {
-        st = hip_check(c, launch_rank_fixups(plan.d, rank16_tables(c->rank_scratch.ptr, N, plan.d), N, n_p, shifts,
+        st = hip_check(c, launch_rank_fixups(plan, rank16_tables(c->rank_scratch.ptr, N, plan.d), N, n_p, shifts,
                                              partial, s),
                        "rank fixup launch");
         if (st) return st;
@@ -259,10 +258,7 @@ static int prepare_distance(ddks_ctx *c, const DistArgs &a)
         if (!st) st = ensure(c, c->rank_scratch, rank16_scratch_bytes(N, a.d), "rank scratch");
     }
     if (!st) st = ensure(c, c->block_best, (size_t)a.plan.groups * sizeof(BlockBest), "block results");
-    if (!st && a.plan.chunks > 1)
-        st = ensure(c, c->partial,
-                    (size_t)a.plan.chunks * a.plan.groups * ((size_t)1 << a.d) * 64 * sizeof(uint2),
-                    "partial counts");
+    if (!st && a.plan.chunks > 1) st = ensure(c, c->partial, partial_bytes(a.plan), "partial counts");
     return st;
 }
 

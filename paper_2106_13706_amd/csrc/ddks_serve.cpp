@@ -130,7 +130,7 @@ struct Slot {
     void *rank_scratch = nullptr;
     uint32_t *rank_ctl = nullptr;  // launch_rank16 control block
     // partial counts and the (always zero) flags word of solo sweeps
-    uint2 *partial = nullptr;
+    void *partial = nullptr;
     uint32_t *flags_d = nullptr;
 };
 
@@ -288,7 +288,7 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         Req *r = batch[i];
         const PackedTest &t = s.tests_h[i];
         BlockBest *tbb = bb + t.bb_offset;
-        uint2 *part = r->plan.chunks > 1 ? s.partial : nullptr;
+        void *part = r->plan.chunks > 1 ? s.partial : nullptr;
         if (r->shifts) {
             const float *zf = (const float *)(base + r->off);
             if (launch_rank16(zf, r->N, r->d, (uint32_t *)t.Z, s.rank_scratch, s.rank_ctl, s.stream) != hipSuccess ||
@@ -299,7 +299,7 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
             }
         }
         if (launch_sweep(r->plan, t.Z, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess ||
-            (r->shifts && launch_rank_fixups(r->d, rank16_tables(s.rank_scratch, r->N, r->d), r->N, r->n_p,
+            (r->shifts && launch_rank_fixups(r->plan, rank16_tables(s.rank_scratch, r->N, r->d), r->N, r->n_p,
                                              r->shifts, part, s.stream) != hipSuccess) ||
             (part && launch_score(r->plan, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess) ||
             launch_reduce(tbb, r->plan.groups, s.flags_d, s.res_d + i, s.stream) != hipSuccess) {
@@ -640,8 +640,7 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
         }
         if (shifted && p.chunks < 2) return false;
         if (!plan_complete(p, N, req->n_p)) return false;
-        const size_t pb = p.chunks > 1 ? (size_t)p.chunks * per_chunk : 0;
-        if (pb > SERVE_SOLO_PARTIAL) return false;
+        if (p.chunks > 1 && partial_bytes(p) > SERVE_SOLO_PARTIAL) return false;
         *out = p;
         return true;
     };

@@ -100,12 +100,13 @@ __device__ __forceinline__ void finish_block(Get get, int64_t group, int64_t N, 
 // of chunk `chunk` (of nchunks), split across the W waves, which add into
 // `hists` LDS histograms (1 <= hists <= W, a power of two).  With nchunks == 1
 // the block scores in place and writes block_best[group] (and counts);
-// otherwise it writes its partial counts.
+// otherwise it writes its partial counts: one uint32 (c_P | c_Q << 16) per
+// entry when a chunk holds at most 65535 points, else a uint2.
 template <int D, int PATH, int W>
 __device__ __forceinline__ void sweep_block(const void *__restrict__ Zv, int64_t N, int64_t n_p,
                                             int64_t n_q, int64_t chunk_len, int64_t chunk,
                                             int64_t nchunks, int64_t group, int64_t groups,
-                                            int hists, uint2 *__restrict__ partial,
+                                            int hists, void *__restrict__ partial,
                                             BlockBest *__restrict__ block_best,
                                             uint32_t *__restrict__ counts, uint32_t *smem)
 {
@@ -189,9 +190,15 @@ __device__ __forceinline__ void sweep_block(const void *__restrict__ Zv, int64_t
     };
     if (nchunks == 1) {
         finish_block<D, W>(get, group, N, n_p, n_q, block_best, counts, smem);
+    } else if (chunk_len <= 65535) {
+        uint32_t *p32 = static_cast<uint32_t *>(partial);
+        for (int j = w; j < BINS; j += W) {
+            const uint2 c = get(j);
+            p32[((chunk * groups + group) * BINS + j) * 64 + lane] = c.x | (c.y << 16);
+        }
     } else {
-        for (int j = w; j < BINS; j += W)
-            partial[((chunk * groups + group) * BINS + j) * 64 + lane] = get(j);
+        uint2 *p64 = static_cast<uint2 *>(partial);
+        for (int j = w; j < BINS; j += W) p64[((chunk * groups + group) * BINS + j) * 64 + lane] = get(j);
     }
 }
 
@@ -199,7 +206,7 @@ template <int D, int PATH, int W>
 __global__ __launch_bounds__(W * 64) void k_sweep(const void *__restrict__ Zv, int64_t N,
                                                   int64_t n_p, int64_t n_q, int64_t chunk_len,
                                                   int64_t groups, int hists,
-                                                  uint2 *__restrict__ partial,
+                                                  void *__restrict__ partial,
                                                   BlockBest *__restrict__ block_best,
                                                   uint32_t *__restrict__ counts)
 {
@@ -222,10 +229,11 @@ __global__ __launch_bounds__(W * 64) void k_sweep_packed(const PackedTest *__res
                             block_best + t.bb_offset, nullptr, smem);
 }
 
+// packed != 0: the partial counts are uint32 (c_P | c_Q << 16), else uint2.
 template <int D, int W>
 __global__ __launch_bounds__(W * 64) void k_score(int64_t N, int64_t n_p, int64_t n_q,
-                                                  int64_t chunks, int64_t groups,
-                                                  const uint2 *__restrict__ partial,
+                                                  int64_t chunks, int64_t groups, int packed,
+                                                  const void *__restrict__ partial,
                                                   BlockBest *__restrict__ block_best,
                                                   uint32_t *__restrict__ counts)
 {
@@ -235,10 +243,20 @@ __global__ __launch_bounds__(W * 64) void k_score(int64_t N, int64_t n_p, int64_
     const int64_t group = blockIdx.x;
     auto get = [&](int j) {
         uint32_t cp = 0, cq = 0;
-        for (int64_t s = 0; s < chunks; ++s) {
-            uint2 c = partial[((s * groups + group) * BINS + j) * 64 + lane];
-            cp += c.x;
-            cq += c.y;
+        if (packed) {
+            const uint32_t *p32 = static_cast<const uint32_t *>(partial);
+            for (int64_t s = 0; s < chunks; ++s) {
+                const uint32_t c = p32[((s * groups + group) * BINS + j) * 64 + lane];
+                cp += c & 0xffffu;
+                cq += c >> 16;
+            }
+        } else {
+            const uint2 *p64 = static_cast<const uint2 *>(partial);
+            for (int64_t s = 0; s < chunks; ++s) {
+                const uint2 c = p64[((s * groups + group) * BINS + j) * 64 + lane];
+                cp += c.x;
+                cq += c.y;
+            }
         }
         return make_uint2(cp, cq);
     };
@@ -409,7 +427,7 @@ static void allow_big_lds(const void *kernel, bool &done)
 
 template <int D, int PATH, int W>
 static hipError_t launch_sweep_t(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p,
-                                 int64_t n_q, uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 int64_t n_q, void *partial, BlockBest *bb, uint32_t *counts,
                                  hipStream_t s)
 {
     size_t lds = sweep_lds_bytes(p);
@@ -423,7 +441,7 @@ static hipError_t launch_sweep_t(const SweepPlan &p, const void *Z, int64_t N, i
 
 template <int D, int PATH>
 static hipError_t launch_sweep_w(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p,
-                                 int64_t n_q, uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 int64_t n_q, void *partial, BlockBest *bb, uint32_t *counts,
                                  hipStream_t s)
 {
     switch (p.waves) {
@@ -438,7 +456,7 @@ static hipError_t launch_sweep_w(const SweepPlan &p, const void *Z, int64_t N, i
 
 template <int PATH>
 static hipError_t launch_sweep_p(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p,
-                                 int64_t n_q, uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 int64_t n_q, void *partial, BlockBest *bb, uint32_t *counts,
                                  hipStream_t s)
 {
     switch (p.d) {
@@ -455,7 +473,7 @@ static hipError_t launch_sweep_p(const SweepPlan &p, const void *Z, int64_t N, i
 }
 
 hipError_t launch_sweep(const SweepPlan &p, const void *Z, int64_t N, int64_t n_p, int64_t n_q,
-                        uint2 *partial, BlockBest *bb, uint32_t *counts, hipStream_t s)
+                        void *partial, BlockBest *bb, uint32_t *counts, hipStream_t s)
 {
     if (p.groups < 1 || p.chunks < 1 || p.chunk_len < 1 || p.groups * 64 < N ||
         p.chunks * p.chunk_len < N || p.groups > 0x7fffffff || p.chunks > 65535)
@@ -523,16 +541,16 @@ hipError_t launch_reduce_packed(const PackedTest *tests, int64_t ntests, const B
 
 template <int D>
 static hipError_t launch_score_d(const SweepPlan &p, int64_t N, int64_t n_p, int64_t n_q,
-                                 const uint2 *partial, BlockBest *bb, uint32_t *counts,
+                                 const void *partial, BlockBest *bb, uint32_t *counts,
                                  hipStream_t s)
 {
     hipLaunchKernelGGL((k_score<D, 4>), dim3((unsigned)p.groups), dim3(256), 0, s, N, n_p, n_q,
-                       p.chunks, p.groups, partial, bb, counts);
+                       p.chunks, p.groups, partial_packed(p) ? 1 : 0, partial, bb, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_score(const SweepPlan &p, int64_t N, int64_t n_p, int64_t n_q,
-                        const uint2 *partial, BlockBest *bb, uint32_t *counts, hipStream_t s)
+                        const void *partial, BlockBest *bb, uint32_t *counts, hipStream_t s)
 {
     switch (p.d) {
     case 1: return launch_score_d<1>(p, N, n_p, n_q, partial, bb, counts, s);

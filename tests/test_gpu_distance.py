@@ -113,6 +113,30 @@ def test_launch_shapes(oracle_mod, waves, chunks):
         c.close()
 
 
+@pytest.mark.parametrize("chunks", [2, 3])
+def test_partial_count_formats(oracle_mod, chunks):
+    """Chunked plans store each chunk's counts as one 32-bit word per bin and
+    lane (16-bit halves) when a chunk holds at most 65535 points, else as two
+    words.  140000 points in 2 chunks take the wide form, in 3 chunks the
+    packed one; each with dense ranks (a 1/8 grid) and with shifted codes
+    (continuous values, whose corrections go to the chunk of the moved point),
+    against the oracle."""
+    from paper_2106_13706_amd import native
+    c = _ctx(DDKS_FORCE_CHUNKS=chunks)
+    try:
+        g = np.random.default_rng(chunks)
+        for grid in (True, False):
+            P = g.standard_normal((71000, 2)).astype(np.float32)
+            Q = (g.standard_normal((69000, 2)) * 1.1 + 0.03).astype(np.float32)
+            if grid:
+                P, Q = (np.rint(P * 8) / 8).astype(np.float32), (np.rint(Q * 8) / 8).astype(np.float32)
+            before = c.profile()["shifted_calls"]
+            check(c, oracle_mod, P, Q, counts=False, flags=native.DDKS_FORCE_RANK16)
+            assert c.profile()["shifted_calls"] == before + (0 if grid else 1)
+    finally:
+        c.close()
+
+
 def _check_sampled(oracle_mod, r, c, P, Q, seed):
     """Counts at sampled origins against the oracle; at every origin the
     counts partition both samples and the reported maximum is the maximum of
