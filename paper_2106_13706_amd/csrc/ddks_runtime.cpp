@@ -100,15 +100,18 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p)
         p.d = d;
         if (plan_complete(p, N, n_p)) return p;
     }
-    // 4 waves per block; 8 at d = 4, whose 68 KB pair table admits two blocks per CU
-    p.waves = d == 4 ? 8 : 4;
+    // 4 waves per block; 8 from d = 4 on, where LDS (the 68 KB pair table at
+    // d = 4, 2^d 256-byte bins above) admits few blocks per CU
+    p.waves = d >= 4 ? 8 : 4;
     if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 ||
               c->force_waves == 8 || c->force_waves == 16))
         p.waves = c->force_waves;
     p.groups = cdiv(N, 64);
-    // about 8 waves per SIMD over the 1024 SIMDs, each sweeping >= 128 points
-    // (a longer chain of point blocks per wave is latency-bound at small N)
-    const int64_t target_waves = 8192;
+    // about 8 waves per SIMD over the 1024 SIMDs (16 at d = 5..7, where more
+    // point chunks measured faster; 2 at d = 8, whose 256-bin partial counts
+    // cost more than the extra waves gain), each sweeping >= 128 points (a
+    // longer chain of point blocks per wave is latency-bound at small N)
+    const int64_t target_waves = d == 8 ? 2048 : (d >= 5 ? 16384 : 8192);
     int64_t chunks = cdiv(target_waves, p.groups * p.waves);
     int64_t max_chunks = std::max<int64_t>(1, N / ((int64_t)p.waves * 128));
     chunks = std::min(chunks, max_chunks);

@@ -627,16 +627,14 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
     r->path = (sv->use_r16 && N >= SERVE_R16_MIN && N <= 65536) ? PATH_R16 : PATH_F32;
     // the launch heuristics of a plain call (not the tuner's entries, which
     // the calling threads may be updating), with no more chunks than the
-    // slot's partial-count buffer holds; a single chunk takes 16 waves per
-    // block, to fill the CUs where LDS admits few blocks.  Shifted codes need
-    // two chunks at least (their corrections go into the partial counts).
+    // slot's partial-count buffer holds.  Shifted codes need two chunks at
+    // least (their corrections go into the partial counts).
     auto solo_plan = [&](int path, bool shifted, SweepPlan *out) {
         SweepPlan p = plan_for(nullptr, path, req->d, N, req->n_p);
         const size_t per_chunk = (size_t)p.groups * ((size_t)1 << p.d) * 64 * sizeof(uint2);
         if (shifted && p.chunks < 2) p.chunks = 2;
         if (p.chunks > 1 && (size_t)p.chunks * per_chunk > SERVE_SOLO_PARTIAL) {
             p.chunks = std::max<int64_t>(1, (int64_t)(SERVE_SOLO_PARTIAL / per_chunk));
-            if (p.chunks == 1) p.waves = 16;
         }
         if (shifted && p.chunks < 2) return false;
         if (!plan_complete(p, N, req->n_p)) return false;
