@@ -24,10 +24,9 @@ namespace ddks {
 
 // One thread per origin o, which alone owns its partial counts (lane o mod
 // 64 of group o / 64, in every chunk), so plain read-modify-writes suffice.
-// F holds, for shifted dimensions,
-// the first sorted position of each point's value (dense ranks elsewhere, where
-// nothing is corrected).  A point to correct in several dimensions is moved
-// once, in the lowest of them.
+// F holds, for shifted dimensions, the first sorted position of each point's
+// value (dense ranks elsewhere, where nothing is corrected).  A point to
+// correct in several dimensions is moved once, in the lowest of them.
 template <int D>
 __global__ __launch_bounds__(256) void k_rank_fixups(const uint32_t *__restrict__ F,
                                                      const uint64_t *__restrict__ S, int64_t N,
