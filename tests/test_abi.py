@@ -84,3 +84,32 @@ def test_constants_match_header():
     for n in names:
         assert n in defs, n
         assert getattr(native, n) == defs[n], n
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror of a header struct has the C compiler's size and
+    field offsets (a mismatch would silently corrupt results)."""
+    import shutil
+    from paper_2106_13706_amd import native
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"ddks_options": native._Options, "ddks_result": native._Result,
+               "ddks_request": native._Request, "ddks_serve_stats": native._ServeStats,
+               "ddks_perm_summary": native._PermSummary, "ddks_profile": native._Profile}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ddks.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
