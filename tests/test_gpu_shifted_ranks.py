@@ -168,13 +168,14 @@ def test_graph_replays_shifted_codes(oracle_mod):
 def test_serving_large_tests_on_shifted_codes(oracle_mod):
     """Serving sweeps solo tests of 65537..131072 points on shifted codes
     (encoded, swept and corrected back to back on the slot's stream), mixed
-    with packed and mid-size tests in the same batches; every result against
-    the oracle, and the stats count the shifted ones."""
+    with packed and mid-size tests in the same batches, and a larger test on
+    fp32 compares; every result against the oracle, and the stats count the
+    shifted ones."""
     from paper_2106_13706_amd import native
     g = np.random.default_rng(41)
     shapes = [(40000, 30000, 8), (50000, 50001, 2), (3000, 2000, 3), (45000, 40000, 5),
-              (20000, 20000, 4), (65537, 1, 1), (70000, 61072, 3)]
-    big = sum(1 for a, b, _ in shapes if a + b > 65536)
+              (20000, 20000, 4), (65537, 1, 1), (70000, 61072, 3), (70000, 70000, 2)]
+    big = sum(1 for a, b, _ in shapes if 65536 < a + b <= 131072)
     reqs = []
     for i, (n_p, n_q, d) in enumerate(shapes):
         P = g.standard_normal((n_p, d)).astype(np.float32)
