@@ -98,6 +98,11 @@ constexpr int RANK_CTL_WORDS = 16;
 // <= 65536 (otherwise see launch_rank16_shift).
 hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch,
                          uint32_t *ctl, hipStream_t s);
+// The same encoding for N = n_p + n_q <= 65536 read straight from P then Q
+// (device pointers, n x d fp32; -0 taken as +0), so that no ingested copy is
+// needed; flags (nullable): bit 0 is set if a value is NaN or infinite.
+hipError_t launch_rank16_pq(const float *P, int64_t n_p, const float *Q, int64_t n_q, int d, uint32_t *R,
+                            void *scratch, uint32_t *flags, hipStream_t s);
 size_t rank16_scratch_bytes(int64_t N, int d);
 
 // N > 65536, after launch_rank16: tables in its scratch.  S: per dimension the

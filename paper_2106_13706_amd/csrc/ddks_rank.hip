@@ -50,6 +50,14 @@ __device__ __forceinline__ uint32_t order_key(float f)
 
 // ------------------------------------------------------------ N <= 65536
 
+// Value of point i in dimension m, P then Q (Q unread while i < n_p), with -0
+// mapped to +0 so that the two compare equal.
+__device__ __forceinline__ float point_value(const float *__restrict__ P, int64_t n_p,
+                                             const float *__restrict__ Q, int64_t i, int d, int m)
+{
+    return (i < n_p ? P[i * d + m] : Q[(i - n_p) * d + m]) + 0.0f;
+}
+
 static constexpr int S32_THREADS = 1024;  // four keys per thread
 static_assert(TILE == 4 * S32_THREADS, "k_rank_sort32 holds four keys per thread");
 
@@ -60,9 +68,13 @@ static_assert(TILE == 4 * S32_THREADS, "k_rank_sort32 holds four keys per thread
 // (shuffles), j >= 256 in another wave (double-buffered LDS, one barrier per
 // stage).  For j >= 4 the direction of a thread's four compare-exchanges is
 // the same (it depends on bits of e above bit 1 only).
-__global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__restrict__ Z, int64_t N,
+// Values are read from P (points 0 .. n_p - 1) then Q; flags (nullable): bit 0
+// is set if a value is NaN or infinite.
+__global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__restrict__ P, int64_t n_p,
+                                                             const float *__restrict__ Q, int64_t N,
                                                              int d, int64_t tiles,
-                                                             uint32_t *__restrict__ K)
+                                                             uint32_t *__restrict__ K,
+                                                             uint32_t *__restrict__ flags)
 {
     __shared__ uint4 buf[2][S32_THREADS];
     const int m = blockIdx.y;
@@ -70,11 +82,15 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__rest
     const int tid = threadIdx.x;
     const int e0 = 4 * tid;
     uint32_t v[4];
+    bool bad = false;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int64_t i = t * TILE + e0 + r;
-        v[r] = i < N ? order_key(Z[i * d + m]) : 0xffffffffu;
+        const float x = i < N ? point_value(P, n_p, Q, i, d, m) : 0.0f;
+        bad |= !isfinite(x);
+        v[r] = i < N ? order_key(x) : 0xffffffffu;
     }
+    if (flags && __any(bad) && (tid & 63) == 0) atomicOr(flags, 1u);
     int cur = 0;
 #pragma unroll
     for (int lk = 1; lk <= 12; ++lk) {
@@ -139,7 +155,8 @@ __device__ __forceinline__ void put_rank(uint16_t *R16, int64_t i, int pw, int m
 
 // Block (t, u, m) with u = blockIdx.z: part[u][m][i] = number of values of
 // sorted tile u below point i's value, for the points i of tile t.
-__global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restrict__ Z, int64_t N,
+__global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restrict__ P, int64_t n_p,
+                                                            const float *__restrict__ Q, int64_t N,
                                                             int d, int64_t tiles,
                                                             const uint32_t *__restrict__ K,
                                                             uint16_t *__restrict__ part)
@@ -161,7 +178,7 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restr
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int64_t i = t * TILE + tid + r * S32_THREADS;
-        key[r] = i < N ? order_key(Z[i * d + m]) : 0u;
+        key[r] = i < N ? order_key(point_value(P, n_p, Q, i, d, m)) : 0u;
     }
     __syncthreads();
     uint16_t *pu = part + ((size_t)u * d + m) * tiles * TILE + t * TILE;
@@ -541,6 +558,27 @@ hipError_t launch_sort_columns(const float *X, int64_t N, int C, void *scratch, 
     return e;
 }
 
+hipError_t launch_rank16_pq(const float *P, int64_t n_p, const float *Q, int64_t n_q, int d, uint32_t *R,
+                            void *scratch, uint32_t *flags, hipStream_t st)
+{
+    const int64_t N = n_p + n_q;
+    if (N < 1 || N > 65536) return hipErrorInvalidValue;
+    const int pw = point_words(PATH_R16, d);
+    const int64_t tiles = tiles_of(N);
+    uint32_t *Kt = (uint32_t *)scratch;
+    uint16_t *part = (uint16_t *)(Kt + (size_t)d * tiles * TILE);
+    hipError_t e;
+    hipLaunchKernelGGL(k_rank_sort32, dim3((unsigned)tiles, d), dim3(S32_THREADS), 0, st, P, n_p, Q, N, d,
+                       tiles, Kt, flags);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rank_count, dim3((unsigned)tiles, d, (unsigned)tiles), dim3(S32_THREADS), 0, st, P,
+                       n_p, Q, N, d, tiles, Kt, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned sblocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_rank_sum, dim3(sblocks, d), dim3(256), 0, st, part, N, d, pw, tiles, (uint16_t *)R);
+    return hipGetLastError();
+}
+
 hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *scratch, uint32_t *ctl,
                          hipStream_t st)
 {
@@ -548,19 +586,7 @@ hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *sc
     const int64_t tiles = tiles_of(N);
     uint16_t *R16 = (uint16_t *)R;
     hipError_t e;
-    if (N <= 65536) {
-        uint32_t *Kt = (uint32_t *)scratch;
-        uint16_t *part = (uint16_t *)(Kt + (size_t)d * tiles * TILE);
-        hipLaunchKernelGGL(k_rank_sort32, dim3((unsigned)tiles, d), dim3(S32_THREADS), 0, st, Z, N, d,
-                           tiles, Kt);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_rank_count, dim3((unsigned)tiles, d, (unsigned)tiles), dim3(S32_THREADS),
-                           0, st, Z, N, d, tiles, Kt, part);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const unsigned sblocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
-        hipLaunchKernelGGL(k_rank_sum, dim3(sblocks, d), dim3(256), 0, st, part, N, d, pw, tiles, R16);
-        return hipGetLastError();
-    }
+    if (N <= 65536) return launch_rank16_pq(Z, N, Z, 0, d, R, scratch, nullptr, st);
     uint64_t *A = (uint64_t *)scratch;
     uint64_t *S = A + (size_t)d * tiles * TILE;
     uint32_t *C = (uint32_t *)(S + (size_t)d * N);

@@ -267,13 +267,23 @@ static int prepare_distance(ddks_ctx *c, const DistArgs &a)
 
 // Ingest, rank encoding (no host decision: past 65536 points every dimension
 // takes the shifted codes) and, if with_sweep, the sweep of device-resident P
-// and Q; the result lands in the pinned c->result_host.
+// and Q; the result lands in the pinned c->result_host.  Up to 65536 points
+// on the rank path the encoding reads P and Q itself and there is no ingest.
 static int enqueue_distance(ddks_ctx *c, const DistArgs &a, hipStream_t s, bool with_sweep)
 {
     const int64_t N = a.n_p + a.n_q;
     float *Z = (float *)c->z.ptr;
-    int st = hip_check(c, launch_ingest_f32(a.P, a.n_p, a.Q, a.n_q, a.d, Z, c->flags_dev, s),
-                       "ingest launch");
+    int st = DDKS_OK;
+    if (a.path == PATH_R16 && N <= 65536) {
+        // the sweep reads only the encoding, which reads P and Q itself (and
+        // checks their values), so no ingested copy is made
+        st = hip_check(c, launch_rank16_pq(a.P, a.n_p, a.Q, a.n_q, a.d, (uint32_t *)c->zr.ptr,
+                                           c->rank_scratch.ptr, c->flags_dev, s), "rank launch");
+        if (st) return st;
+        if (!with_sweep) return DDKS_OK;
+        return run_sweep(c, a.plan, c->zr.ptr, N, a.n_p, a.n_q, a.counts, c->result_host, s, 0);
+    }
+    st = hip_check(c, launch_ingest_f32(a.P, a.n_p, a.Q, a.n_q, a.d, Z, c->flags_dev, s), "ingest launch");
     if (st) return st;
     const void *zdata = Z;
     if (a.path == PATH_R16) {

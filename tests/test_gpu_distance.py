@@ -193,6 +193,36 @@ def test_nonfinite_rejected(ctx):
     assert ctx.distance(P, Q).num == 100
 
 
+def test_nonfinite_rejected_on_the_graph_path(oracle_mod):
+    """Device inputs of 8192..65536 points replay as a graph whose rank
+    encoding reads P and Q itself (no ingested copy): a NaN or infinity in
+    either sample, in the first or last point, is still rejected, a -0 still
+    ties with +0, and the replays before and after stay exact."""
+    import torch
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(9)
+    P = np.rint(g.standard_normal((6000, 3)) * 4).astype(np.float32)
+    Q = np.rint(g.standard_normal((5000, 3)) * 4 + 1).astype(np.float32)
+    P[P == 0] = -0.0
+    o = oracle_mod.distance(P, Q, threads=THREADS)
+    Pd, Qd = torch.from_numpy(P).cuda(), torch.from_numpy(Q).cuda()
+    with native.Context() as c:
+        key = lambda r: (r.num, r.argmax_origin, r.argmax_orthant)
+        assert key(c.distance(Pd, Qd)) == (o.num, o.argmax_origin, o.argmax_orthant)
+        for which, at in (("P", (0, 0)), ("Q", (4999, 2)), ("P", (5999, 1))):
+            for bad in (np.nan, np.inf, -np.inf):
+                X = Pd if which == "P" else Qd
+                keep = X[at].item()
+                X[at] = float(bad)
+                torch.cuda.synchronize()  # the library runs on its own stream
+                with pytest.raises(native.DDKSError) as e:
+                    c.distance(Pd, Qd)
+                assert e.value.status == native.DDKS_E_NONFINITE
+                X[at] = keep
+                torch.cuda.synchronize()
+        assert key(c.distance(Pd, Qd)) == (o.num, o.argmax_origin, o.argmax_orthant)
+
+
 def test_invalid_arguments(ctx):
     from paper_2106_13706_amd import native
     with pytest.raises(native.DDKSError) as e:
