@@ -8,7 +8,7 @@
 // compares two dimensions.
 //
 // N <= 65536 (grid.y = dimension):
-//   1. k_rank_sort32  sorts each tile of TILE order keys (an order-preserving
+//   1. k_rank_sort32  sorts each tile of STILE order keys (an order-preserving
 //                     uint32 image of the fp32 value) in registers, wave
 //                     shuffles and LDS (bitonic network).
 //   2. k_rank_count   block (t, t') stages sorted tile t' in LDS and counts,
@@ -58,11 +58,17 @@ __device__ __forceinline__ float point_value(const float *__restrict__ P, int64_
     return (i < n_p ? P[i * d + m] : Q[(i - n_p) * d + m]) + 0.0f;
 }
 
-static constexpr int S32_THREADS = 1024;  // four keys per thread
-static_assert(TILE == 4 * S32_THREADS, "k_rank_sort32 holds four keys per thread");
+// Tiles of the N <= 65536 path.  2048-key tiles measured slower at 40000
+// points x 4 dimensions: the sort took 8.9 instead of 14.4 us, but the
+// counts (13.5 vs 9.1 us) and their sum (7.2 vs 4.6 us) grew more.
+static constexpr int STILE = 4096;
+static constexpr int S32_THREADS = STILE / 4;  // four keys per thread
+static_assert(STILE == 4 * S32_THREADS, "k_rank_sort32 holds four keys per thread");
+static constexpr int LOG_STILE = 12;
+static_assert((1 << LOG_STILE) == STILE, "tile size");
 
-// Sorts tile blockIdx.x of dimension blockIdx.y: K[m][t][0..TILE) = the order
-// keys of points t*TILE .. t*TILE+TILE-1, ascending (0xffffffff past N).
+// Sorts tile blockIdx.x of dimension blockIdx.y: K[m][t][0..STILE) = the order
+// keys of points t*STILE .. t*STILE+STILE-1, ascending (0xffffffff past N).
 // Bitonic network, fully unrolled: thread tid holds elements e = 4*tid + r;
 // partners at distance j < 4 are in the same thread, j < 256 in the same wave
 // (shuffles), j >= 256 in another wave (double-buffered LDS, one barrier per
@@ -85,7 +91,7 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__rest
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int64_t i = t * TILE + e0 + r;
+        const int64_t i = t * STILE + e0 + r;
         const float x = i < N ? point_value(P, n_p, Q, i, d, m) : 0.0f;
         bad |= !isfinite(x);
         v[r] = i < N ? order_key(x) : 0xffffffffu;
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__rest
     if (flags && __any(bad) && (tid & 63) == 0) atomicOr(flags, 1u);
     int cur = 0;
 #pragma unroll
-    for (int lk = 1; lk <= 12; ++lk) {
+    for (int lk = 1; lk <= LOG_STILE; ++lk) {
         const int k = 1 << lk;
 #pragma unroll
         for (int lj = lk - 1; lj >= 0; --lj) {
@@ -128,21 +134,21 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__rest
             }
         }
     }
-    uint4 *out = reinterpret_cast<uint4 *>(K + ((size_t)m * tiles + t) * TILE);
+    uint4 *out = reinterpret_cast<uint4 *>(K + ((size_t)m * tiles + t) * STILE);
     out[tid] = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
 // The sorted tile in LDS is skewed by one word every 64 entries: the probes
-// of one step of the binary search sit at multiples of TILE/2^k minus one,
+// of one step of the binary search sit at multiples of STILE/2^k minus one,
 // which without the skew all fall in the same LDS bank.
 __device__ __forceinline__ int skew(int e) { return e + (e >> 6); }
 
-// Number of entries of the sorted, skewed LDS tile below key (branchless; 0..TILE).
+// Number of entries of the sorted, skewed LDS tile below key (branchless; 0..STILE).
 __device__ __forceinline__ int count_below(const uint32_t *tile, uint32_t key)
 {
     int p = 0;
 #pragma unroll
-    for (int step = TILE / 2; step >= 1; step >>= 1)
+    for (int step = STILE / 2; step >= 1; step >>= 1)
         if (tile[skew(p + step - 1)] < key) p += step;
     return p + (tile[skew(p)] < key ? 1 : 0);
 }
@@ -161,11 +167,11 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restr
                                                             const uint32_t *__restrict__ K,
                                                             uint16_t *__restrict__ part)
 {
-    __shared__ uint32_t tile[TILE + TILE / 64 + 1];
+    __shared__ uint32_t tile[STILE + STILE / 64 + 1];
     const int m = blockIdx.y;
     const int64_t t = blockIdx.x, u = blockIdx.z;
     const int tid = threadIdx.x;
-    const uint4 *src = reinterpret_cast<const uint4 *>(K + ((size_t)m * tiles + u) * TILE);
+    const uint4 *src = reinterpret_cast<const uint4 *>(K + ((size_t)m * tiles + u) * STILE);
     {
         const uint4 v = src[tid];  // entries 4 tid .. 4 tid + 3, all in one 64-entry row
         const int e = skew(4 * tid);
@@ -177,11 +183,11 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restr
     uint32_t key[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int64_t i = t * TILE + tid + r * S32_THREADS;
+        const int64_t i = t * STILE + tid + r * S32_THREADS;
         key[r] = i < N ? order_key(point_value(P, n_p, Q, i, d, m)) : 0u;
     }
     __syncthreads();
-    uint16_t *pu = part + ((size_t)u * d + m) * tiles * TILE + t * TILE;
+    uint16_t *pu = part + ((size_t)u * d + m) * tiles * STILE + t * STILE;
 #pragma unroll
     for (int r = 0; r < 4; ++r) pu[tid + r * S32_THREADS] = (uint16_t)count_below(tile, key[r]);
 }
@@ -195,7 +201,7 @@ __global__ void k_rank_sum(const uint16_t *__restrict__ part, int64_t N, int d, 
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
         uint32_t rank = 0;
-        for (int64_t u = 0; u < tiles; ++u) rank += part[((size_t)u * d + m) * tiles * TILE + i];
+        for (int64_t u = 0; u < tiles; ++u) rank += part[((size_t)u * d + m) * tiles * STILE + i];
         put_rank(R16, i, pw, m, rank);
         if (m == 0)
             for (int mm = d; mm < 2 * pw; ++mm) R16[(i * pw) * 2 + mm] = 0;
@@ -484,13 +490,15 @@ __global__ void k_rank_shift(uint32_t *__restrict__ R32, const uint32_t *__restr
 }
 
 static int64_t tiles_of(int64_t N) { return (N + TILE - 1) / TILE; }
+static int64_t stiles_of(int64_t N) { return (N + STILE - 1) / STILE; }
 
 size_t rank16_scratch_bytes(int64_t N, int d)
 {
     const int64_t tiles = tiles_of(N);
     if (N <= 65536) {
-        size_t k = (size_t)d * tiles * TILE * sizeof(uint32_t);
-        size_t part = (size_t)tiles * d * tiles * TILE * sizeof(uint16_t);
+        const int64_t st = stiles_of(N);
+        size_t k = (size_t)d * st * STILE * sizeof(uint32_t);
+        size_t part = (size_t)st * d * st * STILE * sizeof(uint16_t);
         return k + part + 256;
     }
     size_t a = (size_t)d * tiles * TILE * sizeof(uint64_t);
@@ -564,9 +572,9 @@ hipError_t launch_rank16_pq(const float *P, int64_t n_p, const float *Q, int64_t
     const int64_t N = n_p + n_q;
     if (N < 1 || N > 65536) return hipErrorInvalidValue;
     const int pw = point_words(PATH_R16, d);
-    const int64_t tiles = tiles_of(N);
+    const int64_t tiles = stiles_of(N);
     uint32_t *Kt = (uint32_t *)scratch;
-    uint16_t *part = (uint16_t *)(Kt + (size_t)d * tiles * TILE);
+    uint16_t *part = (uint16_t *)(Kt + (size_t)d * tiles * STILE);
     hipError_t e;
     hipLaunchKernelGGL(k_rank_sort32, dim3((unsigned)tiles, d), dim3(S32_THREADS), 0, st, P, n_p, Q, N, d,
                        tiles, Kt, flags);

@@ -320,11 +320,13 @@ def test_workload_mixture_grid_d6_scaled(ctx, oracle_mod):
 
 
 @pytest.mark.parametrize("n_p,n_q,d", [(4095, 0, 2), (2048, 2048, 3), (4000, 97, 2),
-                                       (4097, 4096, 1), (32768, 32768, 2)])
+                                       (4097, 4096, 1), (32768, 32768, 2), (2047, 1, 2),
+                                       (2049, 1, 5), (6143, 1, 3), (3000, 3145, 4)])
 def test_rank16_tile_edges(ctx, oracle_mod, n_p, n_q, d):
-    """Rank encoding at tile boundaries (4096 keys per sorted tile) up to the
-    largest size whose ranks always fit 16 bits (65536 points); ties and
-    signed zeros so that equal values span tiles."""
+    """Rank encoding at tile boundaries (4096 keys per sorted tile up to 65536
+    points; also the multiples of 2048) up to the largest size whose ranks
+    always fit 16 bits (65536 points); ties and signed zeros so that equal
+    values span tiles."""
     g = np.random.default_rng(n_p + n_q)
     n_q = max(n_q, 1)
     P = (np.rint(g.standard_normal((n_p, d)) * 40) / 8).astype(np.float32)
