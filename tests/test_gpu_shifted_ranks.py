@@ -55,6 +55,24 @@ def test_counts_exact(ctx, oracle_mod):
     np.testing.assert_array_equal(counts, o.counts)
 
 
+def test_counts_exact_d8(ctx, oracle_mod):
+    """d = 8, where bit 7 of a bin index is stored flipped: every one of the
+    256 orthant counts of every origin after the corrections, against the
+    oracle (70000 points, shifted codes in the continuous dimensions, dense
+    ranks in a rounded one)."""
+    g = np.random.default_rng(88)
+    P = g.standard_normal((40000, 8)).astype(np.float32)
+    Q = (g.standard_normal((30000, 8)) * 1.1).astype(np.float32)
+    P[:, 3] = np.rint(P[:, 3] * 2) / 2
+    Q[:, 3] = np.rint(Q[:, 3] * 2) / 2
+    before = ctx.profile()
+    r, counts = ctx.distance(P, Q, counts=True)
+    assert ctx.profile()["shifted_calls"] == before["shifted_calls"] + 1
+    o = oracle_mod.distance(P, Q, counts=True, threads=THREADS)
+    assert key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+    np.testing.assert_array_equal(counts, o.counts)
+
+
 def test_heavy_ties_in_a_shifted_dimension(ctx, oracle_mod):
     """66000 distinct values plus 4000 more copies of 10.0 and 3000 of 500.5
     (shift 1 on 73000 points): the tied runs cross code boundaries and sit
