@@ -137,6 +137,27 @@ def test_partial_count_formats(oracle_mod, chunks):
         c.close()
 
 
+def test_wide_partial_counts_d8_shifted(oracle_mod):
+    """d = 8, 140000 points in 2 chunks (70000 per chunk: the two-word partial
+    counts) on shifted codes: sampled origins' 256 orthant counts against the
+    oracle, the maximum against the returned counts, and the same result on
+    fp32 compares."""
+    from paper_2106_13706_amd import native
+    c = _ctx(DDKS_FORCE_CHUNKS=2)
+    try:
+        g = np.random.default_rng(808)
+        P = g.standard_normal((70000, 8)).astype(np.float32)
+        Q = (g.standard_normal((70000, 8)) + 0.05).astype(np.float32)
+        before = c.profile()["shifted_calls"]
+        r, cnt = c.distance(P, Q, counts=True, flags=native.DDKS_FORCE_RANK16)
+        assert c.profile()["shifted_calls"] == before + 1
+        _check_sampled(oracle_mod, r, cnt, P, Q, seed=8)
+        rf = c.distance(P, Q, flags=native.DDKS_FORCE_F32)
+        assert (rf.num, rf.argmax_origin, rf.argmax_orthant) == (r.num, r.argmax_origin, r.argmax_orthant)
+    finally:
+        c.close()
+
+
 def _check_sampled(oracle_mod, r, c, P, Q, seed):
     """Counts at sampled origins against the oracle; at every origin the
     counts partition both samples and the reported maximum is the maximum of
