@@ -124,6 +124,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // tail is large enough for the left-out mass to be negligible beside it.
 static constexpr double SIG_K_FULL = 700.0, SIG_K_NARROW = 100.0;
 static constexpr double SIG_NARROW_MIN_TAIL = 1e-30;  // e^-100 ~ 4e-44 left out, < 1e-13 relative
+static constexpr double SIG_WIDE_FIRST_Z = 12.0;       // normal tail ~4e-33
 __host__ __device__ __forceinline__ int64_t window_halfwidth(double sigma, double K = SIG_K_FULL)
 {
     return (int64_t)ceil(K / 3.0 + sqrt(K * K / 9.0 + 2.0 * K * sigma * sigma)) + 1;
@@ -384,8 +385,18 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
             return (O.hi - O.lo + 1 >= 8 * 64) ? tail_two_pass<MODEL, 8>(L, O, I, num, ll, l1m)
                                                : tail_two_pass<MODEL, 1>(L, O, I, num, ll, l1m);
         };
-        double tail = tail_k(SIG_K_NARROW);
-        if (!(tail >= SIG_NARROW_MIN_TAIL)) tail = tail_k(SIG_K_FULL);  // wave-uniform
+        // A normal approximation of delta (variance lam (1 - lam) (1/n_p + 1/n_q),
+        // lam (1/n_p + 1/n_q) for the Poisson model) picks the first window:
+        // where D lies more than SIG_WIDE_FIRST_Z of its deviations out, the
+        // tail is far below SIG_NARROW_MIN_TAIL and the narrow windows would be
+        // summed in vain.  The estimate only decides the work: the wide windows
+        // are valid for every tail.
+        const double var_d = (MODEL == SIG_POISSON ? lam : lam * (1.0 - lam)) *
+                             (1.0 / (double)n_p + 1.0 / (double)n_q);
+        const double z = ((double)num / ((double)n_p * (double)n_q)) / sqrt(var_d);
+        const bool wide_first = z > SIG_WIDE_FIRST_Z;  // wave-uniform
+        double tail = tail_k(wide_first ? SIG_K_FULL : SIG_K_NARROW);
+        if (!wide_first && !(tail >= SIG_NARROW_MIN_TAIL)) tail = tail_k(SIG_K_FULL);  // wave-uniform
         const int64_t wq = window_halfwidth(sq), wp = window_halfwidth(sp);
         if constexpr (MODEL == SIG_POISSON) {
             // mass of either Poisson count beyond its sample size
