@@ -82,7 +82,9 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 bool plan_complete(SweepPlan &p, int64_t N, int64_t n_p)
 {
-    if (p.waves != 1 && p.waves != 2 && p.waves != 4 && p.waves != 8 && p.waves != 16) return false;
+    if (p.waves != 1 && p.waves != 2 && p.waves != 4 && p.waves != 8 && p.waves != 12 &&
+        p.waves != 16)
+        return false;
     p.groups = cdiv(N, 64);
     p.chunks = std::max<int64_t>(1, std::min<int64_t>({p.chunks, N, 65535}));
     p.chunk_len = cdiv(N, p.chunks);
@@ -101,10 +103,13 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p)
         if (plan_complete(p, N, n_p)) return p;
     }
     // 4 waves per block; 8 from d = 4 on, where LDS (the 68 KB pair table at
-    // d = 4, 2^d 256-byte bins above) admits few blocks per CU
-    p.waves = d >= 4 ? 8 : 4;
+    // d = 4, 2^d 256-byte bins above) admits few blocks per CU.  At d = 4 the
+    // table admits two blocks per CU whatever their size, so from 6144 points
+    // on the blocks take 12 waves: 6 per SIMD, the most that the sweep's 112
+    // SGPRs allow beside a second block (16-wave blocks fit one per CU).
+    p.waves = d >= 4 ? (d == 4 && N >= 6144 ? 12 : 8) : 4;
     if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 ||
-              c->force_waves == 8 || c->force_waves == 16))
+              c->force_waves == 8 || c->force_waves == 12 || c->force_waves == 16))
         p.waves = c->force_waves;
     p.groups = cdiv(N, 64);
     // about 8 waves per SIMD over the 1024 SIMDs (16 at d = 5..7, where more

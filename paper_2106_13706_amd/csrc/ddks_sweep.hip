@@ -389,12 +389,14 @@ size_t sweep_lds_bytes(const SweepPlan &p)
 int sweep_hists(int d, int waves, int64_t chunk_len, int64_t n_p, int64_t n_q)
 {
     // A wave sweeps at most ceil(m / waves) points of a sample with m points
-    // in the chunk, and waves / h waves share each of h histograms.
+    // in the chunk, and at most ceil(waves / h) waves share each of h
+    // histograms (wave w adds into histogram w mod h).
     const int64_t mp = chunk_len < n_p ? chunk_len : n_p;
     const int64_t mq = chunk_len < n_q ? chunk_len : n_q;
     const int64_t perp = (mp + waves - 1) / waves, perq = (mq + waves - 1) / waves;
     for (int h = 1; h <= waves; h *= 2) {
-        if ((int64_t)(waves / h) * perp <= 65535 && (int64_t)(waves / h) * perq <= 65535)
+        const int64_t share = (waves + h - 1) / h;
+        if (share * perp <= 65535 && share * perq <= 65535)
             return hist_lds_bytes(d, h) <= (size_t)MAX_LDS_BYTES ? h : 0;
     }
     return 0;
@@ -449,6 +451,7 @@ static hipError_t launch_sweep_w(const SweepPlan &p, const void *Z, int64_t N, i
     case 2: return launch_sweep_t<D, PATH, 2>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     case 4: return launch_sweep_t<D, PATH, 4>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     case 8: return launch_sweep_t<D, PATH, 8>(p, Z, N, n_p, n_q, partial, bb, counts, s);
+    case 12: return launch_sweep_t<D, PATH, 12>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     case 16: return launch_sweep_t<D, PATH, 16>(p, Z, N, n_p, n_q, partial, bb, counts, s);
     default: return hipErrorInvalidValue;
     }

@@ -82,7 +82,9 @@ int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q
     if (!tune_pending(c, path, d, N)) return DDKS_OK;
     const int64_t groups = (N + 63) / 64;
     std::vector<SweepPlan> cand;
-    for (int w : {1, 2, 4, 8, 16}) {
+    for (int w : {1, 2, 4, 8, 12, 16}) {
+        // 12-wave blocks: two per CU beside the d = 4 pair table
+        if (w == 12 && d != 4) continue;
         for (int64_t ch : {1, 2, 3, 4, 6, 8, 12, 16}) {
             SweepPlan p;
             p.path = path;

@@ -99,7 +99,7 @@ def test_subnormals_and_extremes(ctx, oracle_mod, path):
 
 
 @pytest.mark.parametrize("waves,chunks", [(1, 1), (2, 3), (4, 1), (4, 7), (8, 2), (8, 1),
-                                          (16, 1), (16, 3)])
+                                          (12, 1), (12, 3), (16, 1), (16, 3)])
 def test_launch_shapes(oracle_mod, waves, chunks):
     c = _ctx(DDKS_FORCE_WAVES=waves, DDKS_FORCE_CHUNKS=chunks)
     try:
@@ -176,10 +176,11 @@ def _check_sampled(oracle_mod, r, c, P, Q, seed):
     assert divmod(flat, s.shape[1]) == (r.argmax_origin, r.argmax_orthant)
 
 
-@pytest.mark.parametrize("waves,chunks", [(16, 1), (8, 1), (1, 1), (0, 0)])
+@pytest.mark.parametrize("waves,chunks", [(16, 1), (12, 1), (8, 1), (1, 1), (0, 0)])
 def test_counter_bound_shapes(oracle_mod, waves, chunks):
-    """A first sample of 70000 points in one chunk: 16 or 8 waves need two
-    LDS histograms per block so that no 16-bit counter overflows; one wave
+    """A first sample of 70000 points in one chunk: 16, 12 or 8 waves need two
+    LDS histograms per block so that no 16-bit counter overflows (12 waves:
+    waves 0, 2, .. and 1, 3, .. share one each, 6 x 5834 points); one wave
     per block cannot hold it in one chunk, so the planner splits the points.
     (0, 0): the library's own choice.  Every shape must give the same exact
     result."""
