@@ -147,8 +147,9 @@ hipError_t launch_score(const SweepPlan &plan, int64_t N, int64_t n_p, int64_t n
 
 // Reduces block_best[0..nblocks) with the tie rule (num desc, origin asc,
 // code asc) into *out, copies *flags into out->flags and clears *flags.
+// done (nullable, coherent pinned host memory): set to 1 after *out.
 hipError_t launch_reduce(const BlockBest *block_best, int64_t nblocks, uint32_t *flags,
-                         ResultDev *out, hipStream_t s);
+                         ResultDev *out, hipStream_t s, uint32_t *done = nullptr);
 
 // ---------------------------------------------------------------- packed tests
 

@@ -223,7 +223,9 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
         c->ev_score = plan.chunks > 1;
         c->ev_compares = N * N * plan.d;
     }
-    return hip_check(c, launch_reduce(bb, plan.groups, c->flags_dev, res, s), "reduce launch");
+    return hip_check(c, launch_reduce(bb, plan.groups, c->flags_dev, res, s,
+                                      res == c->result_host ? c->done_host : nullptr),
+                     "reduce launch");
 }
 
 void profile_collect(ddks_ctx *c)
@@ -305,6 +307,29 @@ static int enqueue_distance(ddks_ctx *c, const DistArgs &a, hipStream_t s, bool 
 }
 
 // Waits for the call's work, copies host counts if asked, fills *out.
+// Waits for a call whose only output is the result the reduction writes to
+// result_host: polls the done word the reduction sets after it, which returns
+// as soon as that write lands rather than when the runtime has processed the
+// stream's completion.  Checks the stream every 1024 polls (a failed stream
+// ends the wait) and hands a long call over to hipStreamSynchronize, so that
+// it does not hold a host core.
+static int wait_result(ddks_ctx *c, hipStream_t s)
+{
+    for (uint32_t spin = 1; spin <= (1u << 16); ++spin) {
+        if (__atomic_load_n(c->done_host, __ATOMIC_ACQUIRE) == 1u) return DDKS_OK;
+        if ((spin & 1023u) == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return hip_check(c, q, "stream query");
+        }
+        __builtin_ia32_pause();
+    }
+    int st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (!st && __atomic_load_n(c->done_host, __ATOMIC_ACQUIRE) != 1u)
+        st = fail(c, DDKS_E_DEVICE, "the stream finished without a result");
+    return st;
+}
+
 static int finish_distance(ddks_ctx *c, int64_t n_p, int64_t n_q, int d, ddks_result *out,
                            uint32_t *counts_host, const uint32_t *counts_dev, size_t counts_bytes,
                            bool with_S)
@@ -314,7 +339,11 @@ static int finish_distance(ddks_ctx *c, int64_t n_p, int64_t n_q, int d, ddks_re
     if (counts_host)
         st = hip_check(c, hipMemcpyAsync(counts_host, counts_dev, counts_bytes, hipMemcpyDeviceToHost, s),
                        "D2H counts");
-    if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (st) return st;
+    // Timing events, a copy of the counts or the significance still need the
+    // whole stream; otherwise the result word is enough.
+    st = (counts_host || with_S || c->ev_pending) ? hip_check(c, hipStreamSynchronize(s), "stream synchronize")
+                                                  : wait_result(c, s);
     if (st) return st;
     profile_collect(c);
     const ResultDev r = *c->result_host;
@@ -403,6 +432,8 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     if (!st) st = hip_check(c, hipMalloc((void **)&c->result_dev, sizeof(ResultDev)), "hipMalloc");
     if (!st) st = hip_check(c, hipMalloc((void **)&c->flags_dev, 2 * sizeof(uint32_t)), "hipMalloc");
     if (!st) st = hip_check(c, hipMemset(c->flags_dev, 0, 2 * sizeof(uint32_t)), "hipMemset");
+    if (!st) st = hip_check(c, hipHostMalloc((void **)&c->done_host, 64, hipHostMallocCoherent), "hipHostMalloc");
+    if (!st) *c->done_host = 0u;
     if (!st) st = hip_check(c, hipMalloc((void **)&c->rank_ctl_dev, RANK_CTL_WORDS * sizeof(uint32_t)), "hipMalloc");
     if (!st) st = hip_check(c, hipMemset(c->rank_ctl_dev, 0, RANK_CTL_WORDS * sizeof(uint32_t)), "hipMemset");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->result_host, sizeof(ResultDev), 0), "hipHostMalloc");
@@ -435,6 +466,7 @@ int ddks_destroy(ddks_ctx *c)
     if (c->flags_dev) (void)hipFree(c->flags_dev);
     if (c->rank_ctl_dev) (void)hipFree(c->rank_ctl_dev);
     if (c->result_host) (void)hipHostFree(c->result_host);
+    if (c->done_host) (void)hipHostFree(c->done_host);
     if (c->rank_distinct_host) (void)hipHostFree(c->rank_distinct_host);
     if (c->sig_host) (void)hipHostFree(c->sig_host);
     for (int i = 0; i < 4; ++i)
@@ -461,6 +493,7 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     const bool dev = (flags & DDKS_DEVICE_PTRS) != 0;
     hipStream_t s = c->stream;
     const size_t bins = (size_t)1 << d;
+    __atomic_store_n(c->done_host, 0u, __ATOMIC_RELEASE);  // set again by this call's reduction
 
     int st = ensure(c, c->z, (size_t)N * d * sizeof(float), "points");
     if (st) return st;

@@ -58,6 +58,7 @@ struct ddks_ctx {
     ddks::ResultDev *result_dev = nullptr;  // device
     ddks::ResultDev *result_host = nullptr; // pinned
     uint32_t *flags_dev = nullptr;          // device, cleared by the reduction
+    uint32_t *done_host = nullptr;          // pinned, coherent: 1 once a call's result is in result_host
     uint32_t *rank_distinct_host = nullptr; // pinned
     double *sig_host = nullptr;             // pinned, 2 doubles
     uint32_t *rank_ctl_dev = nullptr;

@@ -263,9 +263,11 @@ __global__ __launch_bounds__(W * 64) void k_score(int64_t N, int64_t n_p, int64_
     finish_block<D, W>(get, group, N, n_p, n_q, block_best, counts, scratch);
 }
 
+// done (nullable, coherent host memory): set to 1 once *out is written, so
+// that a host waiting on this result alone can poll it.
 __global__ __launch_bounds__(1024) void k_reduce(const BlockBest *__restrict__ bb, int64_t n,
                                                  uint32_t *__restrict__ flags,
-                                                 ResultDev *__restrict__ out)
+                                                 ResultDev *__restrict__ out, uint32_t *done)
 {
     __shared__ uint64_t sn[16];
     __shared__ uint32_t so[16];
@@ -302,6 +304,10 @@ __global__ __launch_bounds__(1024) void k_reduce(const BlockBest *__restrict__ b
         out->code = code;
         out->flags = *flags;
         *flags = 0u;
+        if (done) {
+            __threadfence_system();  // the result reaches host memory first
+            __hip_atomic_store(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
@@ -569,9 +575,9 @@ hipError_t launch_score(const SweepPlan &p, int64_t N, int64_t n_p, int64_t n_q,
 }
 
 hipError_t launch_reduce(const BlockBest *bb, int64_t nblocks, uint32_t *flags, ResultDev *out,
-                         hipStream_t s)
+                         hipStream_t s, uint32_t *done)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bb, nblocks, flags, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bb, nblocks, flags, out, done);
     return hipGetLastError();
 }
 
