@@ -101,7 +101,10 @@ int ddks_destroy(ddks_ctx *ctx);
  * counts (nullable): caller-allocated uint32 [n_p+n_q][2^d][2], origin-major
  * in P-then-Q order, sample 0 = P -- the membership matrices M of
  * Eq. membership for both origin sets.  Host memory unless DDKS_DEVICE_PTRS.
- * Synchronous: returns after the result (and counts) are available.
+ * Synchronous: returns after the result (and counts) are available.  When
+ * the result is the call's only host output, the call returns once the
+ * final kernel has written it, which may be just before that kernel ends
+ * on the context's stream; work queued on that stream still runs after it.
  * flags DDKS_WITH_SIGNIFICANCE: out->S also receives the analytic
  * significance of the result (as ddks_significance, DDKS_SIG_POISSON for the
  * Poisson model), computed on the device from counts that stay there;
