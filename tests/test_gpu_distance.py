@@ -275,6 +275,40 @@ def test_device_pointers(oracle_mod):
         c.close()
 
 
+@pytest.mark.parametrize("n_p,n_q", [(2600, 2200), (5000, 4000)])
+def test_result_wait_with_device_counts(oracle_mod, n_p, n_q):
+    """A call whose only host output is the result returns once the final
+    kernel has written it, which can be just before that kernel ends on the
+    library's own stream.  Counts written to device memory by the earlier
+    kernels must be complete by then: each call's counts are read on torch's
+    stream (not the library's) right after it returns, over captured and
+    replayed calls with the inputs rewritten in place (fp32 path at 4800
+    points, 16-bit codes at 9000), against the oracle."""
+    import torch
+    from paper_2106_13706_amd import native
+    c = native.Context()  # library-owned stream
+    try:
+        g = np.random.default_rng(91 + n_p)
+        d = 4
+        Pt = torch.empty((n_p, d), dtype=torch.float32, device="cuda")
+        Qt = torch.empty((n_q, d), dtype=torch.float32, device="cuda")
+        for rep in range(4):
+            P = np.rint(g.standard_normal((n_p, d)) * 6).astype(np.float32)
+            Q = np.rint(g.standard_normal((n_q, d)) * 6 + 1).astype(np.float32)
+            Pt.copy_(torch.from_numpy(P))
+            Qt.copy_(torch.from_numpy(Q))
+            torch.cuda.synchronize()  # the library's stream does not follow torch's
+            print(f"  result wait n_p={n_p} n_q={n_q} rep={rep}", flush=True)
+            r, cnt = c.distance(Pt, Qt, counts=True)
+            got = cnt.cpu().numpy().view(np.uint32)
+            o = oracle_mod.distance(P, Q, counts=True, threads=THREADS)
+            assert (r.num, r.argmax_origin, r.argmax_orthant) == (o.num, o.argmax_origin,
+                                                                  o.argmax_orthant)
+            np.testing.assert_array_equal(got, o.counts)
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("flags", [0x0, 0x2, 0x10])
 def test_graph_replays(oracle_mod, flags):
     """Device-resident inputs: the call is captured once and then replayed.
