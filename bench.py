@@ -44,6 +44,19 @@ def _traffic(kernel, workload):
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
 
 
+def _trace(kernel, workload):
+    """The committed rocprofv3 kernel-trace record of this kernel on this
+    workload, or None if the kernel source changed since it was taken."""
+    p = os.path.join(PROFILES, f"trace_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    t = json.load(open(p))
+    if _sources_sha(t["sources"]) != t["sources_sha256"]:
+        return None
+    t["file"] = os.path.relpath(p, ROOT)
+    return t
+
+
 def _sources_sha(sources):
     h = hashlib.sha256()
     for s in sources:
@@ -65,26 +78,99 @@ def _time_distance(ctx, P, Q, steps, warmup, torch):
     return r, (t1 - t0) / steps, ctx.profile(reset=True)
 
 
-def cpu_baseline(P, Q, compares):
-    import oracle
+def host_cpu():
+    """The host's CPU model, logical CPU count and the CPUs this process may use."""
+    model = "unknown"
     try:
-        cores = len(os.sched_getaffinity(0))
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        affinity = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count() or 1, "affinity": affinity}
+
+
+def _time_oracle(fn, runs, budget_s):
     times = []
-    for _ in range(3):
+    out = None
+    for _ in range(runs):
         t0 = time.perf_counter()
-        o = oracle.distance(P, Q, threads=cores)
+        out = fn()
         times.append(time.perf_counter() - t0)
-        if sum(times) > 20.0:
+        if sum(times) > budget_s:
             break
     times.sort()
-    med = times[len(times) // 2]
+    return out, times[len(times) // 2], len(times)
+
+
+def cpu_baseline(P, Q, compares):
+    """The oracle on this host: every CPU the process may use (the reported
+    value), and one thread once, on the full workload."""
+    import oracle
+    cpu = host_cpu()
+    cores = cpu["affinity"]
+    o, med, n = _time_oracle(lambda: oracle.distance(P, Q, threads=cores), 3, 20.0)
+    o1, t1, _ = _time_oracle(lambda: oracle.distance(P, Q, threads=1), 1, 0.0)
+    assert o1.num == o.num
+    N = len(P) + len(Q)
     return o, {"value": compares / med, "unit": "compares/s", "cores": cores, "kind": "oracle",
-               "sample": f"the full workload ({len(P) + len(Q)} origins x "
-                         f"{len(P) + len(Q)} points x {P.shape[1]} dims), median of "
-                         f"{len(times)} run(s), {med:.2f} s each"}
+               "sample": f"the full workload ({N} origins x {N} points x {P.shape[1]} dims), "
+                         f"median of {n} run(s) on {cores} threads, {med:.2f} s each",
+               "single_thread": {"value": compares / t1, "seconds": t1, "runs": 1},
+               "cpu_model": cpu["model"], "nproc": cpu["nproc"], "affinity": cpu["affinity"]}
+
+
+def bench_cpu_full(native, torch, dev):
+    """The oracle at full size on every CPU the process may use, beside the GPU
+    on the same inputs: the d = 6, 100000 + 100000 mixture and all 1024
+    relabellings of the permutation workload (minutes of CPU time on a few
+    cores; not part of the default run)."""
+    import numpy as np
+    import oracle
+    from paper_2106_13706_amd import workloads
+    cpu = host_cpu()
+    cores = cpu["affinity"]
+    out = {"cores": cores, "cpu_model": cpu["model"], "nproc": cpu["nproc"]}
+    P, Q = workloads.mixture_grid()
+    N = len(P) + len(Q)
+    t0 = time.perf_counter()
+    o = oracle.distance(P, Q, threads=cores)
+    sec = time.perf_counter() - t0
+    with native.Context() as ctx:
+        Pt, Qt = torch.from_numpy(P).to(dev), torch.from_numpy(Q).to(dev)
+        r = ctx.distance(Pt, Qt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.distance(Pt, Qt)
+        torch.cuda.synchronize()
+        gsec = time.perf_counter() - t0
+    if (r.num, r.argmax_origin, r.argmax_orthant) != (o.num, o.argmax_origin, o.argmax_orthant):
+        raise SystemExit("mixture: GPU and oracle disagree")
+    out["mixture_grid_d6_100000"] = {"oracle_seconds": sec, "oracle_compares_per_s": N * N * 6 / sec,
+                                     "gpu_seconds": gsec, "num": o.num,
+                                     "argmax": [o.argmax_origin, o.argmax_orthant]}
+    Z, n_p, labels = workloads.permutation()
+    n = len(Z)
+    t0 = time.perf_counter()
+    nums_o = oracle.permutation(Z, n_p, labels, threads=cores)
+    sec = time.perf_counter() - t0
+    with native.Context() as ctx:
+        nums, _, _ = ctx.permutation_batch(Z, n_p, labels)
+        t0 = time.perf_counter()
+        nums, _, _ = ctx.permutation_batch(Z, n_p, labels)
+        gsec = time.perf_counter() - t0
+    if not np.array_equal(nums, nums_o):
+        raise SystemExit("permutation: GPU and oracle disagree")
+    out["permutation_d5_8192x1024"] = {"oracle_seconds": sec,
+                                       "oracle_compares_per_s": len(labels) * n * n * 5 / sec,
+                                       "gpu_seconds_host_inputs": gsec}
+    return out
 
 
 def bench_small(native, torch, dev, calls=300):
@@ -192,7 +278,9 @@ def bench_rdks(ctx, torch, dev, reps=5):
     return out
 
 
-EXTRAS = ("small", "mixture", "significance", "vdks", "rdks", "power", "permutation", "serving")
+EXTRAS = ("small", "mixture", "significance", "vdks", "rdks", "power", "permutation", "serving",
+          "cpu_full")
+DEFAULT_EXTRAS = tuple(e for e in EXTRAS if e != "cpu_full")
 
 
 def bench_power(ctx_factory):
@@ -254,13 +342,22 @@ def bench_batch(ctx, torch, dev, reps=5):
     torch.cuda.synchronize()
     seq_sec = (time.perf_counter() - t0) / nseq
     assert seq_nums == [int(x) for x in nums[:nseq].cpu().numpy().view(np.uint64)]
+    # the paper's analytic significance of the observed split beside the
+    # permutation p-value (Sec. 3)
+    from paper_2106_13706_amd import native
+    Pt, Qt = Zt[:n_p].contiguous(), Zt[n_p:].contiguous()
+    S = {m: ctx.distance(Pt, Qt, flags=native.DDKS_WITH_SIGNIFICANCE | f).S
+         for m, f in (("binomial", 0), ("poisson", native.DDKS_SIG_POISSON))}
     return {"workload": "permutation_d5_8192x1024", "ms_per_batch": sec * 1e3,
             "gpu_ms_per_batch": gpu_ms, "tests_per_s": B / sec,
-            "effective_compares_per_s": eff / sec,
-            "effective_frac_of_valu_peak": (eff / sec) / VALU_COMPARE_PEAK,
+            "relabelled_compares_per_s": eff / sec,
+            "relabelled_compares": "B N^2 d, the compares B separate plain calls would make; "
+                                   "the batch shares the sign codes across relabellings, so this "
+                                   "is a work-equivalent rate, not a fraction of a peak",
             "sequential_plain_calls_tests_per_s": 1.0 / seq_sec,
             "speedup_vs_sequential": (B / sec) * seq_sec,
-            "p_value": summ["p_value"], "observed_D": obs.D}
+            "p_value": summ["p_value"], "n_ge": summ["n_ge"], "observed_D": obs.D,
+            "observed_S_binomial": S["binomial"], "observed_S_poisson": S["poisson"]}
 
 
 def bench_serving(ctx_factory, n_requests, seed_rate=None):
@@ -297,8 +394,12 @@ def bench_serving(ctx_factory, n_requests, seed_rate=None):
     mu_seq = n_requests / seq_s
     out["sequential_plain_calls_tests_per_s"] = mu_seq
 
-    def run(rate):
-        with ctx_factory() as ctx:
+    fd, tune_cache = tempfile.mkstemp(prefix="ddks_serve_tune_", suffix=".txt")
+    os.close(fd)
+
+    def run(rate, tuning=False):
+        from paper_2106_13706_amd import native
+        with native.Context(tune_cache=tune_cache) as ctx:
             tickets = [None] * n_requests
             got = [None] * n_requests
             done = threading.Event()
@@ -328,6 +429,8 @@ def bench_serving(ctx_factory, n_requests, seed_rate=None):
             wall = time.perf_counter() - t0
             st = ctx.serve_stats()
             assert got == seq, "served results differ from the plain calls"
+            if tuning:
+                return None
             return {"tests_per_s": n_requests / wall, "wall_s": wall,
                     "p50_latency_ms": st["p50_latency_us"] / 1e3,
                     "p99_latency_ms": st["p99_latency_us"] / 1e3,
@@ -335,11 +438,18 @@ def bench_serving(ctx_factory, n_requests, seed_rate=None):
                     "compares_per_s": total_compares / wall,
                     "gpu_busy_fraction": st["busy_us"] / 1e6 / wall}
 
+    # the served runs share a tuner cache that a first pass over the same list
+    # fills (the packed sweep's block shape per dimension and size), so that
+    # no timed run spends time tuning
+    run(None, tuning=True)
     out["saturation"] = run(None)
     out["open_loop_at_mu_seq"] = run(mu_seq)
     out["open_loop_at_mu_seq"]["arrival_rate_per_s"] = mu_seq
     out["open_loop_at_2mu_seq"] = run(2 * mu_seq)
     out["open_loop_at_2mu_seq"]["arrival_rate_per_s"] = 2 * mu_seq
+    with open(tune_cache) as f:
+        out["tuned_packed_shapes"] = sum(1 for l in f if l.split()[:1] in (["20"], ["21"]))
+    os.unlink(tune_cache)
     return out
 
 
@@ -393,6 +503,13 @@ def main():
         r, sec, _ = _time_distance(ctx_plain, Pt, Qt, args.steps, args.warmup, torch)
     if (r.num, r.argmax_origin, r.argmax_orthant) != (r_prof.num, r_prof.argmax_origin, r_prof.argmax_orthant):
         raise SystemExit("profiled and plain calls disagree")
+    # the same calls with host buffers: the H2D copy of P and Q and the eager
+    # launches included (reported beside the line, never as its value)
+    _log(f"[bench] {workload}: host inputs (PCIe-inclusive)")
+    with native.Context(stream=stream, tune_cache=tune_cache) as ctx_host:
+        r_h, sec_h, _ = _time_distance(ctx_host, P, Q, args.steps, args.warmup, torch)
+    if r_h.num != r.num:
+        raise SystemExit("host-input calls disagree")
     ms_per_step = sec * 1e3
     value = compares / sec
     sweep_s = prof["sweep_ms"] / max(1, prof["sweeps"]) / 1e3
@@ -419,9 +536,18 @@ def main():
                      "kernel": "k_sweep", "kernel_avg_ms": sweep_s * 1e3,
                      "score_avg_ms": prof["score_ms"] / max(1, prof["sweeps"]),
                      "kernel_timing": "HIP events around each k_sweep launch on the library's stream, "
-                                      f"{args.steps} steps of the same workload and launch shape",
+                                      f"{args.steps} steps of the same workload and launch shape "
+                                      "(achieved and frac)",
                      "profiled_ms_per_step": sec_prof * 1e3},
     }
+    tr = _trace("k_sweep", workload)
+    if tr is not None:
+        line["roofline"]["trace"] = {
+            "kernel_avg_ms": tr["avg_us"] / 1e3,
+            "frac": compares / (tr["avg_us"] * 1e-6) / VALU_COMPARE_PEAK,
+            "calls": tr["calls"],
+            "source": f"{tr['file']}: rocprofv3 --kernel-trace --stats of the command it names "
+                      "(the profiler's own dispatch handling slows the kernel a few percent)"}
     _log(f"[bench] step {ms_per_step:.4f} ms, sweep {sweep_s * 1e3:.4f} ms, "
          f"frac {achieved / VALU_COMPARE_PEAK:.3f}")
 
@@ -433,7 +559,7 @@ def main():
         line["cpu_baseline"] = cb
 
     extras = {}
-    want = set(EXTRAS) if args.extras == "all" else set(args.extras.split(","))
+    want = set(DEFAULT_EXTRAS) if args.extras == "all" else set(args.extras.split(","))
     if args.no_extras:
         want = set()
     unknown = want - set(EXTRAS)
@@ -454,7 +580,7 @@ def main():
         extras["mixture_grid_d6_100000"] = {
             "value": c3 / s3, "unit": "compares/s", "ms_per_step": s3 * 1e3,
             "kernel_avg_ms": k3 * 1e3, "frac": (c3 / k3) / VALU_COMPARE_PEAK,
-            "num": r3.num, "den": r3.den}
+            "num": r3.num, "den": r3.den, "argmax": [r3.argmax_origin, r3.argmax_orthant]}
         del P3t, Q3t
     if "significance" in want:
         _log("[bench] extra: analytic significance")
@@ -475,6 +601,13 @@ def main():
         _log(f"[bench] extra: serving ({args.serve_requests} requests)")
         extras["serving"] = bench_serving(
             lambda: native.Context(flags=native.DDKS_NO_AUTOTUNE), args.serve_requests)
+    if "cpu_full" in want:
+        _log("[bench] extra: oracle at full size (mixture, permutation batch)")
+        extras["cpu_full"] = bench_cpu_full(native, torch, dev)
+    extras["host_inputs"] = {"workload": workload, "ms_per_step": sec_h * 1e3, "value": compares / sec_h,
+                             "unit": "compares/s",
+                             "what": "ddks_distance on host buffers: H2D copy of P and Q, eager launches, "
+                                     "result read back; the PCIe-inclusive rate"}
     if extras:
         line["extras"] = extras
 

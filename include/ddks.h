@@ -148,6 +148,18 @@ int ddks_permutation_batch(ddks_ctx *ctx, const float *Z, int64_t n, int32_t d, 
                            ddks_result *observed, ddks_perm_summary *summary);
 
 /*
+ * Permutation p-value of any statistic (Sec. 3 and Sec. 4.2, e.g. vdKS or
+ * rdKS recomputed on relabelled samples): from the numerators nums[B] of the
+ * relabellings (host memory) and the observed numerator num_obs, all over one
+ * shared denominator, fills *summary as ddks_permutation_batch does (ties
+ * count as at least as extreme; p = (1 + n_ge) / (1 + B)).  B = 0 gives
+ * p = 1 and fraction 0.  Needs no context and no device.
+ * Errors: DDKS_E_INVALID_ARG (null summary, B < 0, or null nums with B > 0).
+ */
+int ddks_perm_summary_of(const uint64_t *nums, int32_t B, uint64_t num_obs,
+                         ddks_perm_summary *summary);
+
+/*
  * Analytic significance S of a statistic num/(n_p*n_q) from its membership
  * counts (Sec. 3, Eq. ddks_significance):
  *   S = 1 - prod over origins k and orthants j of P(delta <= D | lambda_kj),
@@ -207,7 +219,8 @@ typedef struct ddks_request {
     const float *Q; /* host, n_q x d */
     int64_t n_q;
     int32_t d;
-    uint32_t flags; /* reserved, 0 */
+    uint32_t flags; /* 0, or DDKS_WITH_SIGNIFICANCE (optionally | DDKS_SIG_POISSON): the
+                       result's S receives the analytic significance (Sec. 3) */
 } ddks_request;
 
 typedef struct ddks_serve_stats {
@@ -239,7 +252,10 @@ typedef struct ddks_serve_stats {
  * Each test is swept by one block shape whose 16-bit per-sample counters
  * bound a sample to about 8 * 65535 points (4 * 65535 at d = 7, 2 * 65535
  * at d = 8); larger tests get DDKS_E_NOT_SUPPORTED (ddks_distance has no
- * such bound).
+ * such bound).  A test with DDKS_WITH_SIGNIFICANCE is swept on its own with
+ * its membership counts kept in its arena space (N * 2^d * 8 bytes more),
+ * and its S is computed on the device after the sweep, as ddks_distance does;
+ * other request flags are rejected with DDKS_E_INVALID_ARG.
  * Errors: DDKS_E_AGAIN (queue full), DDKS_E_NOMEM (can never fit the
  * budget), DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOT_SUPPORTED,
  * DDKS_E_DEVICE.

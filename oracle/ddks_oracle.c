@@ -19,12 +19,12 @@
  *   x_m >= o_m (IEEE comparison: -0 == +0, ties go to the upper side, so the
  *   origin counts itself in the all-upper orthant).  The orthant of x is
  *   code = sum_m [x_m >= o_m] * 2^m; each of the 2^d orthants is one
- *   "permutation of greater than or less than in each dimension".
+ *   choice of side (below or at-or-above) in every dimension.
  *
  *   Eq. (membership) counts the points of each sample per orthant; Eq. (d1)
  *   takes the maximum absolute difference.  Reading of the normalisation:
- *   the difference is between proportions, |c_P/n_P - c_Q/n_Q| (Fig. 2a
- *   caption: "normalized maximum difference"; Sec. 3, Eq. abs_difference).
+ *   the difference is between proportions, |c_P/n_P - c_Q/n_Q| (the Fig. 2a
+ *   caption calls the value normalised; Sec. 3, Eq. abs_difference).
  *   It is evaluated exactly in integers as |c_P*n_Q - c_Q*n_P| = num, with
  *   den = n_P*n_Q and D = num/den.
  *

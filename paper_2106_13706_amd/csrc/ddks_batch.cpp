@@ -15,7 +15,7 @@ namespace {
 
 struct BatchArgs {
     int64_t n, n_p;
-    int d, B, path, pb;
+    int d, B, path, pb, waves;
     const float *srcZ;
     const uint32_t *labels;
     unsigned long long *nums;
@@ -42,14 +42,84 @@ int enqueue_batch(ddks_ctx *c, const BatchArgs &a, hipStream_t s)
     st = run_sweep(c, a.plan, zdata, a.n, a.n_p, a.n - a.n_p, (uint32_t *)c->obs.ptr, c->result_dev, s);
     if (st) return st;
     if (a.B == 0) return DDKS_OK;
-    st = hip_check(c, launch_perm(a.path, a.d, a.pb, zdata, a.n, a.n_p, (const uint64_t *)c->inc.ptr,
+    st = hip_check(c, launch_perm(a.path, a.d, a.pb, a.waves, zdata, a.n, a.n_p, (const uint64_t *)c->inc.ptr,
                                   a.B, (const uint32_t *)c->obs.ptr, a.nums, s), "permutation launch");
     if (st) return st;
     // number of relabellings at least as extreme as the observed split
     return hip_check(c, launch_count_ge(a.nums, a.B, c->result_dev, s), "count launch");
 }
 
+// Increments buffer of relabellings-per-block pb for B relabellings of n points.
+size_t inc_bytes(int64_t n, int B, int pb)
+{
+    return (size_t)std::max<int64_t>((B + pb - 1) / pb, 1) * n * (pb / 4) * 8;
+}
+
+// Times every admissible (waves, relabellings per block) shape of the
+// permutation kernel on this call's input, once per (path, d, log2 n) key,
+// and records the fastest.  Runs the whole pipeline once eagerly first (the
+// kernel reads the observed split's counts); each timed launch is preceded by
+// the preparation of its increments and cleared numerators.
+int tune_perm(ddks_ctx *c, const BatchArgs &a0, hipStream_t s)
+{
+    std::vector<std::pair<int, int>> cand;
+    for (int pb : {4, 8})
+        for (int w : {4, 8, 16})
+            if (perm_shape_ok(a0.d, pb, w)) cand.emplace_back(w, pb);
+    if (cand.size() < 2) return DDKS_OK;
+    int st = enqueue_batch(c, a0, s);
+    if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (st) return st;
+    const void *zdata = a0.path == PATH_R16 ? c->zr.ptr : c->z.ptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    st = hip_check(c, hipEventCreate(&e0), "hipEventCreate");
+    if (!st) st = hip_check(c, hipEventCreate(&e1), "hipEventCreate");
+    float best_ms = 1e30f;
+    std::pair<int, int> best = {a0.waves, a0.pb};
+    for (const auto &wp : cand) {
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 2 && !st; ++rep) {
+            st = hip_check(c, launch_perm_prepare(a0.labels, a0.n, a0.B, a0.n_p, wp.second, (uint64_t *)c->inc.ptr,
+                                                  c->flags_dev, a0.nums, s), "label preparation");
+            if (!st) st = hip_check(c, hipEventRecord(e0, s), "hipEventRecord");
+            if (!st)
+                st = hip_check(c, launch_perm(a0.path, a0.d, wp.second, wp.first, zdata, a0.n, a0.n_p,
+                                              (const uint64_t *)c->inc.ptr, a0.B, (const uint32_t *)c->obs.ptr,
+                                              a0.nums, s), "permutation launch");
+            if (!st) st = hip_check(c, hipEventRecord(e1, s), "hipEventRecord");
+            if (!st) st = hip_check(c, hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            if (!st) {
+                if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+                else (void)hipGetLastError();
+            }
+        }
+        if (!st && ms_min < best_ms) {
+            best_ms = ms_min;
+            best = wp;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    // the label check above may have flagged rows; the call itself reports them
+    if (!st) st = hip_check(c, hipMemsetAsync(c->flags_dev, 0, sizeof(uint32_t), s), "flags reset");
+    if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (st) return st;
+    tuner_store_perm(c->tuner, a0.path, a0.d, a0.n, best.first, best.second);
+    return DDKS_OK;
+}
+
 }  // namespace
+
+// The permutation p-value of Sec. 3 / Sec. 4.2 from the count of relabellings
+// at least as extreme (the paper gives no formula: the add-one estimator).
+static void perm_summary_fill(int64_t B, uint64_t n_ge, ddks_perm_summary *out)
+{
+    out->B = B;
+    out->n_ge = n_ge;
+    out->p_value = (1.0 + (double)n_ge) / (1.0 + (double)B);
+    out->fraction = B > 0 ? (double)n_ge / (double)B : 0.0;
+}
 
 extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, int32_t d,
                                       int64_t n_p, const uint32_t *labels, int32_t B, uint32_t flags,
@@ -77,15 +147,27 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
     a.n_p = n_p;
     a.d = d;
     a.B = std::max<int32_t>(B, 0);
-    a.pb = perm_max_group(d);
     a.path = choose_path(c, d, n, flags);
     if (a.path == PATH_R16 && n > 65536) a.path = PATH_F32;  // keep the pipeline free of host syncs
     a.plan = plan_for(c, a.path, d, n, n_p);
+    // permutation kernel shape: forced (tests), tuned, or the default
+    a.pb = perm_max_group(d);
+    a.waves = PERM_DEFAULT_WAVES;
+    bool tune = false;
+    if (c->force_perm_waves && perm_shape_ok(d, c->force_perm_pb, c->force_perm_waves)) {
+        a.waves = c->force_perm_waves;
+        a.pb = c->force_perm_pb;
+    } else if (!tuner_lookup_perm(c->tuner, a.path, d, n, &a.waves, &a.pb)) {
+        a.pb = perm_max_group(d);
+        a.waves = PERM_DEFAULT_WAVES;
+        // tune once per key on sizeable batches (small ones are launch-bound)
+        tune = c->tuner && !(c->opt_flags & DDKS_NO_AUTOTUNE) && a.B >= 64 && n >= 4096;
+    }
 
     // every buffer the pipeline touches, allocated before any capture
-    const int64_t gq = (a.B + a.pb - 1) / a.pb;
     int st = ensure(c, c->z, (size_t)n * d * sizeof(float), "points");
-    if (!st && a.B > 0) st = ensure(c, c->inc, (size_t)std::max<int64_t>(gq, 1) * n * (a.pb / 4) * 8, "increments");
+    if (!st && a.B > 0)
+        st = ensure(c, c->inc, std::max(inc_bytes(n, a.B, 4), inc_bytes(n, a.B, perm_max_group(d))), "increments");
     if (!st) st = ensure(c, c->obs, (size_t)n * bins * 2 * sizeof(uint32_t), "observed counts");
     if (!st && !dev && a.B > 0) st = ensure(c, c->labels, (size_t)a.B * words * sizeof(uint32_t), "labels");
     if (!st && !dev && a.B > 0) st = ensure(c, c->nums, (size_t)a.B * sizeof(uint64_t), "nums");
@@ -109,13 +191,22 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
         if (st) return st;
     }
 
+    if (tune && a.B > 0) {
+        st = tune_perm(c, a, s);
+        if (st) return st;
+        if (!tuner_lookup_perm(c->tuner, a.path, d, n, &a.waves, &a.pb)) {
+            a.pb = perm_max_group(d);
+            a.waves = PERM_DEFAULT_WAVES;
+        }
+    }
     if (a.B == 0) {
         st = enqueue_batch(c, a, s);  // observed split only (launch_perm_prepare is a no-op)
     } else {
         const std::vector<uint64_t> key = {
             (uint64_t)n, (uint64_t)n_p, (uint64_t)d, (uint64_t)a.B, (uint64_t)a.path, (uint64_t)a.pb,
             (uint64_t)(uintptr_t)a.srcZ, (uint64_t)(uintptr_t)a.labels, (uint64_t)(uintptr_t)a.nums,
-            c->buf_gen, (uint64_t)a.plan.waves, (uint64_t)a.plan.chunks, (uint64_t)(uintptr_t)s};
+            c->buf_gen, (uint64_t)a.plan.waves, (uint64_t)a.plan.chunks, (uint64_t)(uintptr_t)s,
+            (uint64_t)a.waves};
         if (c->batch_exec && c->batch_key != key) {
             (void)hipGraphExecDestroy(c->batch_exec);
             c->batch_exec = nullptr;
@@ -164,10 +255,7 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
     if (r.flags & 2u) return fail(c, DDKS_E_INVALID_ARG, "a label row does not hold exactly n_p first-sample bits");
     if (r.flags & 1u) return fail(c, DDKS_E_NONFINITE, "input contains NaN or infinity");
     if (summary) {
-        summary->B = a.B;
-        summary->n_ge = a.B > 0 ? r.ge : 0;
-        summary->p_value = (1.0 + (double)summary->n_ge) / (1.0 + (double)a.B);
-        summary->fraction = a.B > 0 ? (double)summary->n_ge / (double)a.B : 0.0;
+        perm_summary_fill(a.B, a.B > 0 ? r.ge : 0, summary);
     }
     if (observed) {
         observed->num = r.num;
@@ -180,5 +268,15 @@ extern "C" int ddks_permutation_batch(ddks_ctx *c, const float *Zin, int64_t n, 
         observed->n_q = n - n_p;
         observed->S = -1.0;
     }
+    return DDKS_OK;
+}
+
+extern "C" int ddks_perm_summary_of(const uint64_t *nums, int32_t B, uint64_t num_obs,
+                                    ddks_perm_summary *out)
+{
+    if (!out || B < 0 || (B > 0 && !nums)) return DDKS_E_INVALID_ARG;
+    uint64_t ge = 0;
+    for (int32_t b = 0; b < B; ++b) ge += nums[b] >= num_obs ? 1 : 0;
+    perm_summary_fill(B, ge, out);
     return DDKS_OK;
 }

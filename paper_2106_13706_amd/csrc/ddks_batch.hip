@@ -11,6 +11,8 @@
 // label-free total: c_Q = c_all - c_P, with c_all taken from the counts of
 // the observed split.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <stdint.h>
 
 #include <algorithm>
@@ -222,9 +224,6 @@ hipError_t launch_count_ge(const unsigned long long *nums, int B, ResultDev *res
     return hipGetLastError();
 }
 
-// Waves per block of the permutation kernel (they share one set of counters).
-static constexpr int PERM_WAVES = 8;
-
 size_t perm_lds_bytes(int d, int pb) { return (size_t)(pb / 4) * ((size_t)1 << d) * 64 * 8; }
 
 int perm_max_group(int d)
@@ -257,59 +256,76 @@ hipError_t launch_perm_prepare(const uint32_t *labels, int64_t n, int B, int64_t
     return hipSuccess;
 }
 
-template <int D, int PATH, int PB>
+template <int D, int PATH, int PB, int W>
 static hipError_t launch_perm_t(const void *Z, int64_t N, int64_t n_p, const uint64_t *inc, int B,
                                 const uint32_t *obs, unsigned long long *nums, hipStream_t s)
 {
     const size_t lds = perm_lds_bytes(D, PB);
-    static bool attr = false;
-    if (!attr && lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void *)k_perm<D, PATH, PB, PERM_WAVES>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            (void)hipGetLastError();
-        attr = true;
-    }
+    static std::once_flag attr;
+    if (lds > 64 * 1024)
+        std::call_once(attr, [lds] {
+            if (hipFuncSetAttribute((const void *)k_perm<D, PATH, PB, W>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                (void)hipGetLastError();
+        });
     dim3 grid((unsigned)((N + 63) / 64), (unsigned)((B + PB - 1) / PB));
-    hipLaunchKernelGGL((k_perm<D, PATH, PB, PERM_WAVES>), grid, dim3(PERM_WAVES * 64), lds, s, Z, N, n_p,
-                       N - n_p, inc, B, obs, nums);
+    hipLaunchKernelGGL((k_perm<D, PATH, PB, W>), grid, dim3(W * 64), lds, s, Z, N, n_p, N - n_p, inc, B,
+                       obs, nums);
     return hipGetLastError();
 }
 
-template <int D, int PATH>
-static hipError_t launch_perm_d(int pb, const void *Z, int64_t N, int64_t n_p, const uint64_t *inc,
+template <int D, int PATH, int PB>
+static hipError_t launch_perm_w(int waves, const void *Z, int64_t N, int64_t n_p, const uint64_t *inc,
                                 int B, const uint32_t *obs, unsigned long long *nums, hipStream_t s)
 {
-    if (pb == 4) return launch_perm_t<D, PATH, 4>(Z, N, n_p, inc, B, obs, nums, s);
-    if constexpr (D <= 6)
-        if (pb == 8) return launch_perm_t<D, PATH, 8>(Z, N, n_p, inc, B, obs, nums, s);
-    return hipErrorInvalidValue;
-}
-
-template <int PATH>
-static hipError_t launch_perm_p(int d, int pb, const void *Z, int64_t N, int64_t n_p,
-                                const uint64_t *inc, int B, const uint32_t *obs,
-                                unsigned long long *nums, hipStream_t s)
-{
-    switch (d) {
-    case 1: return launch_perm_d<1, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
-    case 2: return launch_perm_d<2, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
-    case 3: return launch_perm_d<3, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
-    case 4: return launch_perm_d<4, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
-    case 5: return launch_perm_d<5, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
-    case 6: return launch_perm_d<6, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
-    case 7: return launch_perm_d<7, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
-    case 8: return launch_perm_d<8, PATH>(pb, Z, N, n_p, inc, B, obs, nums, s);
+    switch (waves) {
+    case 4: return launch_perm_t<D, PATH, PB, 4>(Z, N, n_p, inc, B, obs, nums, s);
+    case 8: return launch_perm_t<D, PATH, PB, 8>(Z, N, n_p, inc, B, obs, nums, s);
+    case 16: return launch_perm_t<D, PATH, PB, 16>(Z, N, n_p, inc, B, obs, nums, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_perm(int path, int d, int pb, const void *Z, int64_t N, int64_t n_p,
+template <int D, int PATH>
+static hipError_t launch_perm_d(int pb, int waves, const void *Z, int64_t N, int64_t n_p, const uint64_t *inc,
+                                int B, const uint32_t *obs, unsigned long long *nums, hipStream_t s)
+{
+    if (pb == 4) return launch_perm_w<D, PATH, 4>(waves, Z, N, n_p, inc, B, obs, nums, s);
+    if constexpr (D <= 6)
+        if (pb == 8) return launch_perm_w<D, PATH, 8>(waves, Z, N, n_p, inc, B, obs, nums, s);
+    return hipErrorInvalidValue;
+}
+
+template <int PATH>
+static hipError_t launch_perm_p(int d, int pb, int waves, const void *Z, int64_t N, int64_t n_p,
+                                const uint64_t *inc, int B, const uint32_t *obs,
+                                unsigned long long *nums, hipStream_t s)
+{
+    switch (d) {
+    case 1: return launch_perm_d<1, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    case 2: return launch_perm_d<2, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    case 3: return launch_perm_d<3, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    case 4: return launch_perm_d<4, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    case 5: return launch_perm_d<5, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    case 6: return launch_perm_d<6, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    case 7: return launch_perm_d<7, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    case 8: return launch_perm_d<8, PATH>(pb, waves, Z, N, n_p, inc, B, obs, nums, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool perm_shape_ok(int d, int pb, int waves)
+{
+    return (pb == 4 || (pb == 8 && d <= 6)) && (waves == 4 || waves == 8 || waves == 16);
+}
+
+hipError_t launch_perm(int path, int d, int pb, int waves, const void *Z, int64_t N, int64_t n_p,
                        const uint64_t *inc, int B, const uint32_t *obs_counts,
                        unsigned long long *nums, hipStream_t s)
 {
     if (B < 1 || N < 2 || n_p < 1 || n_p >= N || n_p > 65535) return hipErrorInvalidValue;
-    if (path == PATH_F32) return launch_perm_p<PATH_F32>(d, pb, Z, N, n_p, inc, B, obs_counts, nums, s);
-    if (path == PATH_R16) return launch_perm_p<PATH_R16>(d, pb, Z, N, n_p, inc, B, obs_counts, nums, s);
+    if (path == PATH_F32) return launch_perm_p<PATH_F32>(d, pb, waves, Z, N, n_p, inc, B, obs_counts, nums, s);
+    if (path == PATH_R16) return launch_perm_p<PATH_R16>(d, pb, waves, Z, N, n_p, inc, B, obs_counts, nums, s);
     return hipErrorInvalidValue;
 }
 

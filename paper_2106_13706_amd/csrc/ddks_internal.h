@@ -30,14 +30,16 @@ struct PackedTest {
     int64_t N, n_p, n_q;
     int64_t groups;     // ceil(N / 64)
     int64_t bb_offset;  // first BlockBest slot of this test
-    int32_t hists;      // LDS histograms per block (sweep_hists for PACKED_WAVES, N)
+    int32_t hists;      // LDS histograms per block (sweep_hists for the launch's waves, N)
     int32_t path;       // PATH_F32 (Z fp32) or PATH_R16 (Z rank-encoded)
 };
 
 // LDS a block may use (gfx950: 160 KB per CU, all of it addressable by one block).
 constexpr int MAX_LDS_BYTES = 160 * 1024;
-// Waves per block of the packed (many-test) sweep.
+// Waves per block of the packed (many-test) sweep: the default, and the
+// largest (which bounds the tests admitted to packed launches).
 constexpr int PACKED_WAVES = 8;
+constexpr int PACKED_MAX_WAVES = 16;
 
 // Launch shape of one sweep.
 struct SweepPlan {
@@ -154,11 +156,12 @@ hipError_t launch_reduce(const BlockBest *block_best, int64_t nblocks, uint32_t 
 // ---------------------------------------------------------------- packed tests
 
 // One launch over work items (test, origin group) of tests of dimension d on
-// one path, each test swept in a single chunk by PACKED_WAVES waves with
-// test.hists histograms (nonzero sweep_hists(d, PACKED_WAVES, N, n_p, n_q));
-// block results go to bb[test.bb_offset + group].  max_hists: the largest
-// test.hists of the launch (sizes the LDS).
-hipError_t launch_sweep_packed(int path, int d, const PackedTest *tests, const int2 *items,
+// one path, each test swept in a single chunk by `waves` waves (4, 8 or 16;
+// packed_waves_ok) with test.hists histograms (nonzero sweep_hists(d, waves,
+// N, n_p, n_q)); block results go to bb[test.bb_offset + group].  max_hists:
+// the largest test.hists of the launch (sizes the LDS).
+bool packed_waves_ok(int waves);
+hipError_t launch_sweep_packed(int path, int d, int waves, const PackedTest *tests, const int2 *items,
                                int64_t nitems, int max_hists, BlockBest *bb, hipStream_t s);
 // out[t] = the test's maximum with the tie rule, for t < ntests.
 hipError_t launch_reduce_packed(const PackedTest *tests, int64_t ntests, const BlockBest *bb,
@@ -180,7 +183,11 @@ hipError_t launch_perm_prepare(const uint32_t *labels, int64_t n, int B, int64_t
 // nums[b] = max over origins and orthants of |c_P*n_Q - c_Q*n_P| for relabelling b
 // (atomic max; nums must start at zero).  obs_counts: [N][2^d][2] counts of any
 // one split of the same pooled points (only c_P + c_Q is used).  n_p <= 65535.
-hipError_t launch_perm(int path, int d, int pb, const void *Z, int64_t N, int64_t n_p,
+// pb relabellings per block (inc built for the same pb), `waves` waves per
+// block sharing its 64 origins and counters; perm_shape_ok tells which.
+constexpr int PERM_DEFAULT_WAVES = 8;
+bool perm_shape_ok(int d, int pb, int waves);
+hipError_t launch_perm(int path, int d, int pb, int waves, const void *Z, int64_t N, int64_t n_p,
                        const uint64_t *inc, int B, const uint32_t *obs_counts,
                        unsigned long long *nums, hipStream_t s);
 
@@ -219,14 +226,24 @@ hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V
                             uint32_t *part, uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots, uint32_t *counter,
                             uint64_t *keys, uint64_t *inc, hipStream_t s);
 
+// Launch shape of the weighted sweep: waves per block (4, 8 or 16; they
+// share the block's 64 origins) and point chunks (1..16; with more than one
+// the chunks' counts go through partial sums).
+struct VSweepPlan {
+    int waves = 8;
+    int chunks = 1;
+};
+VSweepPlan vsweep_default_plan(int64_t M);
+bool vsweep_plan_ok(const VSweepPlan &p, int64_t M);
+
 // The weighted sweep over the M filled voxels (R: M x point_words(R16, d)
-// scratch, bb: vdks_best_bytes(M), partial: vsweep_partial_bytes(M, d) of
-// scratch, null when that is 0); *out = (num, lowest maximising voxel key,
+// scratch, bb: vdks_best_bytes(M), partial: vsweep_partial_bytes(M, d, plan)
+// of scratch, null when that is 0); *out = (num, lowest maximising voxel key,
 // its lowest code, *flags), *flags cleared.
-size_t vsweep_partial_bytes(int64_t M, int d);
+size_t vsweep_partial_bytes(int64_t M, int d, const VSweepPlan &plan);
 hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
-                         int64_t n_q, uint32_t *R, void *bb, void *partial, uint32_t *flags, ResultDev *out,
-                         hipStream_t s);
+                         int64_t n_q, const VSweepPlan &plan, uint32_t *R, void *bb, void *partial, uint32_t *flags,
+                         ResultDev *out, hipStream_t s);
 
 // ---------------------------------------------------------------- significance
 

@@ -20,6 +20,32 @@ int fail(ddks_ctx *c, int status, const std::string &msg)
     return status;
 }
 
+bool fault_injected(ddks_ctx *c, int site)
+{
+    if (!c || c->fault_site == FAULT_NONE || c->fault_site != site) return false;
+    return c->fault_countdown.fetch_sub(1) == 1;
+}
+
+static void parse_fault_injection(ddks_ctx *c)
+{
+    const char *e = getenv("DDKS_FAULT_INJECT");
+    if (!e) return;
+    static const struct {
+        const char *name;
+        int site;
+    } sites[] = {{"call:", FAULT_CALL}, {"serve_launch:", FAULT_SERVE_LAUNCH}, {"serve_event:", FAULT_SERVE_EVENT}};
+    for (const auto &x : sites) {
+        const size_t n = strlen(x.name);
+        if (strncmp(e, x.name, n) == 0) {
+            const long long k = atoll(e + n);
+            if (k >= 1) {
+                c->fault_site = x.site;
+                c->fault_countdown = k;
+            }
+        }
+    }
+}
+
 int hip_check(ddks_ctx *c, hipError_t e, const char *what)
 {
     if (e == hipSuccess) return DDKS_OK;
@@ -201,14 +227,22 @@ int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, 
         if (st) return st;
         partial = c->partial.ptr;
     }
-    BlockBest *bb = (BlockBest *)c->block_best.ptr;
     const bool prof = c->profile && s == c->stream && !c->batch_capturing;
+    return sweep_into(c, plan, zdata, N, n_p, n_q, counts_dev, res, s, shifts, (BlockBest *)c->block_best.ptr,
+                      partial, shifts ? c->rank_scratch.ptr : nullptr, prof);
+}
+
+int sweep_into(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p, int64_t n_q,
+               uint32_t *counts_dev, ResultDev *res, hipStream_t s, uint32_t shifts, BlockBest *bb,
+               void *partial, void *rank_scratch, bool prof)
+{
+    if (shifts && plan.chunks < 2) return fail(c, DDKS_E_DEVICE, "shifted ranks need a chunked plan");
     if (prof) (void)hipEventRecord(c->ev[0], s);
-    st = hip_check(c, launch_sweep(plan, zdata, N, n_p, n_q, partial, bb, counts_dev, s), "sweep launch");
+    int st = hip_check(c, launch_sweep(plan, zdata, N, n_p, n_q, partial, bb, counts_dev, s), "sweep launch");
     if (st) return st;
     if (prof) (void)hipEventRecord(c->ev[1], s);
     if (shifts) {
-        st = hip_check(c, launch_rank_fixups(plan, rank16_tables(c->rank_scratch.ptr, N, plan.d), N, n_p, shifts,
+        st = hip_check(c, launch_rank_fixups(plan, rank16_tables(rank_scratch, N, plan.d), N, n_p, shifts,
                                              partial, s),
                        "rank fixup launch");
         if (st) return st;
@@ -416,6 +450,22 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     if (o.tune_cache) c->tune_cache = o.tune_cache;
     if (const char *e = getenv("DDKS_FORCE_WAVES")) c->force_waves = atoi(e);
     if (const char *e = getenv("DDKS_FORCE_CHUNKS")) c->force_chunks = atoll(e);
+    if (const char *e = getenv("DDKS_FORCE_PERM")) {
+        int w = 0, pb = 0;
+        if (sscanf(e, "%d:%d", &w, &pb) == 2) {
+            c->force_perm_waves = w;
+            c->force_perm_pb = pb;
+        }
+    }
+    if (const char *e = getenv("DDKS_FORCE_PACKED_WAVES")) c->force_packed_waves = atoi(e);
+    if (const char *e = getenv("DDKS_FORCE_VSWEEP")) {
+        int w = 0, ch = 0;
+        if (sscanf(e, "%d:%d", &w, &ch) == 2) {
+            c->force_vsweep.waves = w;
+            c->force_vsweep.chunks = ch;
+        }
+    }
+    parse_fault_injection(c);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
         delete c;
@@ -490,6 +540,8 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     const int64_t N = n_p + n_q;
     if (N > 0x7fffffffLL) return fail(c, DDKS_E_INVALID_ARG, "n_p + n_q exceeds 2^31 - 1");
     if (hipSetDevice(c->device) != hipSuccess) return hip_check(c, hipGetLastError(), "hipSetDevice");
+    if (fault_injected(c, FAULT_CALL))
+        return hip_check(c, hipErrorLaunchFailure, "injected launch failure (DDKS_FAULT_INJECT)");
     const bool dev = (flags & DDKS_DEVICE_PTRS) != 0;
     hipStream_t s = c->stream;
     const size_t bins = (size_t)1 << d;

@@ -40,6 +40,11 @@ struct ddks_ctx {
     std::string tune_cache;
     int force_waves = 0;   // test override (DDKS_FORCE_WAVES)
     int64_t force_chunks = 0;  // test override (DDKS_FORCE_CHUNKS)
+    int force_perm_waves = 0, force_perm_pb = 0;  // test override (DDKS_FORCE_PERM="waves:pb")
+    int force_packed_waves = 0;  // test override (DDKS_FORCE_PACKED_WAVES)
+    ddks::VSweepPlan force_vsweep{0, 1};  // test override (DDKS_FORCE_VSWEEP="waves:chunks")
+    int fault_site = 0;        // test override (DDKS_FAULT_INJECT), see fault_injected
+    std::atomic<int64_t> fault_countdown{0};
     std::atomic<bool> poisoned{false};
     std::string last_error;
     std::mutex mu;  // serialises the synchronous calls on `stream`
@@ -80,6 +85,16 @@ struct ddks_ctx {
 
 namespace ddks {
 
+// Test-only fault injection, for the error paths that a real device fault
+// would take: with DDKS_FAULT_INJECT="<site>:<k>" in the environment at
+// context creation (site: call, serve_launch or serve_event), the k-th time
+// the context reaches that site (k >= 1) the library acts as if the HIP
+// runtime had reported a launch failure there.  Nothing is launched at a
+// failing call or serving launch; a failing serving event is reported only
+// after the launch it marks has really completed.
+enum FaultSite : int { FAULT_NONE = 0, FAULT_CALL = 1, FAULT_SERVE_LAUNCH = 2, FAULT_SERVE_EVENT = 3 };
+bool fault_injected(ddks_ctx *c, int site);
+
 // Records an error on the context and returns status.
 int fail(ddks_ctx *c, int status, const std::string &msg);
 // Checks a HIP return code; on failure poisons the context.
@@ -105,6 +120,14 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p);
 // corrections run between sweep and score.
 int run_sweep(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p,
               int64_t n_q, uint32_t *counts_dev, ddks::ResultDev *res, hipStream_t s, uint32_t shifts = 0);
+
+// run_sweep on buffers the caller provides (block_best: plan.groups entries;
+// partial: partial_bytes(plan) when plan.chunks > 1; rank_scratch: the
+// encoding's tables when shifts != 0); allocates nothing.  prof: record the
+// timing events of DDKS_PROFILE_KERNELS.
+int sweep_into(ddks_ctx *c, const SweepPlan &plan, const void *zdata, int64_t N, int64_t n_p, int64_t n_q,
+               uint32_t *counts_dev, ddks::ResultDev *res, hipStream_t s, uint32_t shifts, ddks::BlockBest *bb,
+               void *partial, void *rank_scratch, bool prof);
 
 // Folds the events recorded by the last run_sweep into c->prof (after the
 // stream has been synchronised).
@@ -143,5 +166,16 @@ bool tuner_lookup(Tuner *t, int path, int d, int64_t N, SweepPlan *plan);
 int tune_sweep(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p, int64_t n_q, const void *zdata);
 // True if tune_sweep would time candidate shapes for this key.
 bool tune_pending(ddks_ctx *c, int path, int d, int64_t N);
+// The permutation kernel's tuned (waves, relabellings per block) for (path, d,
+// log2 n), and recording one.
+bool tuner_lookup_perm(Tuner *t, int path, int d, int64_t n, int *waves, int *pb);
+void tuner_store_perm(Tuner *t, int path, int d, int64_t n, int waves, int pb);
+// The packed (serving) sweep's tuned waves per block for (path, d, log2 of
+// the launch's largest test), and recording one.
+bool tuner_lookup_packed(Tuner *t, int path, int d, int64_t n, int *waves);
+void tuner_store_packed(Tuner *t, int path, int d, int64_t n, int waves);
+// vdKS's weighted sweep: the tuned (waves, chunks) for (d, log2 of the filled voxels).
+bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, VSweepPlan *plan);
+void tuner_store_vsweep(Tuner *t, int d, int64_t M, const VSweepPlan &plan);
 
 }  // namespace ddks

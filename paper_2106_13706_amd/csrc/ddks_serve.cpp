@@ -104,9 +104,12 @@ struct Req {
     uint32_t shifts = 0;      // shifted position codes (PATH_R16 past 65536 points)
     bool solo = false;        // swept on its own with `plan` (not packed)
     SweepPlan plan;
+    int sig_model = -1;       // analytic significance asked for: SIG_MODEL_*, else -1
+    int sig_rows = 0;         // its tail kernel's waves in flight
     std::vector<float> data;  // P then Q
     // arena layout: fp32 points | rank-encoded points (PATH_R16) | block results
-    size_t pts_bytes = 0, r16_bytes = 0, bytes = 0;
+    // | (with the significance) counts [N][2^d][2] | significance scratch
+    size_t pts_bytes = 0, r16_bytes = 0, bb_bytes = 0, counts_bytes = 0, sig_bytes = 0, bytes = 0;
     int64_t off = -1;
     bool done = false;
     int status = DDKS_OK;
@@ -125,6 +128,7 @@ struct Slot {
     PackedTest *tests_h = nullptr, *tests_d = nullptr;
     int2 *items_h = nullptr, *items_d = nullptr;
     ResultDev *res_h = nullptr, *res_d = nullptr;
+    double *S_h = nullptr, *S_d = nullptr;  // significance of each test that asked for it
     size_t cap_tests = 0, cap_items = 0;
     // rank encoding of this slot's requests, one after another on its stream
     void *rank_scratch = nullptr;
@@ -133,6 +137,19 @@ struct Slot {
     void *partial = nullptr;
     uint32_t *flags_d = nullptr;
 };
+
+// Packed launches of one batch: tests [i0, i1) share a dimension and a path.
+struct PackedRun {
+    size_t i0 = 0, i1 = 0, items = 0;
+    int waves = PACKED_WAVES;
+    int64_t maxN = 0;
+    bool tune = false;
+    std::vector<int> cand;  // waves to time when tuning
+};
+
+// Work items a packed launch needs before its timing is worth recording
+// (fewer leave the GPU mostly idle and time the launch, not the shape).
+static constexpr size_t PACKED_TUNE_MIN_ITEMS = 1024;
 
 struct Serve {
     ddks_ctx *c = nullptr;
@@ -161,8 +178,11 @@ struct Serve {
     hipEvent_t ref = nullptr;
     std::vector<std::pair<float, float>> spans;
 
+    hipEvent_t tune_e0 = nullptr, tune_e1 = nullptr;  // timing of packed-sweep shapes
+
     int grow_slot(Slot &s, size_t tests, size_t items);
     bool launch_batch(Slot &s, std::vector<Req *> &batch);
+    void fail_req(Req *r);
     void retire(Slot &s);
     void loop();
 };
@@ -175,14 +195,20 @@ int Serve::grow_slot(Slot &s, size_t tests, size_t items)
         if (s.tests_d) (void)hipFree(s.tests_d);
         if (s.res_h) (void)hipHostFree(s.res_h);
         if (s.res_d) (void)hipFree(s.res_d);
+        if (s.S_h) (void)hipHostFree(s.S_h);
+        if (s.S_d) (void)hipFree(s.S_d);
         s.tests_h = nullptr;
         s.tests_d = nullptr;
         s.res_h = nullptr;
         s.res_d = nullptr;
+        s.S_h = nullptr;
+        s.S_d = nullptr;
         if (hipHostMalloc((void **)&s.tests_h, n * sizeof(PackedTest), 0) != hipSuccess ||
             hipMalloc((void **)&s.tests_d, n * sizeof(PackedTest)) != hipSuccess ||
             hipHostMalloc((void **)&s.res_h, n * sizeof(ResultDev), 0) != hipSuccess ||
-            hipMalloc((void **)&s.res_d, n * sizeof(ResultDev)) != hipSuccess)
+            hipMalloc((void **)&s.res_d, n * sizeof(ResultDev)) != hipSuccess ||
+            hipHostMalloc((void **)&s.S_h, n * sizeof(double), 0) != hipSuccess ||
+            hipMalloc((void **)&s.S_d, n * sizeof(double)) != hipSuccess)
             return DDKS_E_DEVICE;
         s.cap_tests = n;
     }
@@ -204,6 +230,10 @@ int Serve::grow_slot(Slot &s, size_t tests, size_t items)
 // dimension present, then the per-test reductions and the result copy.
 bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
 {
+    if (fault_injected(c, FAULT_SERVE_LAUNCH)) {
+        error = "injected serving launch failure (DDKS_FAULT_INJECT)";
+        return false;
+    }
     // packed tests first (sorted by dimension and path), then the solo ones
     std::stable_sort(batch.begin(), batch.end(), [](const Req *a, const Req *b) {
         if (a->solo != b->solo) return !a->solo;
@@ -215,6 +245,50 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
             nitems += (size_t)((r->N + 63) / 64);
             ++npacked;
         }
+    // one packed launch per run of equal dimension and path; its waves per
+    // block: forced (tests), tuned for (path, d, log2 of the run's largest
+    // test), or the default, and timed on this launch when not yet tuned
+    std::vector<PackedRun> runs;
+    std::vector<int> hists(batch.size(), 1);
+    for (size_t i0 = 0; i0 < npacked;) {
+        PackedRun run;
+        run.i0 = i0;
+        run.i1 = i0;
+        int64_t maxN = 0;
+        while (run.i1 < npacked && batch[run.i1]->d == batch[i0]->d && batch[run.i1]->path == batch[i0]->path) {
+            maxN = std::max(maxN, batch[run.i1]->N);
+            run.items += (size_t)((batch[run.i1]->N + 63) / 64);
+            ++run.i1;
+        }
+        const int d = batch[i0]->d, path = batch[i0]->path;
+        // waves w serve the run if every test has histograms for it, as many
+        // as for the default (the test table holds one count per test)
+        auto serves = [&](int w) {
+            if (!packed_waves_ok(w)) return false;
+            for (size_t k = run.i0; k < run.i1; ++k) {
+                const Req *r = batch[k];
+                const int h = sweep_hists(d, w, r->N, r->n_p, r->n_q);
+                if (h == 0 || h != sweep_hists(d, PACKED_WAVES, r->N, r->n_p, r->n_q)) return false;
+            }
+            return true;
+        };
+        int w = 0;
+        if (c->force_packed_waves && serves(c->force_packed_waves)) {
+            w = c->force_packed_waves;
+        } else if (!(tuner_lookup_packed(c->tuner, path, d, maxN, &w) && serves(w))) {
+            w = PACKED_WAVES;
+            run.tune = c->tuner && !(c->opt_flags & DDKS_NO_AUTOTUNE) && run.items >= PACKED_TUNE_MIN_ITEMS;
+            for (int cw : {4, 8, 16})
+                if (run.tune && serves(cw)) run.cand.push_back(cw);
+            run.tune = run.cand.size() >= 2;
+        }
+        run.waves = w;
+        run.maxN = maxN;
+        for (size_t k = run.i0; k < run.i1; ++k)
+            hists[k] = sweep_hists(d, w, batch[k]->N, batch[k]->n_p, batch[k]->n_q);
+        runs.push_back(run);
+        i0 = run.i1;
+    }
     if (grow_slot(s, batch.size(), nitems) != DDKS_OK) {
         error = "serving buffer allocation failed";
         return false;
@@ -236,7 +310,7 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         t.n_q = r->n_q;
         t.groups = (r->N + 63) / 64;
         t.bb_offset = (int64_t)((r->off + r->pts_bytes + r->r16_bytes) / sizeof(BlockBest));
-        t.hists = r->hists;
+        t.hists = r->solo ? r->hists : hists[i];
         t.path = r->path;
         if (!r->solo)
             for (int64_t g = 0; g < t.groups; ++g) s.items_h[it++] = make_int2((int)i, (int)g);
@@ -261,22 +335,46 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
         return false;
     }
     // one launch per run of equal dimension and path (the batch is sorted so)
-    size_t i0 = 0, item0 = 0;
-    while (i0 < npacked) {
-        size_t i1 = i0, items = 0;
+    size_t item0 = 0;
+    for (PackedRun &run : runs) {
+        const int d = batch[run.i0]->d, path = batch[run.i0]->path;
         int max_hists = 1;
-        while (i1 < npacked && batch[i1]->d == batch[i0]->d && batch[i1]->path == batch[i0]->path) {
-            items += (size_t)((batch[i1]->N + 63) / 64);
-            max_hists = std::max(max_hists, batch[i1]->hists);
-            ++i1;
+        for (size_t k = run.i0; k < run.i1; ++k) max_hists = std::max(max_hists, hists[k]);
+        auto launch = [&](int w) {
+            return launch_sweep_packed(path, d, w, s.tests_d, s.items_d + item0, (int64_t)run.items, max_hists,
+                                       bb, s.stream);
+        };
+        if (run.tune) {
+            // time each candidate on this launch's own tests (the sweep only
+            // writes its block results, so repeating it is harmless); the
+            // first timing also waits for the uploads queued before it
+            float best_ms = 1e30f;
+            int best = run.waves;
+            for (int w : run.cand) {
+                float ms_min = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    if (hipEventRecord(tune_e0, s.stream) != hipSuccess || launch(w) != hipSuccess ||
+                        hipEventRecord(tune_e1, s.stream) != hipSuccess || hipEventSynchronize(tune_e1) != hipSuccess) {
+                        error = "packed sweep tuning failed";
+                        return false;
+                    }
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, tune_e0, tune_e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+                    else (void)hipGetLastError();
+                }
+                if (ms_min < best_ms) {
+                    best_ms = ms_min;
+                    best = w;
+                }
+            }
+            tuner_store_packed(c->tuner, path, d, run.maxN, best);
+            run.waves = best;
         }
-        if (launch_sweep_packed(batch[i0]->path, batch[i0]->d, s.tests_d, s.items_d + item0,
-                                (int64_t)items, max_hists, bb, s.stream) != hipSuccess) {
+        if (launch(run.waves) != hipSuccess) {
             error = "packed sweep launch failed";
             return false;
         }
-        item0 += items;
-        i0 = i1;
+        item0 += run.items;
     }
     if (npacked && launch_reduce_packed(s.tests_d, (int64_t)npacked, bb, s.res_d, s.stream) != hipSuccess) {
         error = "packed reduction launch failed";
@@ -298,17 +396,28 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
                 return false;
             }
         }
-        if (launch_sweep(r->plan, t.Z, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess ||
+        uint32_t *counts = r->sig_model >= 0 ? (uint32_t *)((char *)tbb + r->bb_bytes) : nullptr;
+        if (launch_sweep(r->plan, t.Z, r->N, r->n_p, r->n_q, part, tbb, counts, s.stream) != hipSuccess ||
             (r->shifts && launch_rank_fixups(r->plan, rank16_tables(s.rank_scratch, r->N, r->d), r->N, r->n_p,
                                              r->shifts, part, s.stream) != hipSuccess) ||
-            (part && launch_score(r->plan, r->N, r->n_p, r->n_q, part, tbb, nullptr, s.stream) != hipSuccess) ||
+            (part && launch_score(r->plan, r->N, r->n_p, r->n_q, part, tbb, counts, s.stream) != hipSuccess) ||
             launch_reduce(tbb, r->plan.groups, s.flags_d, s.res_d + i, s.stream) != hipSuccess) {
             error = "solo sweep launch failed";
+            return false;
+        }
+        // the analytic significance (Sec. 3) of the statistic just found, from
+        // the counts on the device (num read there too)
+        if (counts && launch_significance(counts, r->N, r->d, r->n_p, r->n_q, 0, &s.res_d[i].num, r->sig_model,
+                                          (char *)counts + r->counts_bytes, r->sig_rows, s.flags_d, s.S_d + i,
+                                          s.stream) != hipSuccess) {
+            error = "significance launch failed";
             return false;
         }
     }
     if (hipMemcpyAsync(s.res_h, s.res_d, batch.size() * sizeof(ResultDev), hipMemcpyDeviceToHost,
                        s.stream) != hipSuccess ||
+        hipMemcpyAsync(s.S_h, s.S_d, batch.size() * sizeof(double), hipMemcpyDeviceToHost, s.stream) !=
+            hipSuccess ||
         hipEventRecord(s.t1, s.stream) != hipSuccess ||
         hipEventRecord(s.done, s.stream) != hipSuccess) {
         error = "packed reduction launch failed";
@@ -320,6 +429,20 @@ bool Serve::launch_batch(Slot &s, std::vector<Req *> &batch)
     launched_tests += batch.size();
     for (const Req *r : batch) shifted_tests += r->shifts ? 1 : 0;
     return true;
+}
+
+// Called with m held: ends a request with a device error and returns its
+// arena space (nothing runs on it any more: the failed loop launches no more
+// work, and a slot's stream has been waited for before its requests get here).
+void Serve::fail_req(Req *r)
+{
+    if (r->done) return;
+    r->status = DDKS_E_DEVICE;
+    r->done = true;
+    if (r->off >= 0) {
+        arena.release((size_t)r->off, r->bytes);
+        r->off = -1;
+    }
 }
 
 // Called with m held, after s.done completed.
@@ -342,7 +465,7 @@ void Serve::retire(Slot &s)
         r->result.d = r->d;
         r->result.n_p = r->n_p;
         r->result.n_q = r->n_q;
-        r->result.S = -1.0;
+        r->result.S = r->sig_model >= 0 ? s.S_h[i] : -1.0;
         r->status = DDKS_OK;
         r->done = true;
         r->t_done = now;
@@ -368,12 +491,21 @@ void Serve::loop()
         for (Slot &s : slots) {
             if (!s.busy) continue;
             hipError_t q = hipEventQuery(s.done);
+            if (q == hipSuccess && fault_injected(c, FAULT_SERVE_EVENT))
+                q = hipErrorLaunchFailure;  // after the real completion: nothing is left running
             if (q == hipSuccess) {
                 retire(s);
                 progress = true;
             } else if (q != hipErrorNotReady) {
                 failed = true;
                 error = std::string("device error in serving: ") + hipGetErrorString(q);
+                (void)hipGetLastError();
+                (void)hipStreamSynchronize(s.stream);  // whatever can still finish, before its memory is returned
+                (void)hipGetLastError();
+                for (Req *r : s.reqs) fail_req(r);
+                s.reqs.clear();
+                s.busy = false;
+                progress = true;
             }
         }
         if (progress) cv_done.notify_all();
@@ -403,22 +535,24 @@ void Serve::loop()
                     items += gi;
                     ready.pop_front();
                 }
-                if (!launch_batch(*free_slot, batch)) failed = true;
+                if (!launch_batch(*free_slot, batch)) {
+                    // the requests taken for the batch are in no queue and on no
+                    // slot: fail them here, once the slot's stream has drained
+                    // any copies enqueued before the failure
+                    failed = true;
+                    (void)hipGetLastError();
+                    (void)hipStreamSynchronize(free_slot->stream);
+                    (void)hipGetLastError();
+                    for (Req *r : batch) fail_req(r);
+                }
                 progress = true;
             }
         }
         if (failed) {
-            // fail every request still held and stop launching
-            auto fail_req = [&](Req *r) {
-                if (!r->done) {
-                    r->status = DDKS_E_DEVICE;
-                    r->done = true;
-                }
-            };
+            // fail every request still queued and stop launching (requests on
+            // slots still in flight are retired, or failed, with their slot)
             for (Req *r : pending) fail_req(r);
             for (Req *r : ready) fail_req(r);
-            for (Slot &s : slots)
-                for (Req *r : s.reqs) fail_req(r);
             pending.clear();
             ready.clear();
             c->poisoned = true;
@@ -516,6 +650,11 @@ int serve_start(ddks_ctx *c)
             return hip_check(c, hipErrorOutOfMemory, "serving stream creation");
         }
     }
+    if (hipEventCreate(&sv->tune_e0) != hipSuccess || hipEventCreate(&sv->tune_e1) != hipSuccess) {
+        c->serve = sv;
+        serve_stop(c);
+        return hip_check(c, hipErrorOutOfMemory, "serving event creation");
+    }
     if (hipEventCreate(&sv->ref) != hipSuccess || hipEventRecord(sv->ref, sv->slots[0].stream) != hipSuccess ||
         hipEventSynchronize(sv->ref) != hipSuccess) {
         c->serve = sv;
@@ -560,6 +699,8 @@ void serve_stop(ddks_ctx *c)
         c->used -= sv->arena.size;
     }
     if (sv->ref) (void)hipEventDestroy(sv->ref);
+    if (sv->tune_e0) (void)hipEventDestroy(sv->tune_e0);
+    if (sv->tune_e1) (void)hipEventDestroy(sv->tune_e1);
     for (auto &kv : sv->table) delete kv.second;
     delete sv;
     c->serve = nullptr;
@@ -577,6 +718,8 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
     if (!req || !ticket || !req->P || !req->Q) return fail(c, DDKS_E_INVALID_ARG, "null pointer argument");
     if (req->d < 1 || req->d > 8) return fail(c, DDKS_E_INVALID_ARG, "d must be in [1, 8]");
     if (req->n_p < 1 || req->n_q < 1) return fail(c, DDKS_E_INVALID_ARG, "each sample needs at least one point");
+    if (req->flags & ~(uint32_t)(DDKS_WITH_SIGNIFICANCE | DDKS_SIG_POISSON))
+        return fail(c, DDKS_E_INVALID_ARG, "request flags other than DDKS_WITH_SIGNIFICANCE and DDKS_SIG_POISSON");
     const int64_t N = req->n_p + req->n_q;
     // one block of PACKED_WAVES waves sweeps a whole test: its histograms must
     // hold either sample's share without overflow and fit in LDS
@@ -642,7 +785,10 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
         *out = p;
         return true;
     };
-    if (sv->use_solo && N >= SERVE_SOLO_MIN) {
+    // The analytic significance needs the counts, which only a solo sweep
+    // writes, so such a test is swept on its own whatever its size.
+    const bool want_S = (req->flags & DDKS_WITH_SIGNIFICANCE) != 0;
+    if (sv->use_solo && (N >= SERVE_SOLO_MIN || want_S)) {
         SweepPlan p;
         if (sv->use_r16 && N > 65536 && N <= SERVE_R16_MAX && solo_plan(PATH_R16, true, &p)) {
             r->path = PATH_R16;
@@ -658,7 +804,19 @@ int ddks_serve_submit(ddks_ctx *c, const ddks_request *req, uint64_t *ticket)
     r->r16_bytes = r->path == PATH_R16
                        ? align256((size_t)N * point_words(PATH_R16, req->d) * sizeof(uint32_t))
                        : 0;
-    r->bytes = r->pts_bytes + r->r16_bytes + align256((size_t)((N + 63) / 64) * sizeof(BlockBest));
+    r->bb_bytes = align256((size_t)((N + 63) / 64) * sizeof(BlockBest));
+    if (want_S) {
+        if (!r->solo) {
+            delete r;
+            return fail(c, DDKS_E_NOT_SUPPORTED,
+                        "the significance of a served test needs a solo sweep, which this memory budget leaves out");
+        }
+        r->sig_model = (req->flags & DDKS_SIG_POISSON) ? SIG_MODEL_POISSON : SIG_MODEL_BINOMIAL;
+        r->sig_rows = significance_rows(req->n_q, r->sig_model);
+        r->counts_bytes = align256((size_t)N * ((size_t)2 << req->d) * sizeof(uint32_t));
+        r->sig_bytes = align256(significance_scratch_bytes(req->n_p, req->n_q, r->sig_rows, r->sig_model) + 64);
+    }
+    r->bytes = r->pts_bytes + r->r16_bytes + r->bb_bytes + r->counts_bytes + r->sig_bytes;
     std::lock_guard<std::mutex> lk(sv->m);
     if (sv->failed) {
         delete r;

@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "ddks_internal.h"
 
@@ -465,14 +466,14 @@ hipError_t launch_significance(const uint32_t *counts, int64_t N, int d, int64_t
         // about one block per CU, each with its own LDS histogram
         const unsigned hb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((entries + 1023) / 1024, 256));
         const size_t lds = (size_t)(n_q + 1) * sizeof(uint32_t);
-        static bool attr = false;
-        if (!attr) {
+        // once per process (serving threads and plain calls may get here together)
+        static std::once_flag attr;
+        std::call_once(attr, [] {
             if (hipFuncSetAttribute((const void *)k_sig_hist<true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     HIST_LDS * (int)sizeof(uint32_t)) != hipSuccess)
                 (void)hipGetLastError();
-            attr = true;
-        }
+        });
         hipLaunchKernelGGL(k_sig_hist<true>, dim3(hb), dim3(1024), lds, s, counts, entries, n_q, hist,
                            flags);
     } else {

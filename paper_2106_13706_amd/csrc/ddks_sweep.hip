@@ -32,6 +32,8 @@
 // counter: +1 for a point of P, +65536 for a point of Q (no histogram ever
 // receives more than 65535 points of either sample).
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <stdint.h>
 
 #include "ddks_device.h"
@@ -423,14 +425,15 @@ hipError_t launch_ingest_f32(const float *P, int64_t n_p, const float *Q, int64_
 }
 
 // Lets a kernel instance use more than the default 64 KB of dynamic LDS (once
-// per instance; if the runtime refuses, the launch reports the real error).
-static void allow_big_lds(const void *kernel, bool &done)
+// per instance, whichever thread launches it first; if the runtime refuses,
+// the launch reports the real error).
+static void allow_big_lds(const void *kernel, std::once_flag &once)
 {
-    if (done) return;
-    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, MAX_LDS_BYTES) !=
-        hipSuccess)
-        (void)hipGetLastError();
-    done = true;
+    std::call_once(once, [kernel] {
+        if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, MAX_LDS_BYTES) !=
+            hipSuccess)
+            (void)hipGetLastError();
+    });
 }
 
 template <int D, int PATH, int W>
@@ -439,7 +442,7 @@ static hipError_t launch_sweep_t(const SweepPlan &p, const void *Z, int64_t N, i
                                  hipStream_t s)
 {
     size_t lds = sweep_lds_bytes(p);
-    static bool attr_set = false;
+    static std::once_flag attr_set;
     if (lds > 64 * 1024) allow_big_lds((const void *)k_sweep<D, PATH, W>, attr_set);
     dim3 grid((unsigned)p.groups, (unsigned)p.chunks);
     hipLaunchKernelGGL((k_sweep<D, PATH, W>), grid, dim3(W * 64), lds, s, Z, N, n_p, n_q,
@@ -507,25 +510,38 @@ static hipError_t launch_packed_t(const PackedTest *tests, const int2 *items, in
     p.hists = max_hists;
     const size_t lds = sweep_lds_bytes(p);
     if (lds > (size_t)MAX_LDS_BYTES) return hipErrorInvalidValue;
-    static bool attr_set = false;
+    static std::once_flag attr_set;
     if (lds > 64 * 1024) allow_big_lds((const void *)k_sweep_packed<D, PATH, W>, attr_set);
     hipLaunchKernelGGL((k_sweep_packed<D, PATH, W>), dim3((unsigned)nitems), dim3(W * 64), lds, s,
                        tests, items, bb);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_packed(int path, int d, const PackedTest *tests, const int2 *items,
+template <int D, int PATH>
+static hipError_t launch_packed_w(int waves, const PackedTest *tests, const int2 *items, int64_t nitems,
+                                  int max_hists, BlockBest *bb, hipStream_t s)
+{
+    switch (waves) {
+    case 4: return launch_packed_t<D, PATH, 4>(tests, items, nitems, max_hists, bb, s);
+    case 8: return launch_packed_t<D, PATH, 8>(tests, items, nitems, max_hists, bb, s);
+    case 16: return launch_packed_t<D, PATH, 16>(tests, items, nitems, max_hists, bb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool packed_waves_ok(int waves) { return waves == 4 || waves == 8 || waves == 16; }
+
+hipError_t launch_sweep_packed(int path, int d, int waves, const PackedTest *tests, const int2 *items,
                                int64_t nitems, int max_hists, BlockBest *bb, hipStream_t s)
 {
-    if (nitems < 1 || nitems > 0x7fffffff) return hipErrorInvalidValue;
-    if (max_hists < 1 || max_hists > PACKED_WAVES || (max_hists & (max_hists - 1)))
+    if (nitems < 1 || nitems > 0x7fffffff || !packed_waves_ok(waves)) return hipErrorInvalidValue;
+    if (max_hists < 1 || max_hists > waves || (max_hists & (max_hists - 1)))
         return hipErrorInvalidValue;
-    constexpr int W = PACKED_WAVES;
-#define DDKS_PACKED_CASE(DD)                                                                   \
-    case DD:                                                                                   \
-        return path == PATH_F32                                                                \
-                   ? launch_packed_t<DD, PATH_F32, W>(tests, items, nitems, max_hists, bb, s)  \
-                   : launch_packed_t<DD, PATH_R16, W>(tests, items, nitems, max_hists, bb, s);
+#define DDKS_PACKED_CASE(DD)                                                                          \
+    case DD:                                                                                          \
+        return path == PATH_F32                                                                       \
+                   ? launch_packed_w<DD, PATH_F32>(waves, tests, items, nitems, max_hists, bb, s)     \
+                   : launch_packed_w<DD, PATH_R16>(waves, tests, items, nitems, max_hists, bb, s);
     if (path != PATH_F32 && path != PATH_R16) return hipErrorInvalidValue;
     switch (d) {
         DDKS_PACKED_CASE(1)

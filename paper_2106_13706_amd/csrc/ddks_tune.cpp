@@ -1,4 +1,5 @@
-// Launch-shape autotuner for the orthant-counting sweep.
+// Launch-shape autotuner for the orthant-counting sweep (and the shapes of
+// the permutation kernel and of the packed serving sweep).
 //
 // The sweep's speed depends on how many waves share a block's origins (and
 // how many LDS histograms they need, hence occupancy) and on how many point
@@ -66,6 +67,62 @@ static void tuner_store(Tuner *t, int path, int d, int64_t N, int waves, int64_t
             fprintf(f, "%d %d %d %d %lld\n", path, d, bucket(N), waves, (long long)chunks);
             fclose(f);
         }
+}
+
+// Entries of the other kernels share the map and the cache file, under
+// their own kinds in the first field: the permutation kernel as PERM_KIND +
+// path with (waves, relabellings per block), the packed sweep as
+// PACKED_KIND + path with (waves, 0), vdKS's weighted sweep as VSWEEP_KIND
+// with (waves, chunks).
+static constexpr int PERM_KIND = 10, PACKED_KIND = 20;
+
+bool tuner_lookup_perm(Tuner *t, int path, int d, int64_t n, int *waves, int *pb)
+{
+    if (!t) return false;
+    std::lock_guard<std::mutex> lk(t->m);
+    auto it = t->best.find({PERM_KIND + path, d, bucket(n)});
+    if (it == t->best.end() || !perm_shape_ok(d, (int)it->second.second, it->second.first)) return false;
+    *waves = it->second.first;
+    *pb = (int)it->second.second;
+    return true;
+}
+
+void tuner_store_perm(Tuner *t, int path, int d, int64_t n, int waves, int pb)
+{
+    if (t) tuner_store(t, PERM_KIND + path, d, n, waves, pb);
+}
+
+bool tuner_lookup_packed(Tuner *t, int path, int d, int64_t n, int *waves)
+{
+    if (!t) return false;
+    std::lock_guard<std::mutex> lk(t->m);
+    auto it = t->best.find({PACKED_KIND + path, d, bucket(n)});
+    if (it == t->best.end()) return false;
+    *waves = it->second.first;
+    return true;
+}
+
+void tuner_store_packed(Tuner *t, int path, int d, int64_t n, int waves)
+{
+    if (t) tuner_store(t, PACKED_KIND + path, d, n, waves, 0);
+}
+
+static constexpr int VSWEEP_KIND = 30;
+
+bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, VSweepPlan *plan)
+{
+    if (!t) return false;
+    std::lock_guard<std::mutex> lk(t->m);
+    auto it = t->best.find({VSWEEP_KIND, d, bucket(M)});
+    if (it == t->best.end()) return false;
+    plan->waves = it->second.first;
+    plan->chunks = (int)it->second.second;
+    return true;
+}
+
+void tuner_store_vsweep(Tuner *t, int d, int64_t M, const VSweepPlan &plan)
+{
+    if (t) tuner_store(t, VSWEEP_KIND, d, M, plan.waves, plan.chunks);
 }
 
 bool tune_pending(ddks_ctx *c, int path, int d, int64_t N)

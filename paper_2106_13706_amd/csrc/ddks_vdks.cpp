@@ -1,9 +1,74 @@
 // Host side of vdKS (arXiv:2106.13706, Sec. 2.2.2, Alg. 1): ddks_vdks.
 #include <math.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "ddks_runtime.h"
 
 using namespace ddks;
+
+namespace {
+
+// Filled voxels from which the weighted sweep's shape is tuned (fewer are
+// launch-bound: the default shape is as good).
+constexpr int64_t VSWEEP_TUNE_MIN = 4096;
+
+// Times every admissible (waves, chunks) shape of the weighted sweep (the
+// encoding, sweep, chunk scoring and reduction: everything that depends on
+// the shape) twice and records the fastest for (d, log2 M) in the tuner.
+int tune_vsweep(ddks_ctx *c, const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
+                int64_t n_q, uint32_t *scratch_flags, hipStream_t s, VSweepPlan *best)
+{
+    const int64_t groups = (M + 63) / 64;
+    std::vector<VSweepPlan> cand;
+    for (int w : {4, 8, 16})
+        for (int ch : {1, 2, 3, 4, 6, 8, 12, 16}) {
+            VSweepPlan p;
+            p.waves = w;
+            p.chunks = ch;
+            if (!vsweep_plan_ok(p, M) || M / ch < (int64_t)w * 64) continue;  // >= 64 voxels per wave
+            if (groups * ch * w > 65536 * 4) continue;
+            if (vsweep_partial_bytes(M, d, p) > (256ull << 20)) continue;
+            cand.push_back(p);
+        }
+    if (cand.size() < 2) return DDKS_OK;
+    size_t pmax = 0;
+    for (const VSweepPlan &p : cand) pmax = std::max(pmax, vsweep_partial_bytes(M, d, p));
+    int st = pmax ? ensure(c, c->partial, pmax, "voxel partial counts") : DDKS_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!st) st = hip_check(c, hipEventCreate(&e0), "hipEventCreate");
+    if (!st) st = hip_check(c, hipEventCreate(&e1), "hipEventCreate");
+    float best_ms = 1e30f;
+    for (const VSweepPlan &p : cand) {
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 2 && !st; ++rep) {
+            st = hip_check(c, hipEventRecord(e0, s), "hipEventRecord");
+            if (!st)
+                st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, p, (uint32_t *)c->zr.ptr,
+                                                c->block_best.ptr, c->partial.ptr, scratch_flags, c->result_dev, s),
+                               "voxel sweep launch");
+            if (!st) st = hip_check(c, hipEventRecord(e1, s), "hipEventRecord");
+            if (!st) st = hip_check(c, hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            if (!st) {
+                if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+                else (void)hipGetLastError();
+            }
+        }
+        if (!st && ms_min < best_ms) {
+            best_ms = ms_min;
+            *best = p;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) return st;
+    tuner_store_vsweep(c->tuner, d, M, *best);
+    return DDKS_OK;
+}
+
+}  // namespace
 
 extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int64_t n_q,
                          int32_t d, int32_t voxels_per_dim, uint32_t flags, ddks_result *out,
@@ -64,9 +129,24 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     if (st) return st;
     const int64_t M = *c->rank_distinct_host;
     if (M < 1 || M > N) return fail(c, DDKS_E_DEVICE, "voxel compaction produced an invalid count");
-    const size_t pb = vsweep_partial_bytes(M, d);
+    VSweepPlan plan = vsweep_default_plan(M);
+    if (c->force_vsweep.waves) {
+        VSweepPlan f = c->force_vsweep;
+        f.chunks = (int)std::min<int64_t>(f.chunks, M);
+        if (vsweep_plan_ok(f, M)) plan = f;
+    } else if (!tuner_lookup_vsweep(c->tuner, d, M, &plan) || !vsweep_plan_ok(plan, M)) {
+        plan = vsweep_default_plan(M);
+        if (c->tuner && !(c->opt_flags & DDKS_NO_AUTOTUNE) && M >= VSWEEP_TUNE_MIN) {
+            // time the admissible shapes on this input once per (d, log2 M);
+            // the timed runs report into a scratch flags word so that the
+            // call's own flags survive them
+            st = tune_vsweep(c, keys, inc, M, d, V, n_p, n_q, counter + 2, s, &plan);
+            if (st) return st;
+        }
+    }
+    const size_t pb = vsweep_partial_bytes(M, d, plan);
     if (pb && (st = ensure(c, c->partial, pb, "voxel partial counts"))) return st;
-    st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, (uint32_t *)c->zr.ptr, c->block_best.ptr,
+    st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, plan, (uint32_t *)c->zr.ptr, c->block_best.ptr,
                                     pb ? c->partial.ptr : nullptr, c->flags_dev, c->result_host, s),
                    "voxel sweep launch");
     if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");

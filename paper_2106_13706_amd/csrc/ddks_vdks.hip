@@ -21,9 +21,12 @@
 //      that any sample size fits, then the scores |c_P n_Q - c_Q n_P| and the
 //      maximum with ties to the lowest voxel key, then the lowest code.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ddks_device.h"
 
@@ -254,15 +257,14 @@ __device__ __forceinline__ bool vbetter(uint64_t an, uint64_t ak, int32_t ac, ui
     return ac < bc;
 }
 
-// Scores the 64 origins of a group from their lane-minor 64-bit counts cnt
-// (bin*64 + lane; LDS or global) and writes the group's best (largest
-// numerator, then lowest voxel key, then lowest code) to bb[group].  red: LDS
-// of W * 64 * 12 bytes, which may alias cnt (it is written only after every
-// wave has read its bins).
-template <int D, int W>
-__device__ __forceinline__ void vfinish(const uint64_t *cnt, uint64_t *red, const uint64_t *__restrict__ keys,
-                                        int64_t M, int64_t n_p, int64_t n_q, int64_t group,
-                                        VBest *__restrict__ bb)
+// Scores the 64 origins of a group from their lane-minor counts: get(j)
+// returns the (c_P, c_Q) of bin j of this lane's origin; writes the group's
+// best (largest numerator, then lowest voxel key, then lowest code) to
+// bb[group].  red: LDS of W * 64 * 12 bytes, which may alias the counts (it
+// is written only after every wave has read its bins).
+template <int D, int W, typename Get>
+__device__ __forceinline__ void vfinish(Get get, uint64_t *red, const uint64_t *__restrict__ keys, int64_t M,
+                                        int64_t n_p, int64_t n_q, int64_t group, VBest *__restrict__ bb)
 {
     constexpr int BINS = Geo<D>::BINS;
     const int lane = threadIdx.x & 63;
@@ -273,9 +275,9 @@ __device__ __forceinline__ void vfinish(const uint64_t *cnt, uint64_t *red, cons
     int32_t bcode = 0x7fffffff;
     if (valid) {
         for (int j = w; j < BINS; j += W) {  // this wave's share of the bins
-            const uint64_t c = cnt[j * 64 + lane];
-            const int64_t cp = (int64_t)(uint32_t)c, cq = (int64_t)(c >> 32);
-            const int64_t sd = cp * n_q - cq * n_p;
+            uint64_t cp, cq;
+            get(j, cp, cq);
+            const int64_t sd = (int64_t)cp * n_q - (int64_t)cq * n_p;
             const uint64_t s = (uint64_t)(sd < 0 ? -sd : sd);
             const int32_t code = j ^ Geo<D>::FLIP;
             if (s > best || (s == best && code < bcode)) {
@@ -326,35 +328,48 @@ __device__ __forceinline__ void vfinish(const uint64_t *cnt, uint64_t *red, cons
     }
 }
 
-// Block (group, chunk): the 64 filled voxels group*64 + lane as origins, the
-// filled voxels of chunk blockIdx.y (of gridDim.y) as weighted points, split
-// over the W waves, one shared histogram of 64-bit bins (lane-minor:
-// bin*64 + lane).  With one chunk the block scores its origins itself;
-// otherwise it adds its counts into G[group][BINS][64] (zeroed beforehand)
-// and k_vscore scores them.
-template <int D, int W>
-__global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ R,
-                                                   const uint64_t *__restrict__ inc,
-                                                   const uint64_t *__restrict__ keys, int64_t M,
-                                                   int64_t n_p, int64_t n_q, unsigned long long *__restrict__ G,
-                                                   VBest *__restrict__ bb)
+// Bins of the weighted sweep: 32-bit words holding c_P | c_Q << 16 when no
+// bin can reach 65536 points of either sample (ds_add_u32, the faster LDS
+// atomic), else 64-bit words c_P | c_Q << 32 (ds_add_u64).
+template <bool WIDE>
+struct VBin {
+    typedef typename std::conditional<WIDE, uint64_t, uint32_t>::type T;
+    typedef __attribute__((address_space(3))) T lds_t;
+    static constexpr int SH = WIDE ? 9 : 8;  // log2 of the bytes of one bin row (64 lanes)
+    // a voxel's increment (c_P in the low, c_Q in the high word) in this format
+    __device__ static __forceinline__ T of(uint64_t v)
+    {
+        if constexpr (WIDE) return v;
+        else return (uint32_t)v | ((uint32_t)(v >> 32) << 16);
+    }
+    __device__ static __forceinline__ void split(T v, uint64_t &cp, uint64_t &cq)
+    {
+        if constexpr (WIDE) {
+            cp = (uint32_t)v;
+            cq = v >> 32;
+        } else {
+            cp = v & 0xffffu;
+            cq = v >> 16;
+        }
+    }
+};
+
+// The weighted sweep of one block's 64 origins over the voxels [c0, c1),
+// split over the W waves, into the block's shared histogram h (lane-minor:
+// bin*64 + lane, zeroed beforehand).
+template <int D, int W, bool WIDE>
+__device__ __forceinline__ void vsweep_range(const uint32_t *__restrict__ R, const uint64_t *__restrict__ inc,
+                                             const Origin<PATH_R16, D> &org, int64_t c0, int64_t c1,
+                                             typename VBin<WIDE>::T *h)
 {
-    constexpr int BINS = Geo<D>::BINS;
+    typedef VBin<WIDE> B;
+    typedef typename B::T T;
+    typedef typename B::lds_t lds_t;
     constexpr int PW = Layout<PATH_R16, D>::PW;
     constexpr int NP = Geo<D>::NPERM;
     constexpr int U = 4;
-    extern __shared__ uint64_t h64[];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t group = blockIdx.x;
-
-    for (int i = threadIdx.x; i < BINS * 64; i += W * 64) h64[i] = 0;
-    const int64_t k = group * 64 + lane;
-    Origin<PATH_R16, D> org;
-    org.load(R, k < M ? k : M - 1);
-    __syncthreads();
-
-    const int64_t c0 = M * (int64_t)blockIdx.y / gridDim.y, c1 = M * ((int64_t)blockIdx.y + 1) / gridDim.y;
     const int64_t per = (c1 - c0 + W - 1) / W;
     int64_t a = c0 + (int64_t)w * per, b = a + per;
     a = a < c1 ? a : c1;
@@ -362,7 +377,7 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
     a = __builtin_amdgcn_readfirstlane((int)a);
     b = __builtin_amdgcn_readfirstlane((int)b);
 
-    const uint32_t base = (uint32_t)(uintptr_t)(lds_u64v *)(h64 + Geo<D>::KOFF * 64 + lane);
+    const uint32_t base = (uint32_t)(uintptr_t)(lds_t *)(h + Geo<D>::KOFF * 64 + lane);
     const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
     // bin addresses of a block of U voxels, and their weighted increments
     auto addrs = [&](const uint32_t (&buf)[U * PW], uint32_t (&ad)[U]) {
@@ -374,12 +389,12 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
             Rg[0][u] = group_bytes<D>(r, 0);
             Rg[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
         }
-        addr4<NP, 9>(Rg, base, ad, w0, w1);
+        addr4<NP, B::SH>(Rg, base, ad, w0, w1);
     };
     auto adds = [&](const uint32_t (&ad)[U], const uint64_t (&iv)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            __hip_atomic_fetch_add((lds_u64v *)(uintptr_t)ad[u], iv[u], __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add((lds_t *)(uintptr_t)ad[u], B::of(iv[u]), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     auto load = [&](int64_t at, uint32_t (&buf)[U * PW], uint64_t (&iv)[U]) {
@@ -430,38 +445,104 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
         signs<PATH_R16, D>(buf, org, r);
         const uint32_t R0 = group_bytes<D>(r, 0);
         const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-        __hip_atomic_fetch_add((lds_u64v *)(uintptr_t)addr1<NP, 9>(R0, R1, base, w0, w1), inc[i],
+        __hip_atomic_fetch_add((lds_t *)(uintptr_t)addr1<NP, B::SH>(R0, R1, base, w0, w1), B::of(inc[i]),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    __syncthreads();
-    if (gridDim.y > 1) {
-        unsigned long long *g = G + (size_t)group * BINS * 64;
-        for (int e = threadIdx.x; e < BINS * 64; e += W * 64) {
-            const uint64_t v = h64[e];
-            if (v) atomicAdd(g + e, (unsigned long long)v);
-        }
-        return;
-    }
-    vfinish<D, W>(h64, h64, keys, M, n_p, n_q, group, bb);
 }
 
-// Scores group blockIdx.x from the counts the chunks added into G.
+// Block (group, chunk): the 64 filled voxels group*64 + lane as origins, the
+// filled voxels of chunk blockIdx.y (of gridDim.y) as weighted points, split
+// over the W waves, one shared histogram (lane-minor: bin*64 + lane).  The
+// block first sums its chunk's increments: when neither sample has more than
+// 65535 points in the chunk, no bin can overflow 16 bits and the histogram
+// takes 32-bit bins.  With one chunk the block scores its origins itself;
+// otherwise it writes its counts (every bin, c_P | c_Q << 32) to
+// G[chunk][group][BINS][64] and k_vscore sums the chunks.
 template <int D, int W>
-__global__ __launch_bounds__(W * 64) void k_vscore(const unsigned long long *__restrict__ G,
+__global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ R,
+                                                   const uint64_t *__restrict__ inc,
+                                                   const uint64_t *__restrict__ keys, int64_t M,
+                                                   int64_t n_p, int64_t n_q, unsigned long long *__restrict__ G,
+                                                   VBest *__restrict__ bb)
+{
+    constexpr int BINS = Geo<D>::BINS;
+    extern __shared__ uint64_t h64[];
+    __shared__ uint64_t tot[2 * W];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t group = blockIdx.x;
+    const int64_t c0 = M * (int64_t)blockIdx.y / gridDim.y, c1 = M * ((int64_t)blockIdx.y + 1) / gridDim.y;
+
+    // the chunk's points per sample
+    uint64_t sp = 0, sq = 0;
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += W * 64) {
+        const uint64_t v = inc[e];
+        sp += (uint32_t)v;
+        sq += v >> 32;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sp += __shfl_xor(sp, off, 64);
+        sq += __shfl_xor(sq, off, 64);
+    }
+    if (lane == 0) {
+        tot[2 * w] = sp;
+        tot[2 * w + 1] = sq;
+    }
+    for (int i = threadIdx.x; i < BINS * 64; i += W * 64) h64[i] = 0;
+    const int64_t k = group * 64 + lane;
+    Origin<PATH_R16, D> org;
+    org.load(R, k < M ? k : M - 1);
+    __syncthreads();
+    sp = 0;
+    sq = 0;
+    for (int v = 0; v < W; ++v) {
+        sp += tot[2 * v];
+        sq += tot[2 * v + 1];
+    }
+    const bool wide = __builtin_amdgcn_readfirstlane((sp > 65535u || sq > 65535u) ? 1 : 0) != 0;
+    if (wide)
+        vsweep_range<D, W, true>(R, inc, org, c0, c1, h64);
+    else
+        vsweep_range<D, W, false>(R, inc, org, c0, c1, reinterpret_cast<uint32_t *>(h64));
+    __syncthreads();
+    if (gridDim.y > 1) {
+        unsigned long long *g = G + ((size_t)blockIdx.y * gridDim.x + group) * BINS * 64;
+        const uint32_t *h32 = reinterpret_cast<const uint32_t *>(h64);
+        for (int e = threadIdx.x; e < BINS * 64; e += W * 64)
+            g[e] = wide ? h64[e] : ((unsigned long long)(h32[e] & 0xffffu) | ((unsigned long long)(h32[e] >> 16) << 32));
+        return;
+    }
+    if (wide) {
+        vfinish<D, W>([&](int j, uint64_t &cp, uint64_t &cq) { VBin<true>::split(h64[j * 64 + lane], cp, cq); },
+                      h64, keys, M, n_p, n_q, group, bb);
+    } else {
+        const uint32_t *h32 = reinterpret_cast<const uint32_t *>(h64);
+        vfinish<D, W>([&](int j, uint64_t &cp, uint64_t &cq) { VBin<false>::split(h32[j * 64 + lane], cp, cq); },
+                      h64, keys, M, n_p, n_q, group, bb);
+    }
+}
+
+// Scores group blockIdx.x from the counts of the `chunks` chunks in G.
+template <int D, int W>
+__global__ __launch_bounds__(W * 64) void k_vscore(const unsigned long long *__restrict__ G, int chunks,
                                                    const uint64_t *__restrict__ keys, int64_t M,
                                                    int64_t n_p, int64_t n_q, VBest *__restrict__ bb)
 {
     __shared__ uint64_t red[W * 64 * 12 / 8];
+    constexpr int BINS = Geo<D>::BINS;
     const int64_t group = blockIdx.x;
-    vfinish<D, W>(reinterpret_cast<const uint64_t *>(G) + (size_t)group * Geo<D>::BINS * 64, red, keys, M,
-                  n_p, n_q, group, bb);
-}
-
-__global__ void k_vzero(unsigned long long *__restrict__ p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0ull;
+    const int lane = threadIdx.x & 63;
+    const size_t stride = (size_t)gridDim.x * BINS * 64;
+    const unsigned long long *g = G + (size_t)group * BINS * 64 + lane;
+    vfinish<D, W>(
+        [&](int j, uint64_t &cp, uint64_t &cq) {
+            uint64_t v = 0;
+            for (int c = 0; c < chunks; ++c) v += g[c * stride + (size_t)j * 64];
+            cp = (uint32_t)v;
+            cq = v >> 32;
+        },
+        red, keys, M, n_p, n_q, group, bb);
 }
 
 __global__ __launch_bounds__(1024) void k_vreduce(const VBest *__restrict__ bb, int64_t n,
@@ -559,60 +640,81 @@ hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V
     }
 }
 
-static constexpr int VSWEEP_WAVES = 8;
-
-size_t vsweep_lds_bytes(int d)
+size_t vsweep_lds_bytes(int d, int waves)
 {
     const size_t hist = ((size_t)1 << d) * 64 * 8;
-    const size_t fin = (size_t)VSWEEP_WAVES * 64 * 12;
+    const size_t fin = (size_t)waves * 64 * 12;
     return std::max(hist, fin);
 }
 
-// Point chunks of the weighted sweep: enough blocks to fill the chip (about
-// four per CU) when the filled voxels are few, each chunk at least 512 points.
-int vsweep_chunks(int64_t M)
+// Default shape of the weighted sweep: 8 waves per block, and point chunks
+// enough for about four blocks per CU when the filled voxels are few, each
+// chunk at least 512 points.
+VSweepPlan vsweep_default_plan(int64_t M)
 {
+    VSweepPlan p;
+    p.waves = 8;
     const int64_t groups = (M + 63) / 64;
-    if (groups >= 1024) return 1;
-    int64_t c = (1024 + groups - 1) / groups;
-    c = std::min<int64_t>(c, std::max<int64_t>(1, M / 512));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(c, 16));
-}
-
-size_t vsweep_partial_bytes(int64_t M, int d)
-{
-    if (vsweep_chunks(M) == 1) return 0;
-    return (size_t)((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint64_t);
-}
-
-template <int D>
-static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int64_t M, int V,
-                                  int64_t n_p, int64_t n_q, uint32_t *R, void *bb, void *partial,
-                                  uint32_t *flags, ResultDev *out, hipStream_t s)
-{
-    constexpr int W = VSWEEP_WAVES;
-    hipLaunchKernelGGL(k_vox_encode<D>, dim3(grid_for(M)), dim3(256), 0, s, keys, M, V, R);
-    const size_t lds = vsweep_lds_bytes(D);
-    static bool attr = false;
-    if (!attr && lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void *)k_vsweep<D, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                MAX_LDS_BYTES) != hipSuccess)
-            (void)hipGetLastError();
-        attr = true;
+    int64_t c = 1;
+    if (groups < 1024) {
+        c = (1024 + groups - 1) / groups;
+        c = std::min<int64_t>(c, std::max<int64_t>(1, M / 512));
+        c = std::max<int64_t>(1, std::min<int64_t>(c, 16));
     }
+    p.chunks = (int)c;
+    return p;
+}
+
+bool vsweep_plan_ok(const VSweepPlan &p, int64_t M)
+{
+    return (p.waves == 4 || p.waves == 8 || p.waves == 16) && p.chunks >= 1 && p.chunks <= 16 &&
+           p.chunks <= M;
+}
+
+size_t vsweep_partial_bytes(int64_t M, int d, const VSweepPlan &p)
+{
+    if (p.chunks <= 1) return 0;
+    return (size_t)p.chunks * ((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint64_t);
+}
+
+template <int D, int W>
+static hipError_t launch_vsweep_w(const uint64_t *keys, const uint64_t *inc, int64_t M, int chunks, int64_t n_p,
+                                  int64_t n_q, const uint32_t *R, void *bb, void *partial, hipStream_t s)
+{
+    const size_t lds = vsweep_lds_bytes(D, W);
+    static std::once_flag attr;
+    if (lds > 64 * 1024)
+        std::call_once(attr, [] {
+            if (hipFuncSetAttribute((const void *)k_vsweep<D, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    MAX_LDS_BYTES) != hipSuccess)
+                (void)hipGetLastError();
+        });
     const int64_t groups = (M + 63) / 64;
-    const int chunks = vsweep_chunks(M);
     unsigned long long *G = (unsigned long long *)partial;
-    if (chunks > 1) {
-        if (!G) return hipErrorInvalidValue;
-        const int64_t n = groups * Geo<D>::BINS * 64;
-        hipLaunchKernelGGL(k_vzero, dim3(grid_for(n)), dim3(256), 0, s, G, n);
-    }
+    if (chunks > 1 && !G) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_vsweep<D, W>), dim3((unsigned)groups, (unsigned)chunks), dim3(W * 64), lds, s, R,
                        inc, keys, M, n_p, n_q, G, (VBest *)bb);
     if (chunks > 1)
-        hipLaunchKernelGGL((k_vscore<D, W>), dim3((unsigned)groups), dim3(W * 64), 0, s, G, keys, M, n_p,
+        hipLaunchKernelGGL((k_vscore<D, W>), dim3((unsigned)groups), dim3(W * 64), 0, s, G, chunks, keys, M, n_p,
                            n_q, (VBest *)bb);
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int64_t M, const VSweepPlan &p,
+                                  int V, int64_t n_p, int64_t n_q, uint32_t *R, void *bb, void *partial,
+                                  uint32_t *flags, ResultDev *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vox_encode<D>, dim3(grid_for(M)), dim3(256), 0, s, keys, M, V, R);
+    hipError_t e;
+    switch (p.waves) {
+    case 4: e = launch_vsweep_w<D, 4>(keys, inc, M, p.chunks, n_p, n_q, R, bb, partial, s); break;
+    case 8: e = launch_vsweep_w<D, 8>(keys, inc, M, p.chunks, n_p, n_q, R, bb, partial, s); break;
+    case 16: e = launch_vsweep_w<D, 16>(keys, inc, M, p.chunks, n_p, n_q, R, bb, partial, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    const int64_t groups = (M + 63) / 64;
     hipLaunchKernelGGL(k_vreduce, dim3(1), dim3(1024), 0, s, (const VBest *)bb, groups, flags, out);
     return hipGetLastError();
 }
@@ -620,12 +722,13 @@ static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int
 size_t vdks_best_bytes(int64_t M) { return (size_t)((M + 63) / 64) * sizeof(VBest); }
 
 hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
-                         int64_t n_q, uint32_t *R, void *bb, void *partial, uint32_t *flags, ResultDev *out,
-                         hipStream_t s)
+                         int64_t n_q, const VSweepPlan &plan, uint32_t *R, void *bb, void *partial, uint32_t *flags,
+                         ResultDev *out, hipStream_t s)
 {
-    if (M < 1 || M > 0x7fffffff) return hipErrorInvalidValue;
+    if (M < 1 || M > 0x7fffffff || !vsweep_plan_ok(plan, M)) return hipErrorInvalidValue;
     switch (d) {
-#define DDKS_VS(DD) case DD: return launch_vsweep_d<DD>(keys, inc, M, V, n_p, n_q, R, bb, partial, flags, out, s);
+#define DDKS_VS(DD) \
+    case DD: return launch_vsweep_d<DD>(keys, inc, M, plan, V, n_p, n_q, R, bb, partial, flags, out, s);
         DDKS_VS(1) DDKS_VS(2) DDKS_VS(3) DDKS_VS(4) DDKS_VS(5) DDKS_VS(6) DDKS_VS(7) DDKS_VS(8)
 #undef DDKS_VS
     default: return hipErrorInvalidValue;

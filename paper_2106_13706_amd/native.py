@@ -40,7 +40,7 @@ EXPORTS = (
     "ddks_default_options", "ddks_create", "ddks_destroy", "ddks_distance",
     "ddks_permutation_batch", "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
     "ddks_serve_stats_get", "ddks_profile_get", "ddks_status_string", "ddks_last_error",
-    "ddks_version", "ddks_vdks", "ddks_rdks",
+    "ddks_version", "ddks_vdks", "ddks_rdks", "ddks_perm_summary_of",
 )
 
 
@@ -133,6 +133,7 @@ def load(path: str = LIB_PATH):
     lib.ddks_create.argtypes = [ctypes.POINTER(_Options), ctypes.POINTER(vp)]
     lib.ddks_destroy.argtypes = [vp]
     lib.ddks_distance.argtypes = [vp, vp, i64, vp, i64, i32, u32, ctypes.POINTER(_Result), vp]
+    lib.ddks_perm_summary_of.argtypes = [vp, i32, u64, ctypes.POINTER(_PermSummary)]
     lib.ddks_permutation_batch.argtypes = [vp, vp, i64, i32, i64, vp, i32, u32, vp,
                                            ctypes.POINTER(_Result), ctypes.POINTER(_PermSummary)]
     lib.ddks_significance.argtypes = [vp, vp, i64, i64, i32, u64, u32,
@@ -337,14 +338,17 @@ class Context:
         self._check(st, "ddks_significance")
         return S.value
 
-    def serve_submit(self, P, Q) -> int:
+    def serve_submit(self, P, Q, flags: int = 0) -> int:
+        """Submits one test (host arrays); flags: DDKS_WITH_SIGNIFICANCE
+        (and DDKS_SIG_POISSON) for the analytic significance in the result.
+        Returns the ticket, or -1 when the queue is full."""
         pp, n_p, d, kp, dev_p = _points(P)
         qp, n_q, dq, kq, dev_q = _points(Q)
         if dev_p or dev_q:
             raise ValueError("serving takes host arrays")
         if d != dq:
             raise ValueError("P and Q must have the same number of columns")
-        req = _Request(pp, n_p, qp, n_q, d, 0)
+        req = _Request(pp, n_p, qp, n_q, d, flags)
         t = ctypes.c_uint64()
         st = self._lib.ddks_serve_submit(self._h, ctypes.byref(req), ctypes.byref(t))
         if st == DDKS_E_AGAIN:
@@ -373,6 +377,18 @@ class Context:
         st = self._lib.ddks_serve_stats_get(self._h, ctypes.byref(s), 1 if reset else 0)
         self._check(st, "ddks_serve_stats_get")
         return {k: getattr(s, k) for k, _ in _ServeStats._fields_}
+
+
+def perm_summary(nums, num_obs: int) -> dict:
+    """Permutation p-value of num_obs among the relabelling numerators nums
+    (ddks_perm_summary_of): {B, n_ge, p_value, fraction}."""
+    a = np.ascontiguousarray(nums, dtype=np.uint64)
+    sm = _PermSummary()
+    st = load().ddks_perm_summary_of(a.ctypes.data if a.size else None, a.size, int(num_obs),
+                                     ctypes.byref(sm))
+    if st != DDKS_OK:
+        raise DDKSError(st, "ddks_perm_summary_of")
+    return {"B": sm.B, "n_ge": sm.n_ge, "p_value": sm.p_value, "fraction": sm.fraction}
 
 
 def version() -> str:

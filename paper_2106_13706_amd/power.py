@@ -7,12 +7,13 @@ Each test is the permutation test the paper uses for every method (Sec. 4.2,
 100 permutations): the p-value is the add-one estimator
 (1 + #{relabellings at least as extreme}) / (1 + B).  For the exact statistic
 all B relabellings run in one batched launch (ddks_permutation_batch); vdKS
-and rdKS re-run the statistic on every relabelled pair.  Reading of the
-bisection target ("a significance within 1e-3 of alpha", which 100
-permutations cannot resolve): the smallest n in [n_lo, n_hi] (or delta in
+and rdKS re-run the statistic on every relabelled pair and take the p-value
+from ddks_perm_summary_of.  Reading of the bisection target (the paper aims
+at a significance within a thousandth of alpha, finer than the 1/101 grid of
+100 permutations can resolve): the smallest n in [n_lo, n_hi] (or delta in
 [lo, hi], to a tolerance) whose test rejects, by bisection on the rejection
-indicator, each point with its own seeded draw.  Everything here is host-side orchestration; the statistics run in the
-library's kernels.
+indicator, each point with its own seeded draw.  Everything here is
+host-side orchestration; the statistics and p-values come from the library.
 """
 from __future__ import annotations
 
@@ -29,6 +30,13 @@ class PowerPoint:
     p_value: float
     D: float
     rejected: bool
+    # what reproduces the point: workloads.power_dataset(dataset, n_points,
+    # d=d, delta=delta, seed=data_seed) and workloads.relabel_rows(2 n_points,
+    # n_points, B, label_seed)
+    n_points: int = 0
+    delta: float | None = None
+    data_seed: int = 0
+    label_seed: int = 0
 
 
 def _unpack_rows(words: np.ndarray, n_total: int) -> np.ndarray:
@@ -48,9 +56,8 @@ def permutation_test(ctx: native.Context, P: np.ndarray, Q: np.ndarray, B: int =
     stat = {"vdks": lambda a, b: ctx.vdks(a, b, voxels_per_dim)[0].num,
             "rdks": lambda a, b: ctx.rdks(a, b)[0].num}[method]
     obs = stat(P, Q)
-    masks = _unpack_rows(labels, n)
-    ge = sum(1 for m in masks if stat(Z[m], Z[~m]) >= obs)
-    return (1.0 + ge) / (1.0 + B), obs / (n_p * (n - n_p))
+    nums = [stat(Z[m], Z[~m]) for m in _unpack_rows(labels, n)]
+    return native.perm_summary(nums, obs)["p_value"], obs / (n_p * (n - n_p))
 
 
 def min_sample_size(ctx: native.Context, dataset: str, method: str = "ddks", alpha: float = 0.05,
@@ -67,7 +74,7 @@ def min_sample_size(ctx: native.Context, dataset: str, method: str = "ddks", alp
             P, Q = workloads.power_dataset(dataset, n, d=d, delta=delta, seed=seed + n)
             p, D = permutation_test(ctx, P, Q, B, method, seed=seed + 7919 * n,
                                     voxels_per_dim=voxels_per_dim)
-            cache[n] = PowerPoint(n, p, D, p <= alpha)
+            cache[n] = PowerPoint(n, p, D, p <= alpha, n, delta, seed + n, seed + 7919 * n)
         return cache[n].rejected
 
     if not rejects(n_hi):
@@ -100,7 +107,7 @@ def min_parameter_gap(ctx: native.Context, dataset: str, method: str = "ddks", n
         P, Q = workloads.power_dataset(dataset, n, d=d, delta=delta, seed=seed + k)
         p, D = permutation_test(ctx, P, Q, B, method, seed=seed + 7919 * (k + 1),
                                 voxels_per_dim=voxels_per_dim)
-        pts.append((delta, PowerPoint(k, p, D, p <= alpha)))
+        pts.append((delta, PowerPoint(k, p, D, p <= alpha, n, delta, seed + k, seed + 7919 * (k + 1))))
         return p <= alpha
 
     if not rejects(hi):

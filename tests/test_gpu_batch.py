@@ -121,3 +121,60 @@ def test_device_pointers(oracle_mod):
                                       oracle_mod.permutation(Z, n_p, words, threads=THREADS))
     finally:
         c.close()
+
+
+def _ctx_env(env, **kw):
+    from paper_2106_13706_amd import native
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return native.Context(**kw)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("shape", ["4:4", "16:4", "4:8", "16:8"])  # waves:relabellings per block
+@pytest.mark.parametrize("d", [3, 5, 7])
+def test_forced_permutation_shapes(oracle_mod, shape, d):
+    """Every relabelling row against the oracle under each admissible shape of
+    the permutation kernel (the tuner picks among these); shapes a dimension
+    does not admit (8 relabellings per block past d = 6) fall back to the
+    default and must still be right."""
+    g = np.random.default_rng(70 + d)
+    n, n_p, B = 1500, 700, 45
+    Z = np.rint(g.standard_normal((n, d)) * 6).astype(np.float32)
+    words = oracle_mod.labels_to_words(_rows(g, n, n_p, B))
+    ctx = _ctx_env({"DDKS_FORCE_PERM": shape})
+    try:
+        print(f"  shape {shape} d={d}", flush=True)
+        for path in sorted(PATHS):
+            nums, obs, _ = ctx.permutation_batch(Z, n_p, words, flags=PATHS[path])
+            np.testing.assert_array_equal(nums, oracle_mod.permutation(Z, n_p, words, threads=THREADS))
+            assert obs.num == oracle_mod.distance(Z[:n_p], Z[n_p:], threads=THREADS).num
+    finally:
+        ctx.close()
+
+
+def test_permutation_shape_tuned_and_cached(oracle_mod, tmp_path):
+    """A sizeable batch tunes the permutation kernel's shape once and records
+    it in the cache file (kind 10 + path: waves, relabellings per block); the
+    tuned call and a replay still match the oracle."""
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(81)
+    n, n_p, B, d = 6000, 3000, 96, 4
+    Z = g.standard_normal((n, d)).astype(np.float32)
+    words = oracle_mod.labels_to_words(_rows(g, n, n_p, B))
+    cache = tmp_path / "tune.txt"
+    exp = oracle_mod.permutation(Z, n_p, words, threads=THREADS)
+    with native.Context(tune_cache=str(cache)) as ctx:
+        for _ in range(2):
+            nums, _, _ = ctx.permutation_batch(Z, n_p, words)
+            np.testing.assert_array_equal(nums, exp)
+    lines = [list(map(int, l.split())) for l in cache.read_text().split("\n") if l.strip()]
+    perm = [l for l in lines if l[0] in (10, 11) and l[1] == d]
+    print(f"  cache: {lines}", flush=True)
+    assert len(perm) == 1 and perm[0][3] in (4, 8, 16) and perm[0][4] in (4, 8)

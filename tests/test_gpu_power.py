@@ -16,6 +16,8 @@ def ctx():
 
 
 def test_batched_p_value_equals_recomputation(ctx):
+    """The batched p-value equals the same test run as separate plain calls
+    (the oracle comparisons below check the values themselves)."""
     from paper_2106_13706_amd import power, workloads
     P, Q = workloads.power_dataset("GVS", 150, seed=3)
     p, D = power.permutation_test(ctx, P, Q, B=40, method="ddks", seed=11)
@@ -54,3 +56,68 @@ def test_parameter_gap_gvm(ctx):
     assert all(p.rejected == (p.p_value <= 0.05) for _, p in pts)
     with pytest.raises(ValueError):
         power.min_parameter_gap(ctx, "DVU")
+
+
+# ---------------------------------------------------------------- against the oracle
+
+THREADS = max(1, len(__import__("os").sched_getaffinity(0)))
+
+
+def _masks(words, n):
+    bits = np.unpackbits(np.ascontiguousarray(words).view(np.uint8), axis=1, bitorder="little")
+    return bits[:, :n].astype(bool)
+
+
+def _oracle_point(oracle_mod, dataset, method, pt, B=100, d=3, V=8):
+    """The oracle's p-value and D of one evaluated point, from the seeds the
+    point records: every relabelling re-run through the oracle (the exact
+    statistic, or vdKS / rdKS), p-value by the oracle's add-one estimator."""
+    from paper_2106_13706_amd import workloads
+    P, Q = workloads.power_dataset(dataset, pt.n_points, d=d, delta=pt.delta, seed=pt.data_seed)
+    Z = np.concatenate([P, Q])
+    n_p, n = len(P), len(Z)
+    labels = workloads.relabel_rows(n, n_p, B, pt.label_seed)
+    if method == "ddks":
+        nums = oracle_mod.permutation(Z, n_p, labels, threads=THREADS)
+        obs = oracle_mod.distance(P, Q, threads=THREADS).num
+    else:
+        stat = (lambda a, b: oracle_mod.vdks(a, b, V).num) if method == "vdks" else \
+               (lambda a, b: oracle_mod.rdks(a, b).num)
+        nums = [stat(Z[m], Z[~m]) for m in _masks(labels, n)]
+        obs = stat(P, Q)
+    return oracle_mod.pvalue(nums, obs)[0], obs / (n_p * (n - n_p))
+
+
+@pytest.mark.parametrize("method", ["ddks", "vdks", "rdks"])
+@pytest.mark.parametrize("dataset", ["GVM", "DVU", "MM"])
+def test_min_sample_size_against_oracle(ctx, oracle_mod, dataset, method):
+    """Every point a seeded bisection evaluates has the oracle's p-value and
+    D exactly, and the endpoint is where the oracle's rejections place it:
+    it rejects and one point fewer, also evaluated, does not."""
+    from paper_2106_13706_amd import power
+    n, pts = power.min_sample_size(ctx, dataset, method=method, n_hi=128)
+    seen = {}
+    for pt in pts:
+        p, D = _oracle_point(oracle_mod, dataset, method, pt)
+        print(f"  {dataset} {method} n={pt.n}: p={pt.p_value} oracle={p}", flush=True)
+        assert (pt.p_value, pt.D) == (p, D)
+        seen[pt.n] = p <= 0.05
+    if n is None:
+        assert not seen[128]
+    else:
+        assert seen[n] and (n == 4 or seen.get(n - 1) is False)
+
+
+@pytest.mark.parametrize("method", ["ddks", "rdks"])
+def test_parameter_gap_against_oracle(ctx, oracle_mod, method):
+    from paper_2106_13706_amd import power
+    gap, pts = power.min_parameter_gap(ctx, "GVM", method=method, n=50)
+    rej = []
+    for delta, pt in pts:
+        p, D = _oracle_point(oracle_mod, "GVM", method, pt)
+        assert (pt.p_value, pt.D, pt.delta) == (p, D, delta)
+        rej.append((delta, p <= 0.05))
+    print(f"  GVM {method} gap {gap}: {rej}", flush=True)
+    assert gap is not None and (gap, True) in rej
+    below = [x for x, r in rej if not r and x < gap]
+    assert gap - max(below, default=0.0) <= 1.0 / 64

@@ -211,3 +211,97 @@ def test_destroy_with_outstanding_requests():
         ctx.serve_submit(g.standard_normal((3000, 4)).astype(np.float32),
                          g.standard_normal((2000, 4)).astype(np.float32))
     ctx.close()  # drains the serving loop and frees everything
+
+
+def test_significance_in_serving(oracle_mod):
+    """Served tests that ask for the analytic significance (Sec. 3), binomial
+    and Poisson, mixed with tests that do not: num and argmax equal the
+    oracle's; S equals the plain call's S exactly (same counts, same kernels,
+    fixed-order reduction) and the oracle's within the relative bound of the
+    significance tests; S = -1 where it was not asked for."""
+    import math
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(31)
+    cases = []
+    for k in range(24):
+        d = int(g.integers(2, 7))
+        n_p, n_q = int(g.integers(20, 2500)), int(g.integers(20, 2500))
+        if k == 5:
+            n_p, n_q = 12000, 9000  # a size served on the rank-16 path
+        P = g.standard_normal((n_p, d)).astype(np.float32)
+        Q = (g.standard_normal((n_q, d)) + g.uniform(0, 0.3)).astype(np.float32)
+        flags = [0, native.DDKS_WITH_SIGNIFICANCE,
+                 native.DDKS_WITH_SIGNIFICANCE | native.DDKS_SIG_POISSON][k % 3]
+        cases.append((P, Q, flags))
+    with native.Context() as ctx:
+        tickets = [ctx.serve_submit(P, Q, flags) for P, Q, flags in cases]
+        got = [ctx.serve_poll(t) for t in tickets]
+        plain = [ctx.distance(P, Q, flags=flags) for P, Q, flags in cases]
+        with pytest.raises(native.DDKSError) as e:
+            ctx.serve_submit(cases[0][0], cases[0][1], native.DDKS_FORCE_F32)
+        assert e.value.status == native.DDKS_E_INVALID_ARG
+    U = 2.0 ** -53
+    for (P, Q, flags), r, p in zip(cases, got, plain):
+        n_p, n_q, d = len(P), len(Q), P.shape[1]
+        o = oracle_mod.distance(P, Q, counts=True, threads=THREADS)
+        assert _key(r) == _key(p) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+        if not flags:
+            assert r.S == -1.0
+            continue
+        model = "poisson" if flags & native.DDKS_SIG_POISSON else "binomial"
+        So = oracle_mod.significance(o.counts, n_p, n_q, d, o.num, model)
+        print(f"  {model} d={d} n=({n_p},{n_q}): served S={r.S!r} plain={p.S!r} oracle={So!r}",
+              flush=True)
+        assert r.S == p.S
+        rtol = 128 * U * math.lgamma(max(n_p, n_q) + 1.0) + 1e-12
+        assert abs(r.S - So) <= rtol * So + o.counts.size * 1e-304
+
+
+@pytest.mark.parametrize("waves", ["4", "16"])
+def test_forced_packed_waves(oracle_mod, waves):
+    """The packed sweep under each admissible block shape (the tuner picks
+    among 4, 8 and 16 waves): a mix of dimensions and sizes against the
+    oracle."""
+    from paper_2106_13706_amd import native
+    reqs = _mix(50 + int(waves), 80)
+    old = os.environ.get("DDKS_FORCE_PACKED_WAVES")
+    os.environ["DDKS_FORCE_PACKED_WAVES"] = waves
+    try:
+        ctx = native.Context()
+    finally:
+        if old is None:
+            os.environ.pop("DDKS_FORCE_PACKED_WAVES")
+        else:
+            os.environ["DDKS_FORCE_PACKED_WAVES"] = old
+    try:
+        tickets = [ctx.serve_submit(P, Q) for P, Q in reqs]
+        got = [ctx.serve_poll(t) for t in tickets]
+    finally:
+        ctx.close()
+    for (P, Q), r in zip(reqs, got):
+        o = oracle_mod.distance(P, Q, threads=THREADS)
+        assert _key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+
+
+def test_packed_waves_tuned_and_cached(oracle_mod, tmp_path):
+    """A burst of small tests of one dimension fills packed launches large
+    enough to tune their block shape, which lands in the cache file (kind
+    20 + path); results match the oracle."""
+    from paper_2106_13706_amd import native
+    g = np.random.default_rng(91)
+    reqs = []
+    for _ in range(300):
+        n_p, n_q = int(g.integers(1500, 4000)), int(g.integers(1500, 4000))
+        reqs.append((g.standard_normal((n_p, 3)).astype(np.float32),
+                     (g.standard_normal((n_q, 3)) + 0.1).astype(np.float32)))
+    cache = tmp_path / "tune.txt"
+    with native.Context(tune_cache=str(cache)) as ctx:
+        tickets = [ctx.serve_submit(P, Q) for P, Q in reqs]
+        got = [ctx.serve_poll(t) for t in tickets]
+    for (P, Q), r in zip(reqs[::10], got[::10]):
+        o = oracle_mod.distance(P, Q, threads=THREADS)
+        assert _key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
+    lines = [list(map(int, l.split())) for l in cache.read_text().split("\n") if l.strip()]
+    print(f"  cache: {lines}", flush=True)
+    packed = [l for l in lines if l[0] in (20, 21) and l[1] == 3]
+    assert packed and all(l[3] in (4, 8, 16) for l in packed)

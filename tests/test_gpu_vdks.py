@@ -91,3 +91,66 @@ def test_device_pointers_and_errors(ctx, oracle_mod):
         ctx.vdks(bad, Q, 5)
     assert e.value.status == native.DDKS_E_NONFINITE
     assert ctx.vdks(P, Q, 5)[0].num == o.num  # the context keeps working
+
+
+def _ctx_env(env, **kw):
+    import os
+    from paper_2106_13706_amd import native
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return native.Context(**kw)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def _heavy_and_light(seed, d, n_heavy):
+    """A sample whose points mostly share one voxel (so the chunk holding it
+    has more than 65535 points: 64-bit bins) beside spread-out points (other
+    chunks stay under 65536: 32-bit bins)."""
+    g = np.random.default_rng(seed)
+    P = np.concatenate([np.full((n_heavy, d), 0.25, np.float32),
+                        g.uniform(-1, 1, size=(3000, d)).astype(np.float32)])
+    Q = np.concatenate([np.full((n_heavy // 2, d), -0.5, np.float32),
+                        g.uniform(-1, 1, size=(2500, d)).astype(np.float32)])
+    return P, Q
+
+
+@pytest.mark.parametrize("shape", ["4:1", "16:3", "8:6", "4:16"])  # waves:chunks
+def test_forced_vsweep_shapes(oracle_mod, shape):
+    """Every admissible shape of the weighted sweep gives the oracle's result,
+    with 32-bit bins (chunks under 65536 points of each sample), with 64-bit
+    bins, and with both kinds of chunk in one launch."""
+    from paper_2106_13706_amd import workloads
+    ctx = _ctx_env({"DDKS_FORCE_VSWEEP": shape})
+    try:
+        P, Q = workloads.gaussian_scale()
+        check(ctx, oracle_mod, P, Q, 8)
+        for d, V in [(3, 7), (6, 4)]:
+            check(ctx, oracle_mod, *_heavy_and_light(d, d, 70000), V)
+        g = np.random.default_rng(44)
+        P = g.standard_normal((90000, 2)).astype(np.float32)
+        Q = (g.standard_normal((80000, 2)) + 0.1).astype(np.float32)
+        check(ctx, oracle_mod, P, Q, 3)  # 9 voxels: every chunk far over 65535 points
+    finally:
+        ctx.close()
+
+
+def test_vsweep_shape_tuned_and_cached(oracle_mod, tmp_path):
+    """Enough filled voxels to tune the weighted sweep's shape: one kind-30
+    entry lands in the cache file and the result is the oracle's."""
+    from paper_2106_13706_amd import native, workloads
+    P, Q = workloads.gaussian_scale()
+    cache = tmp_path / "tune.txt"
+    with native.Context(tune_cache=str(cache)) as ctx:
+        r = check(ctx, oracle_mod, P, Q, 16)
+        r2 = check(ctx, oracle_mod, P, Q, 16)
+        assert r2.num == r.num
+    lines = [list(map(int, l.split())) for l in cache.read_text().split("\n") if l.strip()]
+    print(f"  cache: {lines}", flush=True)
+    vs = [l for l in lines if l[0] == 30 and l[1] == 4]
+    assert len(vs) == 1 and vs[0][3] in (4, 8, 16) and 1 <= vs[0][4] <= 16
