@@ -119,6 +119,32 @@ int ddks_destroy(ddks_ctx *ctx);
 int ddks_distance(ddks_ctx *ctx, const float *P, int64_t n_p, const float *Q, int64_t n_q,
                   int32_t d, uint32_t flags, ddks_result *out, uint32_t *counts);
 
+/*
+ * ddks_distance for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc, processes whose device
+ * memory map must not change once set up): the same result, and the same counts, as ddks_distance, computed
+ * in a static 64 MiB device scratch array instead of buffers the call would
+ * allocate.  It calls no hipMalloc, hipFree or allocating library routine.
+ * P, Q (n_p x d, n_q x d fp32) and counts (nullable, uint32
+ * [n_p+n_q][2^d][2]) are device memory on the context's device
+ * (DDKS_DEVICE_PTRS is implied).  flags: DDKS_FORCE_F32 / DDKS_FORCE_RANK16
+ * as for ddks_distance (rank codes only up to 65536 points, fp32 compares
+ * beyond); DDKS_WITH_SIGNIFICANCE is not supported.  Uses the context's launch
+ * shape with as many point chunks as the scratch holds; out->S = -1.
+ * Every call on one GPU shares that GPU's scratch (held until the process
+ * ends): calls on one context are serialised, but calls from different
+ * contexts on the same GPU that overlap race.  Synchronous, like
+ * ddks_distance.
+ * Limits: those of ddks_distance, and the call's buffers (about N*d*4 bytes
+ * of points, or the rank tables up to 65536 points, plus the partial counts)
+ * within the 64 MiB.
+ * Errors: DDKS_E_INVALID_ARG, DDKS_E_NONFINITE, DDKS_E_NOT_SUPPORTED,
+ * DDKS_E_NOMEM (the input needs more scratch than the array holds; nothing is
+ * launched), DDKS_E_DEVICE (also when the scratch is unavailable).
+ */
+int ddks_distance_noalloc(ddks_ctx *ctx, const float *P, int64_t n_p, const float *Q, int64_t n_q,
+                          int32_t d, uint32_t flags, ddks_result *out, uint32_t *counts);
+
 typedef struct ddks_perm_summary {
     int64_t B;          /* relabellings evaluated */
     uint64_t n_ge;      /* relabellings whose numerator is >= the observed one */

@@ -394,6 +394,67 @@ static int finish_distance(ddks_ctx *c, int64_t n_p, int64_t n_q, int d, ddks_re
     return DDKS_OK;
 }
 
+// ------------------------------------------------ scratch of the no-allocation call
+// ddks_distance_noalloc works in this array instead of buffers it would
+// allocate: one copy per GPU the library runs on, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: the per-device address comes from hipGetSymbolAddress at context
+// creation, and only that address is handed to kernels.  Calls on one GPU
+// share its copy, so calls that overlap on one GPU (from different contexts)
+// race; the kernels write every part of it they later read, so nothing needs
+// to start at zero.
+static constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// With c->device current: looks up this device's copy of `scratch` once.
+static void noalloc_setup(ddks_ctx *c)
+{
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[c->device]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();  // the no-allocation call reports it; other calls are unaffected
+        return;
+    }
+    g_scratch_ptr[c->device] = p;
+}
+
+static void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets of one call's buffers in the scratch.
+struct NoallocLayout {
+    size_t pts = 0, rank = 0, bb = 0, partial = 0, total = 0;
+};
+
+static NoallocLayout noalloc_layout(const SweepPlan &p, int64_t N, int d)
+{
+    NoallocLayout L;
+    size_t off = 0;
+    L.pts = off;
+    off += al256((size_t)N * point_words(p.path, d) * sizeof(uint32_t));
+    L.rank = off;
+    if (p.path == PATH_R16) off += al256(rank16_scratch_bytes(N, d));
+    L.bb = off;
+    off += al256((size_t)p.groups * sizeof(BlockBest));
+    L.partial = off;
+    if (p.chunks > 1) off += al256(partial_bytes(p));
+    L.total = off + 256;  // the sweep's wide point loads may read up to 128 bytes past the points
+    return L;
+}
+
 extern "C" {
 
 const char *ddks_version(void) { return "libddks 0.1 (gfx950)"; }
@@ -494,6 +555,7 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     for (int i = 0; i < 4 && !st && c->profile; ++i)
         st = hip_check(c, hipEventCreate(&c->ev[i]), "hipEventCreate");
     if (!st) c->tuner = tuner_create(c->tune_cache.empty() ? nullptr : c->tune_cache.c_str());
+    if (!st) noalloc_setup(c);
     if (st) {
         ddks_destroy(c);
         return st;
@@ -696,6 +758,63 @@ int ddks_distance(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int6
     }
     return finish_distance(c, n_p, n_q, d, out, counts && !dev ? counts : nullptr, counts_dev,
                            (size_t)N * bins * 2 * sizeof(uint32_t), with_S);
+}
+
+int ddks_distance_noalloc(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int64_t n_q,
+                          int32_t d, uint32_t flags, ddks_result *out, uint32_t *counts)
+{
+    if (!c) return DDKS_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->poisoned) return fail(c, DDKS_E_DEVICE, "context poisoned by an earlier device error");
+    if (!P || !Q || !out) return fail(c, DDKS_E_INVALID_ARG, "null pointer argument");
+    if (d < 1 || d > 8) return fail(c, DDKS_E_INVALID_ARG, "d must be in [1, 8]");
+    if (n_p < 1 || n_q < 1) return fail(c, DDKS_E_INVALID_ARG, "each sample needs at least one point");
+    if (flags & DDKS_WITH_SIGNIFICANCE)
+        return fail(c, DDKS_E_NOT_SUPPORTED, "the no-allocation call does not compute the significance");
+    const int64_t N = n_p + n_q;
+    if (N > 0x7fffffffLL) return fail(c, DDKS_E_INVALID_ARG, "n_p + n_q exceeds 2^31 - 1");
+    if (hipSetDevice(c->device) != hipSuccess) return hip_check(c, hipGetLastError(), "hipSetDevice");
+    char *base = (char *)noalloc_scratch(c->device);
+    if (!base) return fail(c, DDKS_E_DEVICE, "the no-allocation scratch is not available on this device");
+    // Rank codes up to 65536 points, read straight from P and Q; beyond that
+    // fp32 compares (shifted codes would need the larger tables of the
+    // position coding).
+    int path = choose_path(c, d, N, flags);
+    if (path == PATH_R16 && N > 65536) path = PATH_F32;
+    // The context's launch shape (tuned if known; no tuning launches here),
+    // with as many of its point chunks as the scratch holds.
+    const SweepPlan want = plan_for(c, path, d, N, n_p);
+    SweepPlan plan;
+    bool fits = false;
+    for (int64_t k = want.chunks; k >= 1 && !fits; --k) {
+        plan = want;
+        plan.chunks = k;
+        fits = plan_complete(plan, N, n_p) && noalloc_layout(plan, N, d).total <= NOALLOC_SCRATCH_BYTES;
+    }
+    if (!fits) {
+        plan = want;
+        plan.chunks = 1;
+        (void)plan_complete(plan, N, n_p);
+        char msg[160];
+        snprintf(msg, sizeof msg, "input needs %zu bytes of scratch; the no-allocation call has %zu",
+                 noalloc_layout(plan, N, d).total, NOALLOC_SCRATCH_BYTES);
+        return fail(c, DDKS_E_NOMEM, msg);
+    }
+    const NoallocLayout L = noalloc_layout(plan, N, d);
+    hipStream_t s = c->stream;
+    __atomic_store_n(c->done_host, 0u, __ATOMIC_RELEASE);  // set again by this call's reduction
+    void *pts = base + L.pts;
+    int st;
+    if (path == PATH_R16)
+        st = hip_check(c, launch_rank16_pq(P, n_p, Q, n_q, d, (uint32_t *)pts, base + L.rank, c->flags_dev, s),
+                       "rank launch");
+    else
+        st = hip_check(c, launch_ingest_f32(P, n_p, Q, n_q, d, (float *)pts, c->flags_dev, s), "ingest launch");
+    if (st) return st;
+    st = sweep_into(c, plan, pts, N, n_p, n_q, counts, c->result_host, s, 0, (BlockBest *)(base + L.bb),
+                    plan.chunks > 1 ? base + L.partial : nullptr, nullptr, false);
+    if (st) return st;
+    return finish_distance(c, n_p, n_q, d, out, nullptr, nullptr, 0, false);
 }
 
 int ddks_profile_get(ddks_ctx *c, ddks_profile *out, int32_t reset)

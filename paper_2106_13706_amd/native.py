@@ -40,7 +40,7 @@ EXPORTS = (
     "ddks_default_options", "ddks_create", "ddks_destroy", "ddks_distance",
     "ddks_permutation_batch", "ddks_significance", "ddks_serve_submit", "ddks_serve_poll",
     "ddks_serve_stats_get", "ddks_profile_get", "ddks_status_string", "ddks_last_error",
-    "ddks_version", "ddks_vdks", "ddks_rdks", "ddks_perm_summary_of",
+    "ddks_version", "ddks_vdks", "ddks_rdks", "ddks_distance_noalloc", "ddks_perm_summary_of",
 )
 
 
@@ -133,6 +133,7 @@ def load(path: str = LIB_PATH):
     lib.ddks_create.argtypes = [ctypes.POINTER(_Options), ctypes.POINTER(vp)]
     lib.ddks_destroy.argtypes = [vp]
     lib.ddks_distance.argtypes = [vp, vp, i64, vp, i64, i32, u32, ctypes.POINTER(_Result), vp]
+    lib.ddks_distance_noalloc.argtypes = [vp, vp, i64, vp, i64, i32, u32, ctypes.POINTER(_Result), vp]
     lib.ddks_perm_summary_of.argtypes = [vp, i32, u64, ctypes.POINTER(_PermSummary)]
     lib.ddks_permutation_batch.argtypes = [vp, vp, i64, i32, i64, vp, i32, u32, vp,
                                            ctypes.POINTER(_Result), ctypes.POINTER(_PermSummary)]
@@ -258,6 +259,29 @@ class Context:
         self._check(st, "ddks_distance")
         res = Result._from(r)
         return (res, cbuf) if counts else res
+
+    def distance_noalloc(self, P, Q, *, counts=None, flags: int = 0):
+        """ddks_distance_noalloc: the exact statistic of device tensors P and Q
+        computed in the library's static scratch (no device allocation).
+        counts: None or a caller-allocated device tensor of N * 2^d * 2 32-bit
+        words that receives the membership counts."""
+        pp, n_p, d, kp, dev_p = _points(P)
+        qp, n_q, dq, kq, dev_q = _points(Q)
+        if d != dq:
+            raise ValueError("P and Q must have the same number of columns")
+        if not (dev_p and dev_q):
+            raise ValueError("the no-allocation call takes device tensors only")
+        cptr = None
+        if counts is not None:
+            if not (_is_torch(counts) and counts.is_cuda and counts.is_contiguous()
+                    and counts.numel() * counts.element_size() == (n_p + n_q) * (2 << d) * 4):
+                raise ValueError("counts must be a contiguous device tensor of N * 2^d * 2 words")
+            cptr = counts.data_ptr()
+        r = _Result()
+        st = self._lib.ddks_distance_noalloc(self._h, pp, n_p, qp, n_q, d, flags | DDKS_DEVICE_PTRS,
+                                             ctypes.byref(r), cptr)
+        self._check(st, "ddks_distance_noalloc")
+        return Result._from(r)
 
     def permutation_batch(self, Z, n_p: int, labels, *, flags: int = 0):
         """Numerators for every relabelling row (labels: [B, ceil(n/32)] uint32

@@ -58,6 +58,7 @@ def test_failed_call_poisons_every_entry_point():
         calls = {
             "distance": lambda: ctx.distance(P, Q),
             "distance_device": lambda: ctx.distance(Pt, Qt),
+            "distance_noalloc": lambda: ctx.distance_noalloc(Pt, Qt),
             "permutation_batch": lambda: ctx.permutation_batch(Z, 300, np.zeros((0, 16), np.uint32)),
             "significance": lambda: ctx.significance(counts, 300, 200, 3, 1),
             "vdks": lambda: ctx.vdks(P, Q, 4),
