@@ -84,3 +84,28 @@ def test_rdks_invariants(oracle_mod):
     Qc = np.concatenate([Q, np.full((100, 1), 3, np.float32)], axis=1)
     rc = oracle_mod.rdks(Pc, Qc)
     assert list(rc.per_corner[:5]) == list(r.per_corner)
+
+
+@pytest.mark.parametrize("d,n_p,n_q,k", [(2, 70, 90, 3), (3, 120, 100, 4), (6, 60, 75, 2), (12, 40, 55, 3)])
+def test_rdks_exact_on_a_dyadic_lattice(oracle_mod, d, n_p, n_q, k):
+    """An independent pin of the d > 1 distances: coordinates on {0, .., 2^k}
+    with both ends present in every dimension normalise to multiples of
+    2^-k, so every squared distance from a corner is a multiple of 2^-2k below
+    d + 1 and exact in fp32, whatever the order of the operations.  The
+    distances are then computed in exact integer arithmetic (units of 2^-2k),
+    and the per-corner statistic is scipy's two-sample KS statistic of the
+    two distance lists."""
+    g = np.random.default_rng(1000 + d)
+    top = 2 ** k
+    P = g.integers(0, top + 1, size=(n_p, d))
+    Q = g.integers(0, top + 1, size=(n_q, d))
+    P[0], Q[0] = 0, top  # both ends of every dimension present
+    r = oracle_mod.rdks(P.astype(np.float32), Q.astype(np.float32))
+    Z = np.concatenate([P, Q]).astype(np.int64)
+    for c in range(d + 1):
+        corner = np.zeros(d, np.int64)
+        if c > 0:
+            corner[c - 1] = top
+        dist = ((Z - corner) ** 2).sum(axis=1)  # exact, in units of 2^-2k
+        ks = ks_2samp(dist[:n_p], dist[n_p:]).statistic
+        assert abs(r.per_corner[c] / (n_p * n_q) - ks) < 1e-12, c
