@@ -227,23 +227,29 @@ hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V
                             uint64_t *keys, uint64_t *inc, hipStream_t s);
 
 // Launch shape of the weighted sweep: waves per block (4, 8 or 16; they
-// share the block's 64 origins) and point chunks (1..16; with more than one
-// the chunks' counts go through partial sums).
+// share the block's origins), origin groups of 64 per block (1 or 2), and
+// point chunks (1..VSWEEP_MAX_CHUNKS; with more than one the chunks' counts go
+// through partial sums).
+constexpr int VSWEEP_MAX_CHUNKS = 16;
 struct VSweepPlan {
     int waves = 8;
     int chunks = 1;
+    int per_block = 1;  // origin groups per block (1 or 2): each voxel load serves all of them
 };
 VSweepPlan vsweep_default_plan(int64_t M);
-bool vsweep_plan_ok(const VSweepPlan &p, int64_t M);
+bool vsweep_plan_ok(const VSweepPlan &p, int64_t M, int d);
+// Words per filled voxel of the weighted sweep's encoding.
+int vox_words(int d);
 
-// The weighted sweep over the M filled voxels (R: M x point_words(R16, d)
-// scratch, bb: vdks_best_bytes(M), partial: vsweep_partial_bytes(M, d, plan)
-// of scratch, null when that is 0); *out = (num, lowest maximising voxel key,
-// its lowest code, *flags), *flags cleared.
+// The weighted sweep over the M filled voxels (RV: M x vox_words(d) words of
+// scratch for the encoding, fit: VSWEEP_MAX_CHUNKS words of scratch, bb:
+// vdks_best_bytes(M), partial: vsweep_partial_bytes(M, d, plan) of scratch,
+// null when that is 0); *out = (num, lowest maximising voxel key, its lowest
+// code, *flags), *flags cleared.
 size_t vsweep_partial_bytes(int64_t M, int d, const VSweepPlan &plan);
 hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
-                         int64_t n_q, const VSweepPlan &plan, uint32_t *R, void *bb, void *partial, uint32_t *flags,
-                         ResultDev *out, hipStream_t s);
+                         int64_t n_q, const VSweepPlan &plan, uint32_t *RV, uint32_t *fit, void *bb, void *partial,
+                         uint32_t *flags, ResultDev *out, hipStream_t s);
 
 // ---------------------------------------------------------------- significance
 

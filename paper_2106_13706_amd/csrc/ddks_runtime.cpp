@@ -520,10 +520,11 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     }
     if (const char *e = getenv("DDKS_FORCE_PACKED_WAVES")) c->force_packed_waves = atoi(e);
     if (const char *e = getenv("DDKS_FORCE_VSWEEP")) {
-        int w = 0, ch = 0;
-        if (sscanf(e, "%d:%d", &w, &ch) == 2) {
+        int w = 0, ch = 0, g = 1;
+        if (sscanf(e, "%d:%d:%d", &w, &ch, &g) >= 2) {
             c->force_vsweep.waves = w;
             c->force_vsweep.chunks = ch;
+            c->force_vsweep.per_block = g;
         }
     }
     parse_fault_injection(c);

@@ -73,7 +73,7 @@ static void tuner_store(Tuner *t, int path, int d, int64_t N, int waves, int64_t
 // their own kinds in the first field: the permutation kernel as PERM_KIND +
 // path with (waves, relabellings per block), the packed sweep as
 // PACKED_KIND + path with (waves, 0), vdKS's weighted sweep as VSWEEP_KIND
-// with (waves, chunks).
+// with (waves, chunks + 256 (origin groups per block - 1)).
 static constexpr int PERM_KIND = 10, PACKED_KIND = 20;
 
 bool tuner_lookup_perm(Tuner *t, int path, int d, int64_t n, int *waves, int *pb)
@@ -116,13 +116,15 @@ bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, VSweepPlan *plan)
     auto it = t->best.find({VSWEEP_KIND, d, bucket(M)});
     if (it == t->best.end()) return false;
     plan->waves = it->second.first;
-    plan->chunks = (int)it->second.second;
+    plan->chunks = (int)(it->second.second & 0xff);
+    plan->per_block = (int)(it->second.second >> 8) + 1;
     return true;
 }
 
+// stored as (waves, chunks + 256 (origin groups per block - 1))
 void tuner_store_vsweep(Tuner *t, int d, int64_t M, const VSweepPlan &plan)
 {
-    if (t) tuner_store(t, VSWEEP_KIND, d, M, plan.waves, plan.chunks);
+    if (t) tuner_store(t, VSWEEP_KIND, d, M, plan.waves, plan.chunks + 256 * (plan.per_block - 1));
 }
 
 bool tune_pending(ddks_ctx *c, int path, int d, int64_t N)

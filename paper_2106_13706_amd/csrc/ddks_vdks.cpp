@@ -14,24 +14,26 @@ namespace {
 // launch-bound: the default shape is as good).
 constexpr int64_t VSWEEP_TUNE_MIN = 4096;
 
-// Times every admissible (waves, chunks) shape of the weighted sweep (the
+// Times every admissible (origin groups per block, waves, chunks) shape of the weighted sweep (the
 // encoding, sweep, chunk scoring and reduction: everything that depends on
 // the shape) twice and records the fastest for (d, log2 M) in the tuner.
 int tune_vsweep(ddks_ctx *c, const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
-                int64_t n_q, uint32_t *scratch_flags, hipStream_t s, VSweepPlan *best)
+                int64_t n_q, uint32_t *fit, uint32_t *scratch_flags, hipStream_t s, VSweepPlan *best)
 {
     const int64_t groups = (M + 63) / 64;
     std::vector<VSweepPlan> cand;
-    for (int w : {4, 8, 16})
-        for (int ch : {1, 2, 3, 4, 6, 8, 12, 16}) {
-            VSweepPlan p;
-            p.waves = w;
-            p.chunks = ch;
-            if (!vsweep_plan_ok(p, M) || M / ch < (int64_t)w * 64) continue;  // >= 64 voxels per wave
-            if (groups * ch * w > 65536 * 4) continue;
-            if (vsweep_partial_bytes(M, d, p) > (256ull << 20)) continue;
-            cand.push_back(p);
-        }
+    for (int g : {1, 2})
+        for (int w : {4, 8, 16})
+            for (int ch : {1, 2, 3, 4, 5, 6, 8, 10, 12, 16}) {
+                VSweepPlan p;
+                p.waves = w;
+                p.chunks = ch;
+                p.per_block = g;
+                if (!vsweep_plan_ok(p, M, d) || M / ch < (int64_t)w * 64) continue;  // >= 64 voxels per wave
+                if (groups * ch * w > 65536 * 4) continue;
+                if (vsweep_partial_bytes(M, d, p) > (256ull << 20)) continue;
+                cand.push_back(p);
+            }
     if (cand.size() < 2) return DDKS_OK;
     size_t pmax = 0;
     for (const VSweepPlan &p : cand) pmax = std::max(pmax, vsweep_partial_bytes(M, d, p));
@@ -45,7 +47,7 @@ int tune_vsweep(ddks_ctx *c, const uint64_t *keys, const uint64_t *inc, int64_t 
         for (int rep = 0; rep < 2 && !st; ++rep) {
             st = hip_check(c, hipEventRecord(e0, s), "hipEventRecord");
             if (!st)
-                st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, p, (uint32_t *)c->zr.ptr,
+                st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, p, (uint32_t *)c->zr.ptr, fit,
                                                 c->block_best.ptr, c->partial.ptr, scratch_flags, c->result_dev, s),
                                "voxel sweep launch");
             if (!st) st = hip_check(c, hipEventRecord(e1, s), "hipEventRecord");
@@ -94,10 +96,10 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     const size_t pts = (size_t)N * d * sizeof(float);
     const size_t table = (size_t)slots * (sizeof(uint64_t) + 2 * sizeof(uint32_t));
     const size_t list = (size_t)N * 2 * sizeof(uint64_t);  // keys, increments
-    const size_t r16 = (size_t)N * point_words(PATH_R16, d) * sizeof(uint32_t);
+    const size_t r16 = (size_t)N * vox_words(d) * sizeof(uint32_t);
     const size_t best = vdks_best_bytes(N);
     int st = ensure(c, c->z, pts, "points");
-    const size_t extents = 128 + (size_t)VOX_EXTENT_ROWS * 2 * d * sizeof(uint32_t);
+    const size_t extents = 128 + (size_t)VOX_EXTENT_ROWS * 2 * d * sizeof(uint32_t) + VSWEEP_MAX_CHUNKS * 4;
     if (!st) st = ensure(c, c->vox, table + list + extents, "voxel table");  // + counter and extents
     if (!st) st = ensure(c, c->zr, r16, "voxel encoding");
     if (!st) st = ensure(c, c->block_best, best, "block results");
@@ -110,6 +112,7 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     uint32_t *counter = (uint32_t *)(inc + N);
     uint32_t *mm = counter + 4;     // 2 d words
     uint32_t *part = counter + 32;  // VOX_EXTENT_ROWS x 2 d words
+    uint32_t *fit = part + (size_t)VOX_EXTENT_ROWS * 2 * d;  // VSWEEP_MAX_CHUNKS words
 
     const float *srcP = P, *srcQ = Q;
     if (!dev) {
@@ -133,21 +136,21 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     if (c->force_vsweep.waves) {
         VSweepPlan f = c->force_vsweep;
         f.chunks = (int)std::min<int64_t>(f.chunks, M);
-        if (vsweep_plan_ok(f, M)) plan = f;
-    } else if (!tuner_lookup_vsweep(c->tuner, d, M, &plan) || !vsweep_plan_ok(plan, M)) {
+        if (vsweep_plan_ok(f, M, d)) plan = f;
+    } else if (!tuner_lookup_vsweep(c->tuner, d, M, &plan) || !vsweep_plan_ok(plan, M, d)) {
         plan = vsweep_default_plan(M);
         if (c->tuner && !(c->opt_flags & DDKS_NO_AUTOTUNE) && M >= VSWEEP_TUNE_MIN) {
             // time the admissible shapes on this input once per (d, log2 M);
             // the timed runs report into a scratch flags word so that the
             // call's own flags survive them
-            st = tune_vsweep(c, keys, inc, M, d, V, n_p, n_q, counter + 2, s, &plan);
+            st = tune_vsweep(c, keys, inc, M, d, V, n_p, n_q, fit, counter + 2, s, &plan);
             if (st) return st;
         }
     }
     const size_t pb = vsweep_partial_bytes(M, d, plan);
     if (pb && (st = ensure(c, c->partial, pb, "voxel partial counts"))) return st;
-    st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, plan, (uint32_t *)c->zr.ptr, c->block_best.ptr,
-                                    pb ? c->partial.ptr : nullptr, c->flags_dev, c->result_host, s),
+    st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, plan, (uint32_t *)c->zr.ptr, fit,
+                                    c->block_best.ptr, pb ? c->partial.ptr : nullptr, c->flags_dev, c->result_host, s),
                    "voxel sweep launch");
     if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
     if (st) return st;

@@ -26,7 +26,6 @@
 #include <stdint.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "ddks_device.h"
 
@@ -219,17 +218,30 @@ __global__ __launch_bounds__(COMPACT_THREADS) void k_vox_compact(const uint64_t 
 }
 
 // Voxel coordinates as biased int16 ranks in the rank-16 point layout.
+// The weighted sweep's encoding of a filled voxel: the sign words of the rank
+// path (two dimensions each, biased int16), STRIDE words per voxel, and
+// beside them one word of counts per voxel, c_P | c_Q << 16 (meaningful when
+// both fit 16 bits), which the sweep reads into vector registers.
 template <int D>
-__global__ void k_vox_encode(const uint64_t *__restrict__ keys, int64_t M, int V,
-                             uint32_t *__restrict__ R)
+struct VLayout {
+    static constexpr int STRIDE = Geo<D>::NREG;
+    // voxels per unrolled block: a multiple of four, about 32 scalar registers
+    static constexpr int U = ((32 / STRIDE) / 4) * 4 < 4 ? 4 : ((32 / STRIDE) / 4) * 4;
+};
+
+int vox_words(int d) { return (d + 1) / 2 + 1; }
+
+template <int D>
+__global__ void k_vox_encode(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ inc, int64_t M,
+                             int V, uint32_t *__restrict__ R, uint32_t *__restrict__ W32)
 {
-    constexpr int PW = Layout<PATH_R16, D>::PW;
+    constexpr int S = VLayout<D>::STRIDE;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
          i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t k = keys[i];
-        uint32_t w[PW];
+        uint32_t w[S];
 #pragma unroll
-        for (int p = 0; p < PW; ++p) w[p] = 0u;
+        for (int p = 0; p < S; ++p) w[p] = 0u;
 #pragma unroll
         for (int m = 0; m < D; ++m) {
             const uint32_t v = (uint32_t)(k % (uint64_t)V);
@@ -238,7 +250,45 @@ __global__ void k_vox_encode(const uint64_t *__restrict__ keys, int64_t M, int V
             w[m >> 1] |= r << (16 * (m & 1));
         }
 #pragma unroll
-        for (int p = 0; p < PW; ++p) R[i * PW + p] = w[p];
+        for (int p = 0; p < S; ++p) R[i * S + p] = w[p];
+        const uint64_t c = inc[i];
+        W32[i] = ((uint32_t)c & 0xffffu) | ((uint32_t)(c >> 32) << 16);
+    }
+}
+
+// Bin width of the weighted sweep's chunks: all 32-bit, all 64-bit, or per
+// chunk from k_vchunk_fit.
+enum : int { VFIT_NARROW = 0, VFIT_WIDE = 1, VFIT_PER_CHUNK = 2 };
+
+// fit[c] = 1 when chunk c of the M filled voxels (chunks even in voxel count)
+// holds more than 65535 points of either sample, else 0.  Block c sums its
+// chunk.
+__global__ __launch_bounds__(256) void k_vchunk_fit(const uint64_t *__restrict__ inc, int64_t M, int chunks,
+                                                    uint32_t *__restrict__ fit)
+{
+    __shared__ uint64_t sp[4], sq[4];
+    const int c = blockIdx.x;
+    const int64_t c0 = M * c / chunks, c1 = M * (c + 1) / chunks;
+    uint64_t p = 0, q = 0;
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
+        const uint64_t v = inc[e];
+        p += (uint32_t)v;
+        q += v >> 32;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        p += __shfl_xor(p, off, 64);
+        q += __shfl_xor(q, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sp[threadIdx.x >> 6] = p;
+        sq[threadIdx.x >> 6] = q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        p = sp[0] + sp[1] + sp[2] + sp[3];
+        q = sq[0] + sq[1] + sq[2] + sq[3];
+        fit[c] = (p > 65535u || q > 65535u) ? 1u : 0u;
     }
 }
 
@@ -328,48 +378,218 @@ __device__ __forceinline__ void vfinish(Get get, uint64_t *red, const uint64_t *
     }
 }
 
-// Bins of the weighted sweep: 32-bit words holding c_P | c_Q << 16 when no
-// bin can reach 65536 points of either sample (ds_add_u32, the faster LDS
-// atomic), else 64-bit words c_P | c_Q << 32 (ds_add_u64).
-template <bool WIDE>
-struct VBin {
-    typedef typename std::conditional<WIDE, uint64_t, uint32_t>::type T;
-    typedef __attribute__((address_space(3))) T lds_t;
-    static constexpr int SH = WIDE ? 9 : 8;  // log2 of the bytes of one bin row (64 lanes)
-    // a voxel's increment (c_P in the low, c_Q in the high word) in this format
-    __device__ static __forceinline__ T of(uint64_t v)
-    {
-        if constexpr (WIDE) return v;
-        else return (uint32_t)v | ((uint32_t)(v >> 32) << 16);
-    }
-    __device__ static __forceinline__ void split(T v, uint64_t &cp, uint64_t &cq)
-    {
-        if constexpr (WIDE) {
-            cp = (uint32_t)v;
-            cq = v >> 32;
+// Bin addresses (32-bit bins) of U consecutive voxels of the encoding held in
+// buf (stride VLayout<D>::STRIDE words), as block_addrs computes them for
+// points of the rank path.
+template <int D, int U>
+__device__ __forceinline__ void vblock_addrs(const uint32_t *buf, const Origin<PATH_R16, D> &org, uint32_t base,
+                                             uint32_t (&a)[U])
+{
+    constexpr int S = VLayout<D>::STRIDE;
+    constexpr int NP = Geo<D>::NPERM;
+    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+#pragma unroll
+    for (int g = 0; g < U; g += 4) {
+        uint32_t R[2][4];
+        uint32_t q[4];
+        if constexpr (D == 5 || D == 6) {
+            // one v_perm serves the second groups of two voxels (dimensions 4, 5)
+            constexpr uint32_t SEL = D == 6 ? 0x0b0a0908u : 0x0c0a0c08u;
+#pragma unroll
+            for (int u = 0; u < 4; u += 2) {
+                uint32_t r0[Geo<D>::NREG], r1[Geo<D>::NREG];
+                signs<PATH_R16, D>(buf + (g + u) * S, org, r0);
+                signs<PATH_R16, D>(buf + (g + u + 1) * S, org, r1);
+                R[0][u] = group_bytes<D>(r0, 0);
+                R[0][u + 1] = group_bytes<D>(r1, 0);
+                R[1][u] = R[1][u + 1] = __builtin_amdgcn_perm(r1[2], r0[2], SEL);
+            }
+            addr4_w2(R, base, q, w0, w1, w1 << 16);
         } else {
-            cp = v & 0xffffu;
-            cq = v >> 16;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint32_t r[Geo<D>::NREG];
+                signs<PATH_R16, D>(buf + (g + u) * S, org, r);
+                R[0][u] = group_bytes<D>(r, 0);
+                R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+            }
+            addr4<NP>(R, base, q, w0, w1);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[g + u] = q[u];
+    }
+}
+
+// Voxels [lo, hi) of the encoding RV against the lane's G origins (one per
+// origin group, histogram j at base[j]) into 32-bit bins (c_P | c_Q << 16,
+// each voxel's counts word W32[i] as its increment): the exact sweep's
+// software pipeline over blocks of VLayout<D>::U voxels, each block's loads
+// serving all G origin groups.  The sign words come through scalar loads;
+// the counts words through vector loads from an address the compiler must
+// treat as per-lane, so that they land in vector registers, where the LDS
+// atomics take their data, without a move per voxel.
+template <int D, int G>
+__device__ __forceinline__ void vsweep_narrow(const uint32_t *__restrict__ RV, const uint32_t *__restrict__ W32,
+                                              int64_t lo, int64_t hi, const Origin<PATH_R16, D> (&org)[G],
+                                              const uint32_t (&base)[G])
+{
+    constexpr int S = VLayout<D>::STRIDE;
+    constexpr int U = VLayout<D>::U;
+    constexpr int NP = Geo<D>::NPERM;
+    // the same address in every lane, held in vector registers (a global
+    // pointer: global loads count only against the vector-memory counter, so
+    // the waits for the scalar loads and LDS atomics do not include them)
+    typedef const __attribute__((address_space(1))) uint32_t gu32;
+    uint64_t wv = (uint64_t)(uintptr_t)W32;
+    asm volatile("" : "+v"(wv));
+    gu32 *Wv = (gu32 *)(uintptr_t)wv;
+    auto block = [&](const uint32_t (&buf)[U * S], uint32_t (&a)[G][U]) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) vblock_addrs<D, U>(buf, org[j], base[j], a[j]);
+    };
+    auto adds = [&](const uint32_t (&wt)[U], const uint32_t (&a)[G][U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < G; ++j) lds_add(a[j][u], wt[u]);
+    };
+    int64_t i = lo;
+    int64_t nblk = hi > lo ? (hi - lo) / U : 0;
+    if (nblk & 1) {  // an odd block first, so the pipelined loop runs in pairs
+        uint32_t buf[U * S], wt[U], a[G][U];
+#pragma unroll
+        for (int e = 0; e < U * S; ++e) buf[e] = RV[i * S + e];
+#pragma unroll
+        for (int u = 0; u < U; ++u) wt[u] = Wv[i + u];
+        block(buf, a);
+        adds(wt, a);
+        i += U;
+        --nblk;
+    }
+    if (nblk > 0) {
+        const int64_t last = hi - U;
+        uint32_t bufA[U * S], bufB[U * S], wA[U], wB[U];
+#pragma unroll
+        for (int e = 0; e < U * S; ++e) bufA[e] = RV[i * S + e];
+#pragma unroll
+        for (int u = 0; u < U; ++u) wA[u] = Wv[i + u];
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int64_t t = 0; t < nblk; t += 2) {
+#pragma unroll
+            for (int e = 0; e < U * S; ++e) bufB[e] = RV[(i + U) * S + e];
+#pragma unroll
+            for (int u = 0; u < U; ++u) wB[u] = Wv[i + U + u];
+            uint32_t a[G][U];
+            block(bufA, a);
+            wait_lgkm();
+            adds(wA, a);
+            const int64_t na = (i + 2 * U < last) ? i + 2 * U : last;
+#pragma unroll
+            for (int e = 0; e < U * S; ++e) bufA[e] = RV[na * S + e];
+#pragma unroll
+            for (int u = 0; u < U; ++u) wA[u] = Wv[na + u];
+            block(bufB, a);
+            wait_lgkm();
+            adds(wB, a);
+            i += 2 * U;
         }
     }
-};
+    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+    for (; i < hi; ++i) {
+        uint32_t buf[S];
+#pragma unroll
+        for (int e = 0; e < S; ++e) buf[e] = RV[i * S + e];
+        const uint32_t wt = Wv[i];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            uint32_t r[Geo<D>::NREG];
+            signs<PATH_R16, D>(buf, org[j], r);
+            const uint32_t R0 = group_bytes<D>(r, 0);
+            const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+            lds_add(addr1<NP>(R0, R1, base[j], w0, w1), wt);
+        }
+    }
+}
 
-// The weighted sweep of one block's 64 origins over the voxels [c0, c1),
-// split over the W waves, into the block's shared histogram h (lane-minor:
-// bin*64 + lane, zeroed beforehand).
-template <int D, int W, bool WIDE>
-__device__ __forceinline__ void vsweep_range(const uint32_t *__restrict__ R, const uint64_t *__restrict__ inc,
-                                             const Origin<PATH_R16, D> &org, int64_t c0, int64_t c1,
-                                             typename VBin<WIDE>::T *h)
+// The same for a chunk with more than 65535 points of a sample, one sample at
+// a time: 32-bit bins of that sample's counts alone (half = 0: c_P, the low
+// word of each voxel's increment; 1: c_Q, the high word), one origin group.
+template <int D>
+__device__ __forceinline__ void vsweep_one_sample(const uint32_t *__restrict__ RV, const uint64_t *__restrict__ inc,
+                                                  int half, int64_t lo, int64_t hi, const Origin<PATH_R16, D> &org,
+                                                  uint32_t base)
 {
-    typedef VBin<WIDE> B;
-    typedef typename B::T T;
-    typedef typename B::lds_t lds_t;
-    constexpr int PW = Layout<PATH_R16, D>::PW;
+    constexpr int S = VLayout<D>::STRIDE;
     constexpr int NP = Geo<D>::NPERM;
-    constexpr int U = 4;
+    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+    for (int64_t i = lo; i < hi; ++i) {
+        uint32_t buf[S];
+#pragma unroll
+        for (int e = 0; e < S; ++e) buf[e] = RV[i * S + e];
+        uint32_t r[Geo<D>::NREG];
+        signs<PATH_R16, D>(buf, org, r);
+        const uint32_t R0 = group_bytes<D>(r, 0);
+        const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+        const uint32_t c = (uint32_t)(inc[i] >> (32 * half));
+        if (c) lds_add(addr1<NP>(R0, R1, base, w0, w1), c);
+    }
+}
+
+// LDS bytes of the weighted sweep's block: H histograms of 2^d 32-bit bins x
+// 64 lanes (H = G, or 2 for a single chunk too heavy for one-pass bins: one
+// histogram per sample); the scoring's reduction space (W x 64 x 12 bytes)
+// reuses them.
+__host__ __device__ constexpr size_t vsweep_lds(int d, int waves, int H)
+{
+    return (size_t)H * ((size_t)1 << d) * 64 * 4 > (size_t)waves * 64 * 12 ? (size_t)H * ((size_t)1 << d) * 64 * 4
+                                                                           : (size_t)waves * 64 * 12;
+}
+
+// Block (G origin groups, chunk): the filled voxels (blockIdx.x * G + j) *
+// 64 + lane as origins, the filled voxels of chunk blockIdx.y (of gridDim.y)
+// as weighted points, split over the W waves, one shared histogram of 32-bit
+// bins per origin group (lane-minor: bin*64 + lane).  A chunk that holds at
+// most 65535 points of each sample adds both samples' counts at once
+// (c_P | c_Q << 16).  Heavier chunks add one sample at a time: with several
+// chunks (mode VFIT_PER_CHUNK, where fit[chunk] is set) each sample's pass
+// goes through the partial sums; a single chunk (mode VFIT_WIDE, G = 1) keeps
+// one histogram per sample.  With Gpart null the block scores its origins
+// itself; otherwise it adds its non-zero counts into the zeroed 64-bit
+// Gpart[group][BINS][64] (c_P | c_Q << 32) and k_vscore scores them.
+template <int D, int W, int G>
+__global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ RV,
+                                                   const uint32_t *__restrict__ W32,
+                                                   const uint64_t *__restrict__ inc,
+                                                   const uint64_t *__restrict__ keys, int64_t M,
+                                                   int64_t n_p, int64_t n_q, int mode,
+                                                   const uint32_t *__restrict__ fit,
+                                                   unsigned long long *__restrict__ Gpart, VBest *__restrict__ bb)
+{
+    constexpr int S = VLayout<D>::STRIDE;
+    constexpr int HB = Geo<D>::BINS * 64;  // bins of one histogram
+    extern __shared__ uint32_t h32[];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t groups = (M + 63) / 64;
+    const bool wide =
+        mode == VFIT_WIDE || (mode == VFIT_PER_CHUNK && __builtin_amdgcn_readfirstlane(fit[blockIdx.y]) != 0u);
+
+    for (int i = threadIdx.x; i < (mode == VFIT_WIDE ? 2 : G) * HB; i += W * 64) h32[i] = 0;
+    Origin<PATH_R16, D> org[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const int64_t k = ((int64_t)blockIdx.x * G + j) * 64 + lane;
+        const int64_t kk = k < M ? k : M - 1;
+#pragma unroll
+        for (int p = 0; p < Layout<PATH_R16, D>::PW; ++p) org[j].o[p] = p < Geo<D>::NREG ? RV[kk * S + p] : 0u;
+    }
+    uint32_t base[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+        base[j] = (uint32_t)(uintptr_t)(lds_u32 *)(h32 + (size_t)j * HB + Geo<D>::KOFF * 64 + lane);
+    __syncthreads();
+
+    const int64_t c0 = M * (int64_t)blockIdx.y / gridDim.y, c1 = M * ((int64_t)blockIdx.y + 1) / gridDim.y;
     const int64_t per = (c1 - c0 + W - 1) / W;
     int64_t a = c0 + (int64_t)w * per, b = a + per;
     a = a < c1 ? a : c1;
@@ -377,172 +597,96 @@ __device__ __forceinline__ void vsweep_range(const uint32_t *__restrict__ R, con
     a = __builtin_amdgcn_readfirstlane((int)a);
     b = __builtin_amdgcn_readfirstlane((int)b);
 
-    const uint32_t base = (uint32_t)(uintptr_t)(lds_t *)(h + Geo<D>::KOFF * 64 + lane);
-    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
-    // bin addresses of a block of U voxels, and their weighted increments
-    auto addrs = [&](const uint32_t (&buf)[U * PW], uint32_t (&ad)[U]) {
-        uint32_t Rg[2][4];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            uint32_t r[Geo<D>::NREG];
-            signs<PATH_R16, D>(buf + u * PW, org, r);
-            Rg[0][u] = group_bytes<D>(r, 0);
-            Rg[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-        }
-        addr4<NP, B::SH>(Rg, base, ad, w0, w1);
-    };
-    auto adds = [&](const uint32_t (&ad)[U], const uint64_t (&iv)[U]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            __hip_atomic_fetch_add((lds_t *)(uintptr_t)ad[u], B::of(iv[u]), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-    };
-    auto load = [&](int64_t at, uint32_t (&buf)[U * PW], uint64_t (&iv)[U]) {
-#pragma unroll
-        for (int e = 0; e < U * PW; ++e) buf[e] = R[at * PW + e];
-#pragma unroll
-        for (int u = 0; u < U; ++u) iv[u] = inc[at + u];
-    };
-    int64_t i = a;
-    int64_t nblk = b > a ? (b - a) / U : 0;
-    if (nblk & 1) {  // an odd block first, so the pipelined loop runs in pairs
-        uint32_t buf[U * PW], ad[U];
-        uint64_t iv[U];
-        load(i, buf, iv);
-        addrs(buf, ad);
-        adds(ad, iv);
-        i += U;
-        --nblk;
-    }
-    if (nblk > 0) {
-        // The same software pipeline as the exact sweep: the scalar loads of
-        // the next block go out before this block's addresses are computed,
-        // and one wait per block (scalar loads and LDS atomics share its
-        // counter) covers loads issued a whole block earlier.  The last
-        // trip's prefetch is clamped to the last full block (in bounds).
-        const int64_t last = b - U;
-        uint32_t bufA[U * PW], bufB[U * PW], ad[U];
-        uint64_t ivA[U], ivB[U];
-        load(i, bufA, ivA);
-        __builtin_amdgcn_s_waitcnt(0);
-        for (int64_t t = 0; t < nblk; t += 2) {
-            load(i + U, bufB, ivB);
-            addrs(bufA, ad);
-            wait_lgkm();
-            adds(ad, ivA);
-            load((i + 2 * U < last) ? i + 2 * U : last, bufA, ivA);
-            addrs(bufB, ad);
-            wait_lgkm();
-            adds(ad, ivB);
-            i += 2 * U;
-        }
-    }
-    for (; i < b; ++i) {
-        uint32_t buf[PW];
-#pragma unroll
-        for (int e = 0; e < PW; ++e) buf[e] = R[i * PW + e];
-        uint32_t r[Geo<D>::NREG];
-        signs<PATH_R16, D>(buf, org, r);
-        const uint32_t R0 = group_bytes<D>(r, 0);
-        const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-        __hip_atomic_fetch_add((lds_t *)(uintptr_t)addr1<NP, B::SH>(R0, R1, base, w0, w1), B::of(inc[i]),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-}
-
-// Block (group, chunk): the 64 filled voxels group*64 + lane as origins, the
-// filled voxels of chunk blockIdx.y (of gridDim.y) as weighted points, split
-// over the W waves, one shared histogram (lane-minor: bin*64 + lane).  The
-// block first sums its chunk's increments: when neither sample has more than
-// 65535 points in the chunk, no bin can overflow 16 bits and the histogram
-// takes 32-bit bins.  With one chunk the block scores its origins itself;
-// otherwise it writes its counts (every bin, c_P | c_Q << 32) to
-// G[chunk][group][BINS][64] and k_vscore sums the chunks.
-template <int D, int W>
-__global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ R,
-                                                   const uint64_t *__restrict__ inc,
-                                                   const uint64_t *__restrict__ keys, int64_t M,
-                                                   int64_t n_p, int64_t n_q, unsigned long long *__restrict__ G,
-                                                   VBest *__restrict__ bb)
-{
-    constexpr int BINS = Geo<D>::BINS;
-    extern __shared__ uint64_t h64[];
-    __shared__ uint64_t tot[2 * W];
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int64_t group = blockIdx.x;
-    const int64_t c0 = M * (int64_t)blockIdx.y / gridDim.y, c1 = M * ((int64_t)blockIdx.y + 1) / gridDim.y;
-
-    // the chunk's points per sample
-    uint64_t sp = 0, sq = 0;
-    for (int64_t e = c0 + threadIdx.x; e < c1; e += W * 64) {
-        const uint64_t v = inc[e];
-        sp += (uint32_t)v;
-        sq += v >> 32;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        sp += __shfl_xor(sp, off, 64);
-        sq += __shfl_xor(sq, off, 64);
-    }
-    if (lane == 0) {
-        tot[2 * w] = sp;
-        tot[2 * w + 1] = sq;
-    }
-    for (int i = threadIdx.x; i < BINS * 64; i += W * 64) h64[i] = 0;
-    const int64_t k = group * 64 + lane;
-    Origin<PATH_R16, D> org;
-    org.load(R, k < M ? k : M - 1);
-    __syncthreads();
-    sp = 0;
-    sq = 0;
-    for (int v = 0; v < W; ++v) {
-        sp += tot[2 * v];
-        sq += tot[2 * v + 1];
-    }
-    const bool wide = __builtin_amdgcn_readfirstlane((sp > 65535u || sq > 65535u) ? 1 : 0) != 0;
-    if (wide)
-        vsweep_range<D, W, true>(R, inc, org, c0, c1, h64);
-    else
-        vsweep_range<D, W, false>(R, inc, org, c0, c1, reinterpret_cast<uint32_t *>(h64));
-    __syncthreads();
-    if (gridDim.y > 1) {
-        unsigned long long *g = G + ((size_t)blockIdx.y * gridDim.x + group) * BINS * 64;
-        const uint32_t *h32 = reinterpret_cast<const uint32_t *>(h64);
-        for (int e = threadIdx.x; e < BINS * 64; e += W * 64)
-            g[e] = wide ? h64[e] : ((unsigned long long)(h32[e] & 0xffffu) | ((unsigned long long)(h32[e] >> 16) << 32));
+    if (mode == VFIT_WIDE) {
+        // one chunk (G = 1): c_P into the first histogram, c_Q into the second
+        vsweep_one_sample<D>(RV, inc, 0, a, b, org[0], base[0]);
+        vsweep_one_sample<D>(RV, inc, 1, a, b, org[0], base[0] + HB * 4);
+        __syncthreads();
+        if (blockIdx.x < groups)
+            vfinish<D, W>(
+                [&](int jb, uint64_t &cp, uint64_t &cq) {
+                    cp = h32[jb * 64 + lane];
+                    cq = h32[HB + jb * 64 + lane];
+                },
+                reinterpret_cast<uint64_t *>(h32), keys, M, n_p, n_q, blockIdx.x, bb);
         return;
     }
     if (wide) {
-        vfinish<D, W>([&](int j, uint64_t &cp, uint64_t &cq) { VBin<true>::split(h64[j * 64 + lane], cp, cq); },
-                      h64, keys, M, n_p, n_q, group, bb);
-    } else {
-        const uint32_t *h32 = reinterpret_cast<const uint32_t *>(h64);
-        vfinish<D, W>([&](int j, uint64_t &cp, uint64_t &cq) { VBin<false>::split(h32[j * 64 + lane], cp, cq); },
-                      h64, keys, M, n_p, n_q, group, bb);
+        // one sample per pass, each pass's counts added into the partial sums
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            if (half) {
+                __syncthreads();
+                for (int i = threadIdx.x; i < G * HB; i += W * 64) h32[i] = 0;
+                __syncthreads();
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j) vsweep_one_sample<D>(RV, inc, half, a, b, org[j], base[j]);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int64_t group = (int64_t)blockIdx.x * G + j;
+                if (group >= groups) break;  // block-uniform
+                unsigned long long *g = Gpart + (size_t)group * HB;
+                for (int e = threadIdx.x; e < HB; e += W * 64) {
+                    const uint64_t v = h32[(size_t)j * HB + e];
+                    if (v) atomicAdd(g + e, (unsigned long long)(v << (32 * half)));
+                }
+            }
+        }
+        return;
+    }
+    vsweep_narrow<D, G>(RV, W32, a, b, org, base);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const int64_t group = (int64_t)blockIdx.x * G + j;
+        if (group >= groups) break;  // block-uniform
+        if (Gpart) {
+            unsigned long long *g = Gpart + (size_t)group * HB;
+            for (int e = threadIdx.x; e < HB; e += W * 64) {
+                const uint32_t v = h32[(size_t)j * HB + e];
+                if (v) atomicAdd(g + e, (unsigned long long)(v & 0xffffu) | ((unsigned long long)(v >> 16) << 32));
+            }
+        } else {
+            // vfinish reads every bin of histogram j before it writes its
+            // reduction space over the start of the histograms; the later
+            // groups' histograms lie beyond that space (checked on the host)
+            vfinish<D, W>(
+                [&](int jb, uint64_t &cp, uint64_t &cq) {
+                    const uint32_t v = h32[(size_t)j * HB + jb * 64 + lane];
+                    cp = v & 0xffffu;
+                    cq = v >> 16;
+                },
+                reinterpret_cast<uint64_t *>(h32), keys, M, n_p, n_q, group, bb);
+        }
     }
 }
 
-// Scores group blockIdx.x from the counts of the `chunks` chunks in G.
+// Scores group blockIdx.x from the counts the chunks added into G.
 template <int D, int W>
-__global__ __launch_bounds__(W * 64) void k_vscore(const unsigned long long *__restrict__ G, int chunks,
+__global__ __launch_bounds__(W * 64) void k_vscore(const unsigned long long *__restrict__ G,
                                                    const uint64_t *__restrict__ keys, int64_t M,
                                                    int64_t n_p, int64_t n_q, VBest *__restrict__ bb)
 {
     __shared__ uint64_t red[W * 64 * 12 / 8];
     constexpr int BINS = Geo<D>::BINS;
-    const int64_t group = blockIdx.x;
     const int lane = threadIdx.x & 63;
-    const size_t stride = (size_t)gridDim.x * BINS * 64;
-    const unsigned long long *g = G + (size_t)group * BINS * 64 + lane;
+    const unsigned long long *g = G + (size_t)blockIdx.x * BINS * 64 + lane;
     vfinish<D, W>(
         [&](int j, uint64_t &cp, uint64_t &cq) {
-            uint64_t v = 0;
-            for (int c = 0; c < chunks; ++c) v += g[c * stride + (size_t)j * 64];
+            const uint64_t v = g[(size_t)j * 64];
             cp = (uint32_t)v;
             cq = v >> 32;
         },
-        red, keys, M, n_p, n_q, group, bb);
+        red, keys, M, n_p, n_q, blockIdx.x, bb);
+}
+
+__global__ void k_vzero(unsigned long long *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 __global__ __launch_bounds__(1024) void k_vreduce(const VBest *__restrict__ bb, int64_t n,
@@ -640,16 +784,10 @@ hipError_t launch_vox_front(const float *Z, int64_t N, int64_t n_p, int d, int V
     }
 }
 
-size_t vsweep_lds_bytes(int d, int waves)
-{
-    const size_t hist = ((size_t)1 << d) * 64 * 8;
-    const size_t fin = (size_t)waves * 64 * 12;
-    return std::max(hist, fin);
-}
 
 // Default shape of the weighted sweep: 8 waves per block, and point chunks
 // enough for about four blocks per CU when the filled voxels are few, each
-// chunk at least 512 points.
+// chunk at least 512 voxels.
 VSweepPlan vsweep_default_plan(int64_t M)
 {
     VSweepPlan p;
@@ -665,52 +803,91 @@ VSweepPlan vsweep_default_plan(int64_t M)
     return p;
 }
 
-bool vsweep_plan_ok(const VSweepPlan &p, int64_t M)
+static int vsweep_mode(const VSweepPlan &p, int64_t n_p, int64_t n_q)
 {
-    return (p.waves == 4 || p.waves == 8 || p.waves == 16) && p.chunks >= 1 && p.chunks <= 16 &&
-           p.chunks <= M;
+    if (n_p <= 65535 && n_q <= 65535) return VFIT_NARROW;
+    return p.chunks == 1 ? VFIT_WIDE : VFIT_PER_CHUNK;
+}
+
+bool vsweep_plan_ok(const VSweepPlan &p, int64_t M, int d)
+{
+    // with two groups scored in the block, the reduction space (at the start
+    // of the histograms) must leave the second group's histogram alone
+    const size_t hist = ((size_t)1 << d) * 64 * 4, red = (size_t)p.waves * 64 * 12;
+    return (p.waves == 4 || p.waves == 8 || p.waves == 16) && (p.per_block == 1 || p.per_block == 2) &&
+           p.chunks >= 1 && p.chunks <= VSWEEP_MAX_CHUNKS && p.chunks <= M &&
+           vsweep_lds(d, p.waves, 2) <= (size_t)MAX_LDS_BYTES && (p.per_block == 1 || red <= hist);
 }
 
 size_t vsweep_partial_bytes(int64_t M, int d, const VSweepPlan &p)
 {
     if (p.chunks <= 1) return 0;
-    return (size_t)p.chunks * ((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint64_t);
+    return (size_t)((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint64_t);
 }
 
-template <int D, int W>
+template <int D, int W, int G>
 static hipError_t launch_vsweep_w(const uint64_t *keys, const uint64_t *inc, int64_t M, int chunks, int64_t n_p,
-                                  int64_t n_q, const uint32_t *R, void *bb, void *partial, hipStream_t s)
+                                  int64_t n_q, const uint32_t *RV, const uint32_t *W32, int mode, const uint32_t *fit, void *bb,
+                                  void *partial, hipStream_t s)
 {
-    const size_t lds = vsweep_lds_bytes(D, W);
+    const size_t lds = vsweep_lds(D, W, mode == VFIT_WIDE ? 2 : G);
+    if (lds > (size_t)MAX_LDS_BYTES || (mode == VFIT_WIDE && (G != 1 || chunks != 1))) return hipErrorInvalidValue;
     static std::once_flag attr;
     if (lds > 64 * 1024)
         std::call_once(attr, [] {
-            if (hipFuncSetAttribute((const void *)k_vsweep<D, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            if (hipFuncSetAttribute((const void *)k_vsweep<D, W, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     MAX_LDS_BYTES) != hipSuccess)
                 (void)hipGetLastError();
         });
     const int64_t groups = (M + 63) / 64;
-    unsigned long long *G = (unsigned long long *)partial;
-    if (chunks > 1 && !G) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_vsweep<D, W>), dim3((unsigned)groups, (unsigned)chunks), dim3(W * 64), lds, s, R,
-                       inc, keys, M, n_p, n_q, G, (VBest *)bb);
-    if (chunks > 1)
-        hipLaunchKernelGGL((k_vscore<D, W>), dim3((unsigned)groups), dim3(W * 64), 0, s, G, chunks, keys, M, n_p,
-                           n_q, (VBest *)bb);
+    // the partial sums take the chunks' counts; a single chunk scores in the block
+    const bool via_partial = chunks > 1;
+    unsigned long long *Gp = via_partial ? (unsigned long long *)partial : nullptr;
+    if (via_partial) {
+        if (!Gp) return hipErrorInvalidValue;
+        const int64_t n = groups * Geo<D>::BINS * 64;
+        hipLaunchKernelGGL(k_vzero, dim3(grid_for(n)), dim3(256), 0, s, Gp, n);
+    }
+    hipLaunchKernelGGL((k_vsweep<D, W, G>), dim3((unsigned)((groups + G - 1) / G), (unsigned)chunks), dim3(W * 64),
+                       lds, s, RV, W32, inc, keys, M, n_p, n_q, mode, fit, Gp, (VBest *)bb);
+    if (via_partial)
+        hipLaunchKernelGGL((k_vscore<D, W>), dim3((unsigned)groups), dim3(W * 64), 0, s, Gp, keys, M, n_p, n_q,
+                           (VBest *)bb);
     return hipGetLastError();
+}
+
+template <int D, int W>
+static hipError_t launch_vsweep_g(int G, const uint64_t *keys, const uint64_t *inc, int64_t M, int chunks,
+                                  int64_t n_p, int64_t n_q, const uint32_t *RV, const uint32_t *W32, int mode, const uint32_t *fit,
+                                  void *bb, void *partial, hipStream_t s)
+{
+    if (G == 2 && mode != VFIT_WIDE)
+        return launch_vsweep_w<D, W, 2>(keys, inc, M, chunks, n_p, n_q, RV, W32, mode, fit, bb, partial, s);
+    return launch_vsweep_w<D, W, 1>(keys, inc, M, chunks, n_p, n_q, RV, W32, mode, fit, bb, partial, s);
 }
 
 template <int D>
 static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int64_t M, const VSweepPlan &p,
-                                  int V, int64_t n_p, int64_t n_q, uint32_t *R, void *bb, void *partial,
-                                  uint32_t *flags, ResultDev *out, hipStream_t s)
+                                  int V, int64_t n_p, int64_t n_q, uint32_t *RV, uint32_t *fit, void *bb,
+                                  void *partial, uint32_t *flags, ResultDev *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vox_encode<D>, dim3(grid_for(M)), dim3(256), 0, s, keys, M, V, R);
+    // the counts words follow the M voxels' sign words
+    uint32_t *W32 = RV + M * VLayout<D>::STRIDE;
+    hipLaunchKernelGGL(k_vox_encode<D>, dim3(grid_for(M)), dim3(256), 0, s, keys, inc, M, V, RV, W32);
+    // chunks of more than 65535 points of a sample cannot take the one-pass
+    // bins: with both samples that small no chunk can hold so many; a single
+    // chunk holds them all
+    const uint32_t *fitp = nullptr;
+    const int mode = vsweep_mode(p, n_p, n_q);
+    if (mode == VFIT_PER_CHUNK) {
+        hipLaunchKernelGGL(k_vchunk_fit, dim3((unsigned)p.chunks), dim3(256), 0, s, inc, M, p.chunks, fit);
+        fitp = fit;
+    }
     hipError_t e;
     switch (p.waves) {
-    case 4: e = launch_vsweep_w<D, 4>(keys, inc, M, p.chunks, n_p, n_q, R, bb, partial, s); break;
-    case 8: e = launch_vsweep_w<D, 8>(keys, inc, M, p.chunks, n_p, n_q, R, bb, partial, s); break;
-    case 16: e = launch_vsweep_w<D, 16>(keys, inc, M, p.chunks, n_p, n_q, R, bb, partial, s); break;
+    case 4: e = launch_vsweep_g<D, 4>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s); break;
+    case 8: e = launch_vsweep_g<D, 8>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s); break;
+    case 16: e = launch_vsweep_g<D, 16>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -722,13 +899,13 @@ static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int
 size_t vdks_best_bytes(int64_t M) { return (size_t)((M + 63) / 64) * sizeof(VBest); }
 
 hipError_t launch_vsweep(const uint64_t *keys, const uint64_t *inc, int64_t M, int d, int V, int64_t n_p,
-                         int64_t n_q, const VSweepPlan &plan, uint32_t *R, void *bb, void *partial, uint32_t *flags,
-                         ResultDev *out, hipStream_t s)
+                         int64_t n_q, const VSweepPlan &plan, uint32_t *RV, uint32_t *fit, void *bb, void *partial,
+                         uint32_t *flags, ResultDev *out, hipStream_t s)
 {
-    if (M < 1 || M > 0x7fffffff || !vsweep_plan_ok(plan, M)) return hipErrorInvalidValue;
+    if (M < 1 || M > 0x7fffffff || !vsweep_plan_ok(plan, M, d)) return hipErrorInvalidValue;
     switch (d) {
 #define DDKS_VS(DD) \
-    case DD: return launch_vsweep_d<DD>(keys, inc, M, plan, V, n_p, n_q, R, bb, partial, flags, out, s);
+    case DD: return launch_vsweep_d<DD>(keys, inc, M, plan, V, n_p, n_q, RV, fit, bb, partial, flags, out, s);
         DDKS_VS(1) DDKS_VS(2) DDKS_VS(3) DDKS_VS(4) DDKS_VS(5) DDKS_VS(6) DDKS_VS(7) DDKS_VS(8)
 #undef DDKS_VS
     default: return hipErrorInvalidValue;

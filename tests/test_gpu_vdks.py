@@ -120,11 +120,13 @@ def _heavy_and_light(seed, d, n_heavy):
     return P, Q
 
 
-@pytest.mark.parametrize("shape", ["4:1", "16:3", "8:6", "4:16"])  # waves:chunks
+@pytest.mark.parametrize("shape", ["4:1", "16:3", "8:6", "4:16", "4:1:2", "8:6:2", "16:3:2"])  # waves:chunks[:groups]
 def test_forced_vsweep_shapes(oracle_mod, shape):
-    """Every admissible shape of the weighted sweep gives the oracle's result,
-    with 32-bit bins (chunks under 65536 points of each sample), with 64-bit
-    bins, and with both kinds of chunk in one launch."""
+    """Every admissible shape of the weighted sweep (one or two origin groups
+    per block) gives the oracle's result, with 32-bit bins (chunks under 65536
+    points of each sample), with 64-bit bins, and with both kinds of chunk in
+    one launch; a shape the dimension does not admit (two groups of 64-bit
+    bins at d = 8 exceed the LDS) falls back to the default."""
     from paper_2106_13706_amd import workloads
     ctx = _ctx_env({"DDKS_FORCE_VSWEEP": shape})
     try:
@@ -136,6 +138,10 @@ def test_forced_vsweep_shapes(oracle_mod, shape):
         P = g.standard_normal((90000, 2)).astype(np.float32)
         Q = (g.standard_normal((80000, 2)) + 0.1).astype(np.float32)
         check(ctx, oracle_mod, P, Q, 3)  # 9 voxels: every chunk far over 65535 points
+        check(ctx, oracle_mod, *_heavy_and_light(8, 8, 70000), 3)
+        P = g.standard_normal((3000, 5)).astype(np.float32)
+        Q = (g.standard_normal((2900, 5)) + 0.2).astype(np.float32)
+        check(ctx, oracle_mod, P, Q, 6)  # an odd number of origin groups
     finally:
         ctx.close()
 
@@ -153,4 +159,4 @@ def test_vsweep_shape_tuned_and_cached(oracle_mod, tmp_path):
     lines = [list(map(int, l.split())) for l in cache.read_text().split("\n") if l.strip()]
     print(f"  cache: {lines}", flush=True)
     vs = [l for l in lines if l[0] == 30 and l[1] == 4]
-    assert len(vs) == 1 and vs[0][3] in (4, 8, 16) and 1 <= vs[0][4] <= 16
+    assert len(vs) == 1 and vs[0][3] in (4, 8, 16) and 1 <= vs[0][4] % 256 <= 16 and vs[0][4] // 256 in (0, 1)
