@@ -11,12 +11,11 @@
 //   1. k_rank_sort32  sorts each tile of STILE order keys (an order-preserving
 //                     uint32 image of the fp32 value) in registers, wave
 //                     shuffles and LDS (bitonic network).
-//   2. k_rank_count   block (t, t') stages sorted tile t' in LDS and counts,
-//                     for every point of tile t, the values of t' strictly
-//                     below its own (binary search);
-//   3. k_rank_sum     the rank of a point is the sum of its counts over all
-//                     tiles: the number of pooled values below it, which fits
-//                     16 bits since N <= 65536.
+//   2. k_rank_count   stages every sorted tile in LDS in turn and adds up,
+//                     for each of its points, the values of the tile strictly
+//                     below its own (binary search): the rank, the number of
+//                     pooled values below the point, fits 16 bits since
+//                     N <= 65536.
 // N > 65536:
 //   1. k_rank_tiles   sorts tiles of (key, index) pairs (bitonic, in
 //                     registers, wave shuffles and LDS);
@@ -58,84 +57,222 @@ __device__ __forceinline__ float point_value(const float *__restrict__ P, int64_
     return (i < n_p ? P[i * d + m] : Q[(i - n_p) * d + m]) + 0.0f;
 }
 
-// Tiles of the N <= 65536 path.  2048-key tiles measured slower at 40000
-// points x 4 dimensions: the sort took 8.9 instead of 14.4 us, but the
-// counts (13.5 vs 9.1 us) and their sum (7.2 vs 4.6 us) grew more.
-static constexpr int STILE = 4096;
-static constexpr int S32_THREADS = STILE / 4;  // four keys per thread
-static_assert(STILE == 4 * S32_THREADS, "k_rank_sort32 holds four keys per thread");
-static constexpr int LOG_STILE = 12;
-static_assert((1 << LOG_STILE) == STILE, "tile size");
+// Tiles of the N <= 65536 path: 2^LOG_STILE keys, sorted by one block of
+// 256 threads holding SKPT keys each.
+#ifndef DDKS_STILE_LOG
+#define DDKS_STILE_LOG 12
+#endif
+#ifndef DDKS_SORT_KPT
+#define DDKS_SORT_KPT 16
+#endif
+static constexpr int LOG_STILE = DDKS_STILE_LOG;
+static constexpr int STILE = 1 << LOG_STILE;
+static constexpr int SKPT = DDKS_SORT_KPT;  // keys per thread
+static constexpr int LOG_SKPT = SKPT == 16 ? 4 : 3;
+static constexpr int S32_THREADS = STILE / SKPT;
+static_assert((SKPT == 8 || SKPT == 16) && S32_THREADS >= 256 && S32_THREADS <= 1024, "tile size");
+
+// ---- the tile sort: a bitonic network on SKPT keys per thread (element
+// e = SKPT tid + r of the tile in register r of thread tid), in the form where
+// every compare-exchange puts the minimum at the lower element: phase lk
+// (blocks of 2^lk elements) first pairs e with e ^ (2^lk - 1) (the "flip",
+// which merges two sorted runs read in opposite directions), then e with
+// e ^ j for j = 2^(lk-2) .. 1.  Distances below SKPT are exchanges between a
+// thread's registers; SKPT .. 32 SKPT are lane distances 1 .. 32 within a
+// wave, exchanged through DPP and the gfx950 permlane swaps (no LDS traffic);
+// the three stages that cross waves go through LDS.
+
+// DPP controls (row = 16 lanes, bank = 4 lanes of a row).
+constexpr int DPP_QUAD_X1 = 0xB1;  // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int DPP_QUAD_X2 = 0x4E;  // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int DPP_QUAD_X3 = 0x1B;  // quad_perm [3,2,1,0]: lane ^ 3
+constexpr int DPP_ROW_SHL = 0x100;  // + n: lane l reads lane l + n of its row
+constexpr int DPP_ROW_SHR = 0x110;  // + n: lane l reads lane l - n of its row
+constexpr int DPP_ROW_MIRROR = 0x140;       // lane ^ 15
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane ^ 7
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, false);
+}
+
+// src moved by CTRL into the lanes of the banks in BANKS; old elsewhere.
+template <int CTRL, int BANKS>
+__device__ __forceinline__ uint32_t dpp_into(uint32_t old, uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xf, BANKS, false);
+}
+
+// The value of lane l ^ 16 (l ^ 32): a permlane swap of x with itself leaves
+// the partner half in one of its two results.
+__device__ __forceinline__ uint32_t lane_xor16(uint32_t x, int lane)
+{
+    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (lane & 16) ? s[0] : s[1];
+}
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t x, int lane)
+{
+    const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (lane & 32) ? s[0] : s[1];
+}
+
+// Partner value of a flip within the wave: lane l ^ (2^LM - 1), 1 <= LM <= 6.
+template <int LM>
+__device__ __forceinline__ uint32_t flip_lanes(uint32_t x, int lane)
+{
+    if constexpr (LM == 1) return dpp<DPP_QUAD_X1>(x);
+    else if constexpr (LM == 2) return dpp<DPP_QUAD_X3>(x);
+    else if constexpr (LM == 3) return dpp<DPP_ROW_HALF_MIRROR>(x);
+    else if constexpr (LM == 4) return dpp<DPP_ROW_MIRROR>(x);
+    else if constexpr (LM == 5) return lane_xor16(dpp<DPP_ROW_MIRROR>(x), lane);
+    else return lane_xor32(lane_xor16(dpp<DPP_ROW_MIRROR>(x), lane), lane);
+}
+
+__device__ __forceinline__ void cmpx(uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t a = min(lo, hi), b = max(lo, hi);
+    lo = a;
+    hi = b;
+}
+
+// A stage whose partner thread is tid ^ M, in another wave (M >= 64), with
+// the partner's registers reversed when FLIP; buf holds 256 x 4 uint4.
+template <int M, bool FLIP>
+__device__ __forceinline__ void sort_cross_wave(uint32_t (&v)[SKPT], int tid, uint4 *buf)
+{
+    const bool lower = (tid & (FLIP ? (M + 1) / 2 : M)) == 0;
+#pragma unroll
+    for (int q = 0; q < SKPT / 4; ++q) buf[q * S32_THREADS + tid] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    __syncthreads();
+    uint32_t p[SKPT];
+#pragma unroll
+    for (int q = 0; q < SKPT / 4; ++q) {
+        const uint4 x = buf[q * S32_THREADS + (tid ^ M)];
+        p[4 * q] = x.x;
+        p[4 * q + 1] = x.y;
+        p[4 * q + 2] = x.z;
+        p[4 * q + 3] = x.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SKPT; ++r) {
+        const uint32_t x = p[FLIP ? SKPT - 1 - r : r];
+        v[r] = lower ? min(v[r], x) : max(v[r], x);
+    }
+}
+
+// Half-cleaner stage j = 2^LJ.
+template <int LJ>
+__device__ __forceinline__ void sort_half(uint32_t (&v)[SKPT], int lane, int tid, uint4 *buf)
+{
+    constexpr int J = 1 << LJ;
+    if constexpr (J < SKPT) {
+#pragma unroll
+        for (int r = 0; r < SKPT; ++r)
+            if (!(r & J)) cmpx(v[r], v[r | J]);
+    } else if constexpr (J <= 2 * SKPT) {
+        // lane ^ 1, lane ^ 2: partner value by quad_perm
+        constexpr int A = J / SKPT;
+        const bool lower = (lane & A) == 0;
+#pragma unroll
+        for (int r = 0; r < SKPT; ++r) {
+            const uint32_t p = dpp<A == 1 ? DPP_QUAD_X1 : DPP_QUAD_X2>(v[r]);
+            v[r] = lower ? min(v[r], p) : max(v[r], p);
+        }
+    } else if constexpr (J <= 8 * SKPT) {
+        // lane ^ 4, lane ^ 8 on register pairs (X, Y): row shifts masked by
+        // bank put each pair's two elements in one lane (the lower one in
+        // X1), compare-exchange, then the inverse shifts put them back
+        constexpr int A = J / SKPT;
+        constexpr int LOW = A == 4 ? 0x5 : 0x3, HIGH = A == 4 ? 0xA : 0xC;
+#pragma unroll
+        for (int b = 0; b < SKPT / 2; ++b) {
+            const uint32_t X = v[2 * b], Y = v[2 * b + 1];
+            const uint32_t X1 = dpp_into<DPP_ROW_SHR + A, HIGH>(X, Y);
+            const uint32_t Y1 = dpp_into<DPP_ROW_SHL + A, LOW>(Y, X);
+            const uint32_t mn = min(X1, Y1), mx = max(X1, Y1);
+            v[2 * b] = dpp_into<DPP_ROW_SHR + A, HIGH>(mn, mx);
+            v[2 * b + 1] = dpp_into<DPP_ROW_SHL + A, LOW>(mx, mn);
+        }
+    } else if constexpr (J <= 32 * SKPT) {
+        // lane ^ 16, lane ^ 32 on register pairs: a permlane swap of the
+        // pair puts each pair's two elements in one lane, the same swap undoes it
+        constexpr int A = J / SKPT;
+#pragma unroll
+        for (int b = 0; b < SKPT / 2; ++b) {
+            const auto s = A == 16 ? __builtin_amdgcn_permlane16_swap(v[2 * b], v[2 * b + 1], false, false)
+                                   : __builtin_amdgcn_permlane32_swap(v[2 * b], v[2 * b + 1], false, false);
+            const uint32_t mn = min(s[0], s[1]), mx = max(s[0], s[1]);
+            const auto t = A == 16 ? __builtin_amdgcn_permlane16_swap(mn, mx, false, false)
+                                   : __builtin_amdgcn_permlane32_swap(mn, mx, false, false);
+            v[2 * b] = t[0];
+            v[2 * b + 1] = t[1];
+        }
+    } else {
+        sort_cross_wave<J / SKPT, false>(v, tid, buf);
+    }
+    if constexpr (LJ > 0) sort_half<LJ - 1>(v, lane, tid, buf);
+}
+
+// Phase LK: the flip, then the half-cleaners.
+template <int LK>
+__device__ __forceinline__ void sort_phase(uint32_t (&v)[SKPT], int lane, int tid, uint4 *buf)
+{
+    constexpr int K = 1 << LK;
+    if constexpr (K <= SKPT) {
+#pragma unroll
+        for (int r = 0; r < SKPT; ++r)
+            if (!(r & (K / 2))) cmpx(v[r], v[r ^ (K - 1)]);
+    } else if constexpr (K <= 64 * SKPT) {
+        const bool lower = (lane & (K / (2 * SKPT))) == 0;
+        uint32_t p[SKPT];
+#pragma unroll
+        for (int r = 0; r < SKPT; ++r) p[r] = flip_lanes<LK - LOG_SKPT>(v[SKPT - 1 - r], lane);
+#pragma unroll
+        for (int r = 0; r < SKPT; ++r) v[r] = lower ? min(v[r], p[r]) : max(v[r], p[r]);
+    } else {
+        sort_cross_wave<K / SKPT - 1, true>(v, tid, buf);
+    }
+    if constexpr (LK >= 2) sort_half<LK - 2>(v, lane, tid, buf);
+}
+
+template <int LK>
+__device__ __forceinline__ void sort_phases(uint32_t (&v)[SKPT], int lane, int tid, uint4 *buf)
+{
+    sort_phase<LK>(v, lane, tid, buf);
+    if constexpr (LK < LOG_STILE) sort_phases<LK + 1>(v, lane, tid, buf);
+}
 
 // Sorts tile blockIdx.x of dimension blockIdx.y: K[m][t][0..STILE) = the order
 // keys of points t*STILE .. t*STILE+STILE-1, ascending (0xffffffff past N).
-// Bitonic network, fully unrolled: thread tid holds elements e = 4*tid + r;
-// partners at distance j < 4 are in the same thread, j < 256 in the same wave
-// (shuffles), j >= 256 in another wave (double-buffered LDS, one barrier per
-// stage).  For j >= 4 the direction of a thread's four compare-exchanges is
-// the same (it depends on bits of e above bit 1 only).
-// Values are read from P (points 0 .. n_p - 1) then Q; flags (nullable): bit 0
-// is set if a value is NaN or infinite.
+// Thread tid reads points t*STILE + tid + 256 r (coalesced; a sort does not
+// care where its inputs start).  Values are read from P (points 0 .. n_p - 1)
+// then Q; flags (nullable): bit 0 is set if a value is NaN or infinite.
 __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__restrict__ P, int64_t n_p,
                                                              const float *__restrict__ Q, int64_t N,
                                                              int d, int64_t tiles,
                                                              uint32_t *__restrict__ K,
                                                              uint32_t *__restrict__ flags)
 {
-    __shared__ uint4 buf[2][S32_THREADS];
+    __shared__ uint4 buf[S32_THREADS * SKPT / 4];
     const int m = blockIdx.y;
     const int64_t t = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int e0 = 4 * tid;
-    uint32_t v[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint32_t v[SKPT];
     bool bad = false;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t i = t * STILE + e0 + r;
+    for (int r = 0; r < SKPT; ++r) {
+        const int64_t i = t * STILE + tid + r * S32_THREADS;
         const float x = i < N ? point_value(P, n_p, Q, i, d, m) : 0.0f;
         bad |= !isfinite(x);
         v[r] = i < N ? order_key(x) : 0xffffffffu;
     }
-    if (flags && __any(bad) && (tid & 63) == 0) atomicOr(flags, 1u);
-    int cur = 0;
+    if (flags && __any(bad) && lane == 0) atomicOr(flags, 1u);
+    sort_phases<1>(v, lane, tid, buf);
+    uint4 *out = reinterpret_cast<uint4 *>(K + ((size_t)m * tiles + t) * STILE) + tid * (SKPT / 4);
 #pragma unroll
-    for (int lk = 1; lk <= LOG_STILE; ++lk) {
-        const int k = 1 << lk;
-#pragma unroll
-        for (int lj = lk - 1; lj >= 0; --lj) {
-            const int j = 1 << lj;
-            if (j >= 4) {
-                const bool keep_min = ((e0 & j) == 0) == ((e0 & k) == 0);
-                uint32_t pv[4];
-                if (j >= 256) {
-                    buf[cur][tid] = make_uint4(v[0], v[1], v[2], v[3]);
-                    __syncthreads();
-                    const uint4 p = buf[cur][tid ^ (j >> 2)];
-                    pv[0] = p.x;
-                    pv[1] = p.y;
-                    pv[2] = p.z;
-                    pv[3] = p.w;
-                    cur ^= 1;
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) pv[r] = __shfl_xor(v[r], j >> 2, 64);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = keep_min ? min(v[r], pv[r]) : max(v[r], pv[r]);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (r & j) continue;
-                    const bool up = (((e0 + r) & k) == 0);
-                    const uint32_t lo = min(v[r], v[r | j]), hi = max(v[r], v[r | j]);
-                    v[r] = up ? lo : hi;
-                    v[r | j] = up ? hi : lo;
-                }
-            }
-        }
-    }
-    uint4 *out = reinterpret_cast<uint4 *>(K + ((size_t)m * tiles + t) * STILE);
-    out[tid] = make_uint4(v[0], v[1], v[2], v[3]);
+    for (int q = 0; q < SKPT / 4; ++q) out[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
 }
 
 // The sorted tile in LDS is skewed by one word every 64 entries: the probes
@@ -143,14 +280,29 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__rest
 // which without the skew all fall in the same LDS bank.
 __device__ __forceinline__ int skew(int e) { return e + (e >> 6); }
 
-// Number of entries of the sorted, skewed LDS tile below key (branchless; 0..STILE).
+// Number of entries of the sorted, skewed LDS tile below key (branchless
+// binary search; 0..STILE).  With p the entries found below so far (a
+// multiple of twice the current step), the search keeps a = the LDS byte
+// address of entry skew(p) = p + p/64: the probe of step j, entry
+// p + j - 1, then sits at a constant byte offset from a (4 (j - 1 + j/64 - 1)
+// for j >= 64, 4 (j - 1) below), folded into the LDS instruction, and taking
+// the step adds 4 (j + j/64) (or 4 j) to a.  At the end p = s - s/65 with
+// s = skew(p).
 __device__ __forceinline__ int count_below(const uint32_t *tile, uint32_t key)
 {
-    int p = 0;
+    typedef const __attribute__((address_space(3))) uint32_t lds_cu32;
+    const uint32_t a0 = (uint32_t)(uintptr_t)(lds_cu32 *)tile;
+    uint32_t a = a0;
 #pragma unroll
-    for (int step = STILE / 2; step >= 1; step >>= 1)
-        if (tile[skew(p + step - 1)] < key) p += step;
-    return p + (tile[skew(p)] < key ? 1 : 0);
+    for (int step = STILE / 2; step >= 1; step >>= 1) {
+        const uint32_t off = 4u * (uint32_t)(step - 1 + (step >= 64 ? step / 64 - 1 : 0));
+        const uint32_t inc = 4u * (uint32_t)(step + (step >= 64 ? step / 64 : 0));
+        const uint32_t v = *(lds_cu32 *)(uintptr_t)(a + off);
+        a += v < key ? inc : 0u;
+    }
+    const uint32_t sk = (a - a0) >> 2;
+    const int p = (int)(sk - sk / 65u);
+    return p + (*(lds_cu32 *)(uintptr_t)a < key ? 1 : 0);
 }
 
 // Writes the biased 16-bit rank of dimension m of point i.
@@ -159,54 +311,94 @@ __device__ __forceinline__ void put_rank(uint16_t *R16, int64_t i, int pw, int m
     R16[(i * pw) * 2 + m] = (uint16_t)(uint32_t)(rank - 32768);
 }
 
-// Block (t, u, m) with u = blockIdx.z: part[u][m][i] = number of values of
-// sorted tile u below point i's value, for the points i of tile t.
-__global__ __launch_bounds__(S32_THREADS) void k_rank_count(const float *__restrict__ P, int64_t n_p,
-                                                            const float *__restrict__ Q, int64_t N,
-                                                            int d, int64_t tiles,
-                                                            const uint32_t *__restrict__ K,
-                                                            uint16_t *__restrict__ part)
-{
-    __shared__ uint32_t tile[STILE + STILE / 64 + 1];
-    const int m = blockIdx.y;
-    const int64_t t = blockIdx.x, u = blockIdx.z;
-    const int tid = threadIdx.x;
-    const uint4 *src = reinterpret_cast<const uint4 *>(K + ((size_t)m * tiles + u) * STILE);
-    {
-        const uint4 v = src[tid];  // entries 4 tid .. 4 tid + 3, all in one 64-entry row
-        const int e = skew(4 * tid);
-        tile[e] = v.x;
-        tile[e + 1] = v.y;
-        tile[e + 2] = v.z;
-        tile[e + 3] = v.w;
-    }
-    uint32_t key[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t i = t * STILE + tid + r * S32_THREADS;
-        key[r] = i < N ? order_key(point_value(P, n_p, Q, i, d, m)) : 0u;
-    }
-    __syncthreads();
-    uint16_t *pu = part + ((size_t)u * d + m) * tiles * STILE + t * STILE;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pu[tid + r * S32_THREADS] = (uint16_t)count_below(tile, key[r]);
-}
+// Block (part, m) of k_rank_count<KPT, TPS> takes RC_THREADS * KPT
+// consecutive points of one tile (rc_parts(KPT) blocks per tile).
+static constexpr int RC_THREADS = 256;
+__host__ __device__ constexpr int rc_parts(int kpt) { return STILE / (RC_THREADS * kpt); }
+constexpr int RC_TILE_WORDS = STILE + STILE / 64 + 1;  // one skewed tile in LDS
 
-// The rank of point i in dimension m (values below it over all tiles), from
-// the partial counts; also zeroes the padding dimensions of each point.
-__global__ void k_rank_sum(const uint16_t *__restrict__ part, int64_t N, int d, int pw,
-                           int64_t tiles, uint16_t *__restrict__ R16)
+// The rank in dimension m of each of the block's points: the number of pooled
+// values below it, summed over all sorted tiles.  The block stages TPS tiles
+// at a time in LDS (skewed; the loads of the next TPS tiles are in flight
+// while these are searched) and searches them side by side (branchless
+// binary searches, TPS x KPT independent chains per thread).  Ranks fit 16
+// bits since N <= 65536: the biased rank is written directly, and for m = 0
+// the padding dimensions of each point are zeroed.
+template <int KPT, int TPS>
+__global__ __launch_bounds__(RC_THREADS) void k_rank_count(const float *__restrict__ P, int64_t n_p,
+                                                           const float *__restrict__ Q, int64_t N, int d,
+                                                           int pw, int64_t tiles,
+                                                           const uint32_t *__restrict__ K,
+                                                           uint16_t *__restrict__ R16)
 {
+    constexpr int LOADS = STILE / (4 * RC_THREADS);  // uint4 loads per thread and tile
+    __shared__ uint32_t tile[TPS][RC_TILE_WORDS];
     const int m = blockIdx.y;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t rank = 0;
-        for (int64_t u = 0; u < tiles; ++u) rank += part[((size_t)u * d + m) * tiles * STILE + i];
-        put_rank(R16, i, pw, m, rank);
+    const int tid = threadIdx.x;
+    const int64_t first = (int64_t)blockIdx.x * (RC_THREADS * KPT);
+    uint32_t key[KPT], rank[KPT];
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int64_t i = first + tid + r * RC_THREADS;
+        key[r] = i < N ? order_key(point_value(P, n_p, Q, i, d, m)) : 0u;
+        rank[r] = 0;
+    }
+    const uint4 *src = reinterpret_cast<const uint4 *>(K + (size_t)m * tiles * STILE);
+    // A group's slots past the last tile hold a copy of the last tile, whose
+    // counts are dropped: no branch separates the searches, so that their
+    // chains interleave.
+    uint4 nxt[TPS][LOADS];
+    auto load = [&](int64_t u0) {
+#pragma unroll
+        for (int s = 0; s < TPS; ++s) {
+            const int64_t u = u0 + s < tiles ? u0 + s : tiles - 1;
+#pragma unroll
+            for (int c = 0; c < LOADS; ++c) nxt[s][c] = src[u * (STILE / 4) + tid + c * RC_THREADS];
+        }
+    };
+    load(0);
+    for (int64_t u0 = 0; u0 < tiles; u0 += TPS) {
+        __syncthreads();  // the previous group's searches are done
+#pragma unroll
+        for (int s = 0; s < TPS; ++s)
+#pragma unroll
+            for (int c = 0; c < LOADS; ++c) {
+                const int e = skew(4 * (tid + c * RC_THREADS));  // 4 entries in one 64-entry row
+                tile[s][e] = nxt[s][c].x;
+                tile[s][e + 1] = nxt[s][c].y;
+                tile[s][e + 2] = nxt[s][c].z;
+                tile[s][e + 3] = nxt[s][c].w;
+            }
+        __syncthreads();
+        if (u0 + TPS < tiles) load(u0 + TPS);
+        int cnt[TPS][KPT];
+#pragma unroll
+        for (int s = 0; s < TPS; ++s)
+#pragma unroll
+            for (int r = 0; r < KPT; ++r) cnt[s][r] = count_below(tile[s], key[r]);
+#pragma unroll
+        for (int s = 0; s < TPS; ++s)
+#pragma unroll
+            for (int r = 0; r < KPT; ++r) rank[r] += u0 + s < tiles ? (uint32_t)cnt[s][r] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int64_t i = first + tid + r * RC_THREADS;
+        if (i >= N) continue;
+        put_rank(R16, i, pw, m, rank[r]);
         if (m == 0)
             for (int mm = d; mm < 2 * pw; ++mm) R16[(i * pw) * 2 + mm] = 0;
     }
 }
+
+#ifndef DDKS_RC_KPT
+#define DDKS_RC_KPT 1
+#endif
+#ifndef DDKS_RC_TPS
+#define DDKS_RC_TPS 2
+#endif
+static constexpr int RC_KPT = DDKS_RC_KPT, RC_TPS = DDKS_RC_TPS;
+
 
 // ------------------------------------------------------------ N > 65536
 
@@ -497,9 +689,7 @@ size_t rank16_scratch_bytes(int64_t N, int d)
     const int64_t tiles = tiles_of(N);
     if (N <= 65536) {
         const int64_t st = stiles_of(N);
-        size_t k = (size_t)d * st * STILE * sizeof(uint32_t);
-        size_t part = (size_t)st * d * st * STILE * sizeof(uint16_t);
-        return k + part + 256;
+        return (size_t)d * st * STILE * sizeof(uint32_t) + 256;
     }
     size_t a = (size_t)d * tiles * TILE * sizeof(uint64_t);
     size_t s = (size_t)d * N * sizeof(uint64_t);
@@ -574,16 +764,12 @@ hipError_t launch_rank16_pq(const float *P, int64_t n_p, const float *Q, int64_t
     const int pw = point_words(PATH_R16, d);
     const int64_t tiles = stiles_of(N);
     uint32_t *Kt = (uint32_t *)scratch;
-    uint16_t *part = (uint16_t *)(Kt + (size_t)d * tiles * STILE);
     hipError_t e;
     hipLaunchKernelGGL(k_rank_sort32, dim3((unsigned)tiles, d), dim3(S32_THREADS), 0, st, P, n_p, Q, N, d,
                        tiles, Kt, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rank_count, dim3((unsigned)tiles, d, (unsigned)tiles), dim3(S32_THREADS), 0, st, P,
-                       n_p, Q, N, d, tiles, Kt, part);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const unsigned sblocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_rank_sum, dim3(sblocks, d), dim3(256), 0, st, part, N, d, pw, tiles, (uint16_t *)R);
+    hipLaunchKernelGGL((k_rank_count<RC_KPT, RC_TPS>), dim3((unsigned)(tiles * rc_parts(RC_KPT)), d),
+                       dim3(RC_THREADS), 0, st, P, n_p, Q, N, d, pw, tiles, Kt, (uint16_t *)R);
     return hipGetLastError();
 }
 

@@ -519,6 +519,7 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
         }
     }
     if (const char *e = getenv("DDKS_FORCE_PACKED_WAVES")) c->force_packed_waves = atoi(e);
+    if (const char *e = getenv("DDKS_SERVE_HOLD")) c->serve_hold = atoll(e);
     if (const char *e = getenv("DDKS_FORCE_VSWEEP")) {
         int w = 0, ch = 0, g = 1;
         if (sscanf(e, "%d:%d:%d", &w, &ch, &g) >= 2) {

@@ -42,6 +42,7 @@ struct ddks_ctx {
     int64_t force_chunks = 0;  // test override (DDKS_FORCE_CHUNKS)
     int force_perm_waves = 0, force_perm_pb = 0;  // test override (DDKS_FORCE_PERM="waves:pb")
     int force_packed_waves = 0;  // test override (DDKS_FORCE_PACKED_WAVES)
+    int64_t serve_hold = 0;      // test override (DDKS_SERVE_HOLD): first launch waits for this many requests
     ddks::VSweepPlan force_vsweep{0, 1, 1};  // test override (DDKS_FORCE_VSWEEP="waves:chunks[:groups]")
     int fault_site = 0;        // test override (DDKS_FAULT_INJECT), see fault_injected
     std::atomic<int64_t> fault_countdown{0};

@@ -485,6 +485,9 @@ void Serve::loop()
     // cap on work items per launch, so that a flood of requests still yields
     // several launches that overlap instead of one long one
     const size_t max_items = 1u << 16;
+    // test override: the first launch waits until this many requests are held
+    // (or the context closes), so that a burst lands in one batch
+    int64_t hold = c->serve_hold;
     std::unique_lock<std::mutex> lk(m);
     while (true) {
         bool progress = false;
@@ -517,7 +520,8 @@ void Serve::loop()
             ready.push_back(r);
             pending.pop_front();
         }
-        if (!ready.empty() && !failed) {
+        if (hold > 0 && (stop || (int64_t)(ready.size() + pending.size()) >= hold)) hold = 0;
+        if (!ready.empty() && !failed && hold <= 0) {
             Slot *free_slot = nullptr;
             for (Slot &s : slots)
                 if (!s.busy) {

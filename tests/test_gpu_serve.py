@@ -30,6 +30,22 @@ def _mix(seed, count, nmax=3000):
     return reqs
 
 
+def _ctx_env(env, **kw):
+    """A context created with the environment overrides in env (restored after)."""
+    import os
+    from paper_2106_13706_amd import native
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return native.Context(**kw)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
 def _key(r):
     return (r.num, r.den, r.argmax_origin, r.argmax_orthant)
 
@@ -295,9 +311,12 @@ def test_packed_waves_tuned_and_cached(oracle_mod, tmp_path):
         reqs.append((g.standard_normal((n_p, 3)).astype(np.float32),
                      (g.standard_normal((n_q, 3)) + 0.1).astype(np.float32)))
     cache = tmp_path / "tune.txt"
-    with native.Context(tune_cache=str(cache)) as ctx:
+    # the first launch waits for the whole burst, so that one packed run holds
+    # enough work to be tuned (whatever the pace of the submissions)
+    with _ctx_env({"DDKS_SERVE_HOLD": str(len(reqs))}, tune_cache=str(cache)) as ctx:
         tickets = [ctx.serve_submit(P, Q) for P, Q in reqs]
         got = [ctx.serve_poll(t) for t in tickets]
+        assert ctx.serve_stats()["launches"] >= 1
     for (P, Q), r in zip(reqs[::10], got[::10]):
         o = oracle_mod.distance(P, Q, threads=THREADS)
         assert _key(r) == (o.num, o.den, o.argmax_origin, o.argmax_orthant)
