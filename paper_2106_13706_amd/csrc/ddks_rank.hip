@@ -58,12 +58,15 @@ __device__ __forceinline__ float point_value(const float *__restrict__ P, int64_
 }
 
 // Tiles of the N <= 65536 path: 2^LOG_STILE keys, sorted by one block of
-// 256 threads holding SKPT keys each.
+// S32_THREADS threads holding SKPT keys each (4096 keys, 512 threads x 8:
+// two waves per SIMD hide the exchange latencies that one wave of 16 keys
+// per thread left exposed, 10.6 against 12.2 us at 40000 points x 4
+// dimensions; 2048-key tiles sorted in 7.0 us but made the count slower).
 #ifndef DDKS_STILE_LOG
 #define DDKS_STILE_LOG 12
 #endif
 #ifndef DDKS_SORT_KPT
-#define DDKS_SORT_KPT 16
+#define DDKS_SORT_KPT 8
 #endif
 static constexpr int LOG_STILE = DDKS_STILE_LOG;
 static constexpr int STILE = 1 << LOG_STILE;
@@ -137,7 +140,7 @@ __device__ __forceinline__ void cmpx(uint32_t &lo, uint32_t &hi)
 }
 
 // A stage whose partner thread is tid ^ M, in another wave (M >= 64), with
-// the partner's registers reversed when FLIP; buf holds 256 x 4 uint4.
+// the partner's registers reversed when FLIP; buf holds S32_THREADS x SKPT words.
 template <int M, bool FLIP>
 __device__ __forceinline__ void sort_cross_wave(uint32_t (&v)[SKPT], int tid, uint4 *buf)
 {
@@ -246,7 +249,7 @@ __device__ __forceinline__ void sort_phases(uint32_t (&v)[SKPT], int lane, int t
 
 // Sorts tile blockIdx.x of dimension blockIdx.y: K[m][t][0..STILE) = the order
 // keys of points t*STILE .. t*STILE+STILE-1, ascending (0xffffffff past N).
-// Thread tid reads points t*STILE + tid + 256 r (coalesced; a sort does not
+// Thread tid reads points t*STILE + tid + S32_THREADS r (coalesced; a sort does not
 // care where its inputs start).  Values are read from P (points 0 .. n_p - 1)
 // then Q; flags (nullable): bit 0 is set if a value is NaN or infinite.
 __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__restrict__ P, int64_t n_p,

@@ -171,7 +171,10 @@ def _points(x, d=None):
             raise ValueError("torch inputs must be contiguous float32")
         if not x.is_cuda:
             return _points(x.numpy(), d)
-        t = x.reshape(x.shape[0], -1) if x.dim() > 1 else x.reshape(-1, 1)
+        shape = x.shape
+        if len(shape) == 2:  # the usual case, without building a reshaped view
+            return x.data_ptr(), shape[0], shape[1], x, True
+        t = x.reshape(shape[0], -1) if len(shape) > 1 else x.reshape(-1, 1)
         return t.data_ptr(), t.shape[0], t.shape[1], t, True
     a = np.ascontiguousarray(x, dtype=np.float32)
     if a.ndim == 1:
