@@ -357,7 +357,28 @@ def bench_batch(ctx, torch, dev, reps=5):
             "sequential_plain_calls_tests_per_s": 1.0 / seq_sec,
             "speedup_vs_sequential": (B / sec) * seq_sec,
             "p_value": summ["p_value"], "n_ge": summ["n_ge"], "observed_D": obs.D,
-            "observed_S_binomial": S["binomial"], "observed_S_poisson": S["poisson"]}
+            "observed_S_binomial": S["binomial"], "observed_S_poisson": S["poisson"],
+            "lds_roofline": _perm_lds_roofline(B, n, gpu_ms)}
+
+
+# Lane-minor ds_add_u64 on random bins: 6.2 CU clocks per wave64 instruction
+# (paper_2106_13706_amd/probes/lds_atomic_rate, profiles/lds_atomic_rate.md);
+# each 64-bit lane-atomic of the permutation kernel carries four 16-bit counters.
+LDS_U64_CLOCKS_PER_WAVE_INST = 6.2
+PERM_LDS_PEAK = 256 * 2.4e9 * 64 / LDS_U64_CLOCKS_PER_WAVE_INST * 4  # counter updates/s
+
+
+def _perm_lds_roofline(B, n, gpu_ms):
+    """The permutation batch against the LDS atomic peak of its counter
+    update: B n^2 relabelling-origin-point updates over the whole batch's
+    device time (k_perm plus the observed sweep and the label preparation, so
+    the fraction is a lower bound for k_perm itself)."""
+    achieved = B * n * n / (gpu_ms * 1e-3) if gpu_ms > 0 else None
+    return {"bound": "lds", "achieved": achieved, "peak": PERM_LDS_PEAK, "unit": "counter updates/s",
+            "frac": achieved / PERM_LDS_PEAK if achieved else None,
+            "peak_source": "lane-minor ds_add_u64 at 6.2 CU clocks per wave instruction x 4 counters "
+                           "(profiles/lds_atomic_rate.md)",
+            "time_source": "HIP events around each whole batch (graph replay)"}
 
 
 def bench_serving(ctx_factory, n_requests, seed_rate=None):

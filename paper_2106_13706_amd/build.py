@@ -52,6 +52,27 @@ def _compile(src, force, verbose):
     return obj
 
 
+PROBES = os.path.join(HERE, "probes")
+
+
+def build_probes(verbose: bool = False) -> list:
+    """Compiles each probes/*.hip (a standalone measurement program, not part
+    of the library) into an executable beside it."""
+    out = []
+    for src in sorted(glob.glob(os.path.join(PROBES, "*.hip"))):
+        exe = src[:-len(".hip")]
+        cmd = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Wall",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", src, "-o", exe + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}{r.stderr}")
+        os.replace(exe + ".tmp", exe)
+        out.append(exe)
+    return out
+
+
 def build(force: bool = True, verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = _sources()
@@ -65,6 +86,7 @@ def build(force: bool = True, verbose: bool = False, jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(OUT + ".tmp", OUT)
+    build_probes(verbose)
     return OUT
 
 
