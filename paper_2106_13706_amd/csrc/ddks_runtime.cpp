@@ -551,6 +551,7 @@ int ddks_create(const ddks_options *opt, ddks_ctx **out)
     if (!st) st = hip_check(c, hipMemset(c->rank_ctl_dev, 0, RANK_CTL_WORDS * sizeof(uint32_t)), "hipMemset");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->result_host, sizeof(ResultDev), 0), "hipHostMalloc");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->rank_distinct_host, 16 * sizeof(uint32_t), 0), "hipHostMalloc");
+    if (!st) st = hip_check(c, hipHostMalloc((void **)&c->count_host, 64, hipHostMallocCoherent), "hipHostMalloc");
     if (!st) st = hip_check(c, hipHostMalloc((void **)&c->sig_host, 2 * sizeof(double), 0), "hipHostMalloc");
     if (!st) c->used += sizeof(ResultDev) + 2 * sizeof(uint32_t) + 16 * sizeof(uint32_t);
     c->profile = (o.flags & DDKS_PROFILE_KERNELS) != 0;
@@ -582,10 +583,13 @@ int ddks_destroy(ddks_ctx *c)
     if (c->result_host) (void)hipHostFree(c->result_host);
     if (c->done_host) (void)hipHostFree(c->done_host);
     if (c->rank_distinct_host) (void)hipHostFree(c->rank_distinct_host);
+    if (c->count_host) (void)hipHostFree(c->count_host);
     if (c->sig_host) (void)hipHostFree(c->sig_host);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->dist_exec) (void)hipGraphExecDestroy(c->dist_exec);
+    if (c->vdks_front_exec) (void)hipGraphExecDestroy(c->vdks_front_exec);
+    if (c->vdks_back_exec) (void)hipGraphExecDestroy(c->vdks_back_exec);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     tuner_destroy(c->tuner);
     delete c;

@@ -61,11 +61,18 @@ struct ddks_ctx {
     hipGraphExec_t dist_exec = nullptr;
     std::vector<uint64_t> dist_key;
     bool dist_graphs = true;  // cleared for good if a capture ever fails
+    // vdKS with device-resident inputs: the launches before the host read of
+    // the filled-voxel count, and those after it, each captured and replayed
+    // while their key matches (the second key includes the count and shape)
+    hipGraphExec_t vdks_front_exec = nullptr, vdks_back_exec = nullptr;
+    std::vector<uint64_t> vdks_front_key, vdks_back_key;
+    bool vdks_graphs = true;  // cleared for good if a capture ever fails
     ddks::ResultDev *result_dev = nullptr;  // device
     ddks::ResultDev *result_host = nullptr; // pinned
     uint32_t *flags_dev = nullptr;          // device, cleared by the reduction
     uint32_t *done_host = nullptr;          // pinned, coherent: 1 once a call's result is in result_host
     uint32_t *rank_distinct_host = nullptr; // pinned
+    uint32_t *count_host = nullptr;         // pinned, coherent: vdKS's filled-voxel count, polled by the host
     double *sig_host = nullptr;             // pinned, 2 doubles
     uint32_t *rank_ctl_dev = nullptr;
 

@@ -70,6 +70,66 @@ int tune_vsweep(ddks_ctx *c, const uint64_t *keys, const uint64_t *inc, int64_t 
     return DDKS_OK;
 }
 
+constexpr uint32_t COUNT_PENDING = 0xffffffffu;  // above any count (N < 2^30)
+
+// Waits until the filled-voxel count lands in count_host: polls it, checks
+// the stream every 1024 polls (a failed stream ends the wait) and hands a long
+// wait over to hipStreamSynchronize, so that it does not hold a host core.
+int wait_count(ddks_ctx *c, hipStream_t s)
+{
+    for (uint32_t spin = 1; spin <= (1u << 16); ++spin) {
+        if (__atomic_load_n(c->count_host, __ATOMIC_ACQUIRE) != COUNT_PENDING) return DDKS_OK;
+        if ((spin & 1023u) == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return hip_check(c, q, "stream query");
+        }
+        __builtin_ia32_pause();
+    }
+    int st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    if (!st && __atomic_load_n(c->count_host, __ATOMIC_ACQUIRE) == COUNT_PENDING)
+        st = fail(c, DDKS_E_DEVICE, "the stream finished without the voxel count");
+    return st;
+}
+
+// Launches enqueue's work on s: by replaying the graph in *exec when *key_have
+// equals key, else by capturing enqueue into a new graph first.  A failed
+// capture falls back to an eager run and to eager runs for good (launches
+// refused inside a failed capture are not device errors, so they do not
+// poison the context; a real fault shows again on the eager path).
+template <typename F>
+int replay_or_capture(ddks_ctx *c, hipGraphExec_t *exec, std::vector<uint64_t> *key_have,
+                      const std::vector<uint64_t> &key, hipStream_t s, F enqueue)
+{
+    if (!c->vdks_graphs) return enqueue();
+    if (*exec && *key_have != key) {
+        (void)hipGraphExecDestroy(*exec);
+        *exec = nullptr;
+    }
+    if (!*exec) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        int st = DDKS_OK;
+        if (ok) {
+            st = enqueue();
+            ok = hipStreamEndCapture(s, &g) == hipSuccess && st == DDKS_OK;
+        }
+        ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+            (void)hipGetLastError();
+            if (ex) (void)hipGraphExecDestroy(ex);
+            c->vdks_graphs = false;
+            c->poisoned = false;
+            return enqueue();
+        }
+        *exec = ex;
+        *key_have = key;
+    }
+    return hip_check(c, hipGraphLaunch(*exec, s), "graph launch");
+}
+
 }  // namespace
 
 extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int64_t n_q,
@@ -122,15 +182,27 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
         srcP = Z;
         srcQ = Z + n_p * d;
     }
-    st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
-    if (!st) st = hip_check(c, launch_vox_front(Z, N, n_p, d, V, mm, part, tab_key, tab_cnt, slots, counter, keys,
-                                                inc, s), "voxel launch");
-    // the number of filled voxels sizes the sweep
-    if (!st) st = hip_check(c, hipMemcpyAsync(c->rank_distinct_host, counter, sizeof(uint32_t),
-                                              hipMemcpyDeviceToHost, s), "D2H voxel count");
-    if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
+    auto front = [&]() {
+        int r = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
+        if (!r) r = hip_check(c, launch_vox_front(Z, N, n_p, d, V, mm, part, tab_key, tab_cnt, slots, counter, keys,
+                                                 inc, s), "voxel launch");
+        return r;
+    };
+    // with device-resident inputs the launches up to the voxel count form one
+    // captured graph, replayed while (inputs, sizes, buffers, stream) match
+    const std::vector<uint64_t> fkey = {(uint64_t)(uintptr_t)P, (uint64_t)(uintptr_t)Q, (uint64_t)n_p,
+                                        (uint64_t)n_q, (uint64_t)d, (uint64_t)V, c->buf_gen,
+                                        (uint64_t)(uintptr_t)s};
+    st = dev ? replay_or_capture(c, &c->vdks_front_exec, &c->vdks_front_key, fkey, s, front) : front();
+    // the number of filled voxels sizes the sweep: copied into a coherent
+    // pinned word that the host polls (it lands well before the runtime would
+    // report the stream idle), with a sentinel no count can take
+    __atomic_store_n(c->count_host, COUNT_PENDING, __ATOMIC_RELEASE);
+    if (!st) st = hip_check(c, hipMemcpyAsync(c->count_host, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                            "D2H voxel count");
+    if (!st) st = wait_count(c, s);
     if (st) return st;
-    const int64_t M = *c->rank_distinct_host;
+    const int64_t M = __atomic_load_n(c->count_host, __ATOMIC_ACQUIRE);
     if (M < 1 || M > N) return fail(c, DDKS_E_DEVICE, "voxel compaction produced an invalid count");
     VSweepPlan plan = vsweep_default_plan(M);
     if (c->force_vsweep.waves) {
@@ -149,9 +221,23 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     }
     const size_t pb = vsweep_partial_bytes(M, d, plan);
     if (pb && (st = ensure(c, c->partial, pb, "voxel partial counts"))) return st;
-    st = hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, plan, (uint32_t *)c->zr.ptr, fit,
-                                    c->block_best.ptr, pb ? c->partial.ptr : nullptr, c->flags_dev, c->result_host, s),
-                   "voxel sweep launch");
+    auto back = [&]() {
+        return hip_check(c, launch_vsweep(keys, inc, M, d, V, n_p, n_q, plan, (uint32_t *)c->zr.ptr, fit,
+                                          c->block_best.ptr, pb ? c->partial.ptr : nullptr, c->flags_dev,
+                                          c->result_host, s),
+                         "voxel sweep launch");
+    };
+    if (dev) {
+        // the launches after the count: a second graph, keyed also by the
+        // count and the shape (a partial-count buffer grown above bumps buf_gen)
+        std::vector<uint64_t> bkey = fkey;
+        bkey[6] = c->buf_gen;
+        bkey.insert(bkey.end(), {(uint64_t)M, (uint64_t)plan.waves, (uint64_t)plan.chunks,
+                                 (uint64_t)plan.per_block});
+        st = replay_or_capture(c, &c->vdks_back_exec, &c->vdks_back_key, bkey, s, back);
+    } else {
+        st = back();
+    }
     if (!st) st = hip_check(c, hipStreamSynchronize(s), "stream synchronize");
     if (st) return st;
     const ResultDev r = *c->result_host;
