@@ -34,9 +34,21 @@ extern "C" int ddks_rdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
         srcQ = Z + n_p * d;
     }
     unsigned long long *cn = (unsigned long long *)c->nums.ptr;
-    st = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
-    if (!st) st = hip_check(c, launch_rdks(Z, N, n_p, d, c->rank_scratch.ptr, cn, c->flags_dev, c->result_host, s),
-                            "rdks launch");
+    auto enqueue = [&]() {
+        int r = hip_check(c, launch_ingest_f32(srcP, n_p, srcQ, n_q, d, Z, c->flags_dev, s), "ingest launch");
+        if (!r) r = hip_check(c, launch_rdks(Z, N, n_p, d, c->rank_scratch.ptr, cn, c->flags_dev, c->result_host, s),
+                              "rdks launch");
+        return r;
+    };
+    if (dev) {
+        // device-resident inputs: the call's launches form one captured graph,
+        // replayed while (inputs, sizes, buffers, stream) match
+        const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)P, (uint64_t)(uintptr_t)Q, (uint64_t)n_p,
+                                           (uint64_t)n_q, (uint64_t)d, c->buf_gen, (uint64_t)(uintptr_t)s};
+        st = replay_or_capture(c, &c->rdks_graphs, &c->rdks_exec, &c->rdks_key, key, s, enqueue);
+    } else {
+        st = enqueue();
+    }
     if (!st && corner_nums)
         st = hip_check(c, hipMemcpyAsync(corner_nums, cn, (size_t)C * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
                        "D2H corner numerators");

@@ -590,6 +590,7 @@ int ddks_destroy(ddks_ctx *c)
     if (c->dist_exec) (void)hipGraphExecDestroy(c->dist_exec);
     if (c->vdks_front_exec) (void)hipGraphExecDestroy(c->vdks_front_exec);
     if (c->vdks_back_exec) (void)hipGraphExecDestroy(c->vdks_back_exec);
+    if (c->rdks_exec) (void)hipGraphExecDestroy(c->rdks_exec);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     tuner_destroy(c->tuner);
     delete c;

@@ -67,6 +67,10 @@ struct ddks_ctx {
     hipGraphExec_t vdks_front_exec = nullptr, vdks_back_exec = nullptr;
     std::vector<uint64_t> vdks_front_key, vdks_back_key;
     bool vdks_graphs = true;  // cleared for good if a capture ever fails
+    // rdKS with device-resident inputs: the whole call, same scheme
+    hipGraphExec_t rdks_exec = nullptr;
+    std::vector<uint64_t> rdks_key;
+    bool rdks_graphs = true;
     ddks::ResultDev *result_dev = nullptr;  // device
     ddks::ResultDev *result_host = nullptr; // pinned
     uint32_t *flags_dev = nullptr;          // device, cleared by the reduction
@@ -185,5 +189,44 @@ void tuner_store_packed(Tuner *t, int path, int d, int64_t n, int waves);
 // vdKS's weighted sweep: the tuned (waves, chunks) for (d, log2 of the filled voxels).
 bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, VSweepPlan *plan);
 void tuner_store_vsweep(Tuner *t, int d, int64_t M, const VSweepPlan &plan);
+
+// Launches enqueue()'s work on s: by replaying the graph in *exec when
+// *key_have equals key, else by capturing enqueue() into a new graph first.
+// A failed capture falls back to an eager run, and to eager runs for good
+// (*enabled cleared; launches refused inside a failed capture are not device
+// errors, so they do not poison the context: a real fault shows again on the
+// eager path).
+template <typename F>
+int replay_or_capture(ddks_ctx *c, bool *enabled, hipGraphExec_t *exec, std::vector<uint64_t> *key_have,
+                      const std::vector<uint64_t> &key, hipStream_t s, F enqueue)
+{
+    if (!*enabled) return enqueue();
+    if (*exec && *key_have != key) {
+        (void)hipGraphExecDestroy(*exec);
+        *exec = nullptr;
+    }
+    if (!*exec) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        int st = DDKS_OK;
+        if (ok) {
+            st = enqueue();
+            ok = hipStreamEndCapture(s, &g) == hipSuccess && st == DDKS_OK;
+        }
+        ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+            (void)hipGetLastError();
+            if (ex) (void)hipGraphExecDestroy(ex);
+            *enabled = false;
+            c->poisoned = false;
+            return enqueue();
+        }
+        *exec = ex;
+        *key_have = key;
+    }
+    return hip_check(c, hipGraphLaunch(*exec, s), "graph launch");
+}
 
 }  // namespace ddks

@@ -92,44 +92,6 @@ int wait_count(ddks_ctx *c, hipStream_t s)
     return st;
 }
 
-// Launches enqueue's work on s: by replaying the graph in *exec when *key_have
-// equals key, else by capturing enqueue into a new graph first.  A failed
-// capture falls back to an eager run and to eager runs for good (launches
-// refused inside a failed capture are not device errors, so they do not
-// poison the context; a real fault shows again on the eager path).
-template <typename F>
-int replay_or_capture(ddks_ctx *c, hipGraphExec_t *exec, std::vector<uint64_t> *key_have,
-                      const std::vector<uint64_t> &key, hipStream_t s, F enqueue)
-{
-    if (!c->vdks_graphs) return enqueue();
-    if (*exec && *key_have != key) {
-        (void)hipGraphExecDestroy(*exec);
-        *exec = nullptr;
-    }
-    if (!*exec) {
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ex = nullptr;
-        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        int st = DDKS_OK;
-        if (ok) {
-            st = enqueue();
-            ok = hipStreamEndCapture(s, &g) == hipSuccess && st == DDKS_OK;
-        }
-        ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
-        if (g) (void)hipGraphDestroy(g);
-        if (!ok) {
-            (void)hipGetLastError();
-            if (ex) (void)hipGraphExecDestroy(ex);
-            c->vdks_graphs = false;
-            c->poisoned = false;
-            return enqueue();
-        }
-        *exec = ex;
-        *key_have = key;
-    }
-    return hip_check(c, hipGraphLaunch(*exec, s), "graph launch");
-}
-
 }  // namespace
 
 extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *Q, int64_t n_q,
@@ -193,7 +155,7 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
     const std::vector<uint64_t> fkey = {(uint64_t)(uintptr_t)P, (uint64_t)(uintptr_t)Q, (uint64_t)n_p,
                                         (uint64_t)n_q, (uint64_t)d, (uint64_t)V, c->buf_gen,
                                         (uint64_t)(uintptr_t)s};
-    st = dev ? replay_or_capture(c, &c->vdks_front_exec, &c->vdks_front_key, fkey, s, front) : front();
+    st = dev ? replay_or_capture(c, &c->vdks_graphs, &c->vdks_front_exec, &c->vdks_front_key, fkey, s, front) : front();
     // the number of filled voxels sizes the sweep: copied into a coherent
     // pinned word that the host polls (it lands well before the runtime would
     // report the stream idle), with a sentinel no count can take
@@ -234,7 +196,7 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
         bkey[6] = c->buf_gen;
         bkey.insert(bkey.end(), {(uint64_t)M, (uint64_t)plan.waves, (uint64_t)plan.chunks,
                                  (uint64_t)plan.per_block});
-        st = replay_or_capture(c, &c->vdks_back_exec, &c->vdks_back_key, bkey, s, back);
+        st = replay_or_capture(c, &c->vdks_graphs, &c->vdks_back_exec, &c->vdks_back_key, bkey, s, back);
     } else {
         st = back();
     }
