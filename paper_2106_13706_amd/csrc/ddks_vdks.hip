@@ -553,9 +553,10 @@ __host__ __device__ constexpr size_t vsweep_lds(int d, int waves, int H)
 // (c_P | c_Q << 16).  Heavier chunks add one sample at a time: with several
 // chunks (mode VFIT_PER_CHUNK, where fit[chunk] is set) each sample's pass
 // goes through the partial sums; a single chunk (mode VFIT_WIDE, G = 1) keeps
-// one histogram per sample.  With Gpart null the block scores its origins
-// itself; otherwise it adds its non-zero counts into the zeroed 64-bit
-// Gpart[group][BINS][64] (c_P | c_Q << 32) and k_vscore scores them.
+// one histogram per sample.  With part null the block scores its origins
+// itself; otherwise it stores its counts as its chunk's rows of the partial
+// counts (plain stores: every entry of every row is written) and k_vscore
+// sums the chunks and scores them.
 template <int D, int W, int G>
 __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ RV,
                                                    const uint32_t *__restrict__ W32,
@@ -563,7 +564,7 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
                                                    const uint64_t *__restrict__ keys, int64_t M,
                                                    int64_t n_p, int64_t n_q, int mode,
                                                    const uint32_t *__restrict__ fit,
-                                                   unsigned long long *__restrict__ Gpart, VBest *__restrict__ bb)
+                                                   uint32_t *__restrict__ part, VBest *__restrict__ bb)
 {
     constexpr int S = VLayout<D>::STRIDE;
     constexpr int HB = Geo<D>::BINS * 64;  // bins of one histogram
@@ -611,8 +612,12 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
                 reinterpret_cast<uint64_t *>(h32), keys, M, n_p, n_q, blockIdx.x, bb);
         return;
     }
+    // this chunk's rows of the partial counts: [chunk][group][bin][lane]
+    // words, c_P | c_Q << 16 from a one-pass chunk, else c_P here and c_Q in
+    // the second plane (gridDim.y chunks further on)
+    const size_t plane = (size_t)gridDim.y * groups * HB;
     if (wide) {
-        // one sample per pass, each pass's counts added into the partial sums
+        // one sample per pass, each pass's counts stored in its own plane
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             if (half) {
@@ -627,11 +632,8 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
             for (int j = 0; j < G; ++j) {
                 const int64_t group = (int64_t)blockIdx.x * G + j;
                 if (group >= groups) break;  // block-uniform
-                unsigned long long *g = Gpart + (size_t)group * HB;
-                for (int e = threadIdx.x; e < HB; e += W * 64) {
-                    const uint64_t v = h32[(size_t)j * HB + e];
-                    if (v) atomicAdd(g + e, (unsigned long long)(v << (32 * half)));
-                }
+                uint32_t *g = part + half * plane + ((size_t)blockIdx.y * groups + group) * HB;
+                for (int e = threadIdx.x; e < HB; e += W * 64) g[e] = h32[(size_t)j * HB + e];
             }
         }
         return;
@@ -642,12 +644,9 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
     for (int j = 0; j < G; ++j) {
         const int64_t group = (int64_t)blockIdx.x * G + j;
         if (group >= groups) break;  // block-uniform
-        if (Gpart) {
-            unsigned long long *g = Gpart + (size_t)group * HB;
-            for (int e = threadIdx.x; e < HB; e += W * 64) {
-                const uint32_t v = h32[(size_t)j * HB + e];
-                if (v) atomicAdd(g + e, (unsigned long long)(v & 0xffffu) | ((unsigned long long)(v >> 16) << 32));
-            }
+        if (part) {
+            uint32_t *g = part + ((size_t)blockIdx.y * groups + group) * HB;
+            for (int e = threadIdx.x; e < HB; e += W * 64) g[e] = h32[(size_t)j * HB + e];
         } else {
             // vfinish reads every bin of histogram j before it writes its
             // reduction space over the start of the histograms; the later
@@ -663,31 +662,61 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
     }
 }
 
-// Scores group blockIdx.x from the counts the chunks added into G.
-template <int D, int W>
-__global__ __launch_bounds__(W * 64) void k_vscore(const unsigned long long *__restrict__ G,
+// Scores group blockIdx.x from the chunks' rows of the partial counts
+// (fit non-null: fit[chunk] set for a chunk stored in two planes, else every
+// chunk one-pass).  Each bin's rows of all chunks are loaded together (MC >=
+// chunks rows, clamped to the last chunk past `chunks`, whose repeats are
+// dropped), so a bin costs one memory latency whatever the chunk count; the
+// second plane is read only when some chunk of the launch was stored in two.
+template <int D, int W, int MC>
+__global__ __launch_bounds__(W * 64) void k_vscore(const uint32_t *__restrict__ part, int chunks,
+                                                   const uint32_t *__restrict__ fit,
                                                    const uint64_t *__restrict__ keys, int64_t M,
                                                    int64_t n_p, int64_t n_q, VBest *__restrict__ bb)
 {
     __shared__ uint64_t red[W * 64 * 12 / 8];
     constexpr int BINS = Geo<D>::BINS;
+    constexpr int HB = BINS * 64;
     const int lane = threadIdx.x & 63;
-    const unsigned long long *g = G + (size_t)blockIdx.x * BINS * 64 + lane;
+    const int64_t groups = gridDim.x;
+    const size_t row = (size_t)groups * HB;  // one chunk's rows
+    const size_t plane = (size_t)chunks * row;
+    uint32_t wide = 0;  // chunks stored in two planes
+    if (fit)
+        for (int c = 0; c < chunks; ++c) wide |= (fit[c] != 0u ? 1u : 0u) << c;
+    wide = __builtin_amdgcn_readfirstlane(wide);
+    const uint32_t *g = part + (size_t)blockIdx.x * HB + lane;
     vfinish<D, W>(
         [&](int j, uint64_t &cp, uint64_t &cq) {
-            const uint64_t v = g[(size_t)j * 64];
-            cp = (uint32_t)v;
-            cq = v >> 32;
+            uint32_t v[MC];
+#pragma unroll
+            for (int c = 0; c < MC; ++c) v[c] = g[(size_t)(c < chunks ? c : chunks - 1) * row + (size_t)j * 64];
+            uint32_t sp = 0, sq = 0;
+            if (wide) {
+                uint32_t q[MC];
+#pragma unroll
+                for (int c = 0; c < MC; ++c)
+                    q[c] = g[plane + (size_t)(c < chunks ? c : chunks - 1) * row + (size_t)j * 64];
+#pragma unroll
+                for (int c = 0; c < MC; ++c) {
+                    const bool on = c < chunks, two = (wide >> c) & 1u;
+                    sp += on ? (two ? v[c] : (v[c] & 0xffffu)) : 0u;
+                    sq += on ? (two ? q[c] : (v[c] >> 16)) : 0u;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < MC; ++c) {
+                    const bool on = c < chunks;
+                    sp += on ? (v[c] & 0xffffu) : 0u;
+                    sq += on ? (v[c] >> 16) : 0u;
+                }
+            }
+            cp = sp;
+            cq = sq;
         },
         red, keys, M, n_p, n_q, blockIdx.x, bb);
 }
 
-__global__ void k_vzero(unsigned long long *__restrict__ p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0ull;
-}
 
 __global__ __launch_bounds__(1024) void k_vreduce(const VBest *__restrict__ bb, int64_t n,
                                                   uint32_t *__restrict__ flags,
@@ -822,7 +851,9 @@ bool vsweep_plan_ok(const VSweepPlan &p, int64_t M, int d)
 size_t vsweep_partial_bytes(int64_t M, int d, const VSweepPlan &p)
 {
     if (p.chunks <= 1) return 0;
-    return (size_t)((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint64_t);
+    // two planes of [chunk][group][bin][lane] words (the second for the c_Q
+    // of chunks too heavy for one pass)
+    return 2 * (size_t)p.chunks * (size_t)((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint32_t);
 }
 
 template <int D, int W, int G>
@@ -840,19 +871,24 @@ static hipError_t launch_vsweep_w(const uint64_t *keys, const uint64_t *inc, int
                 (void)hipGetLastError();
         });
     const int64_t groups = (M + 63) / 64;
-    // the partial sums take the chunks' counts; a single chunk scores in the block
+    // the partial counts take the chunks' counts; a single chunk scores in the block
     const bool via_partial = chunks > 1;
-    unsigned long long *Gp = via_partial ? (unsigned long long *)partial : nullptr;
-    if (via_partial) {
-        if (!Gp) return hipErrorInvalidValue;
-        const int64_t n = groups * Geo<D>::BINS * 64;
-        hipLaunchKernelGGL(k_vzero, dim3(grid_for(n)), dim3(256), 0, s, Gp, n);
-    }
+    uint32_t *Pp = via_partial ? (uint32_t *)partial : nullptr;
+    if (via_partial && !Pp) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_vsweep<D, W, G>), dim3((unsigned)((groups + G - 1) / G), (unsigned)chunks), dim3(W * 64),
-                       lds, s, RV, W32, inc, keys, M, n_p, n_q, mode, fit, Gp, (VBest *)bb);
-    if (via_partial)
-        hipLaunchKernelGGL((k_vscore<D, W>), dim3((unsigned)groups), dim3(W * 64), 0, s, Gp, keys, M, n_p, n_q,
-                           (VBest *)bb);
+                       lds, s, RV, W32, inc, keys, M, n_p, n_q, mode, fit, Pp, (VBest *)bb);
+    if (via_partial) {
+        const uint32_t *f = mode == VFIT_PER_CHUNK ? fit : nullptr;
+        if (chunks <= 4)
+            hipLaunchKernelGGL((k_vscore<D, W, 4>), dim3((unsigned)groups), dim3(W * 64), 0, s, (const uint32_t *)Pp,
+                               chunks, f, keys, M, n_p, n_q, (VBest *)bb);
+        else if (chunks <= 8)
+            hipLaunchKernelGGL((k_vscore<D, W, 8>), dim3((unsigned)groups), dim3(W * 64), 0, s, (const uint32_t *)Pp,
+                               chunks, f, keys, M, n_p, n_q, (VBest *)bb);
+        else
+            hipLaunchKernelGGL((k_vscore<D, W, VSWEEP_MAX_CHUNKS>), dim3((unsigned)groups), dim3(W * 64), 0, s,
+                               (const uint32_t *)Pp, chunks, f, keys, M, n_p, n_q, (VBest *)bb);
+    }
     return hipGetLastError();
 }
 
