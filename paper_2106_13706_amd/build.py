@@ -3,7 +3,11 @@
 Every HIP/C++ source under csrc/ is compiled for gfx950 only, with packed
 FP32 instructions disabled, then linked into one shared library next to
 this file.  Objects go to csrc/_build/ and are rebuilt when their source or
-any header changed.
+any header changed.  The same sources are also compiled with
+AddressSanitizer and UndefinedBehaviorSanitizer on their host code (the
+device code as usual) into csrc/_build_hostsan/ and linked with the serving
+stress driver tests/native/serve_stress.cpp into tests/native/serve_stress,
+which a GPU test runs.
 """
 import glob
 import os
@@ -32,13 +36,22 @@ def _headers():
     return glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
 
 
-def _compile(src, force, verbose):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+# host-side sanitizers only: each -fsanitize= goes to the host compilation
+HOST_SANITIZE = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined -Xarch_host -fno-omit-frame-pointer".split()
+BUILD_SAN = os.path.join(CSRC, "_build_hostsan")
+STRESS_SRC = os.path.join(ROOT, "tests", "native", "serve_stress.cpp")
+STRESS_EXE = os.path.join(ROOT, "tests", "native", "serve_stress")
+
+
+def _compile(src, force, verbose, flags=None, outdir=None):
+    flags = FLAGS if flags is None else flags
+    outdir = BUILD if outdir is None else outdir
+    obj = os.path.join(outdir, os.path.basename(src) + ".o")
     newest = max([os.path.getmtime(src)] + [os.path.getmtime(h) for h in _headers()])
     if not force and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
         return obj
     lang = ["-x", "hip"]
-    cmd = [HIPCC] + FLAGS + lang + ["-c", src, "-o", obj + ".tmp"]
+    cmd = [HIPCC] + flags + lang + ["-c", src, "-o", obj + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -73,6 +86,26 @@ def build_probes(verbose: bool = False) -> list:
     return out
 
 
+def build_stress(force: bool = True, verbose: bool = False, jobs: int = 8) -> str:
+    """tests/native/serve_stress: the serving stress driver linked with the
+    library's sources built with host-side AddressSanitizer and
+    UndefinedBehaviorSanitizer (objects only on the link line: hipcc's
+    "-x hip" would otherwise apply to them)."""
+    os.makedirs(BUILD_SAN, exist_ok=True)
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-gline-tables-only"] + HOST_SANITIZE
+    srcs = _sources() + [STRESS_SRC]
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, force, verbose, flags, BUILD_SAN), srcs))
+    cmd = [HIPCC, f"--offload-arch={ARCH}"] + HOST_SANITIZE + ["-o", STRESS_EXE + ".tmp"] + objs + ["-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link of the stress driver failed:\n" + r.stdout + r.stderr)
+    os.replace(STRESS_EXE + ".tmp", STRESS_EXE)
+    return STRESS_EXE
+
+
 def build(force: bool = True, verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = _sources()
@@ -87,6 +120,7 @@ def build(force: bool = True, verbose: bool = False, jobs: int = 8) -> str:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(OUT + ".tmp", OUT)
     build_probes(verbose)
+    build_stress(force, verbose, jobs)
     return OUT
 
 
