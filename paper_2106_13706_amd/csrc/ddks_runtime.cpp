@@ -131,18 +131,25 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p)
     // 4 waves per block; 8 from d = 4 on, where LDS (the 68 KB pair table at
     // d = 4, 2^d 256-byte bins above) admits few blocks per CU.  At d = 4 the
     // table admits two blocks per CU whatever their size, so from 6144 points
-    // on the blocks take 12 waves: 6 per SIMD, the most that the sweep's 112
-    // SGPRs allow beside a second block (16-wave blocks fit one per CU).
-    p.waves = d >= 4 ? (d == 4 && N >= 6144 ? 12 : 8) : 4;
+    // on the blocks take 12 waves, and from 32768 on 16: two of them fill the
+    // CU's 8 waves per SIMD (the sweep's 80 SGPRs allow that many; 214 us
+    // against 216 with 12 at 2 x 20000).  The d = 6, 2 x 100000 sweep
+    // measured fastest with 16 waves as well (8.17 ms, against 8.28 with 12
+    // and 8.35 with 8).
+    p.waves = d >= 4 ? 8 : 4;
+    if (d == 4 && N >= 6144) p.waves = 12;
+    if ((d == 4 || d == 6) && N >= 32768) p.waves = 16;
     if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 ||
               c->force_waves == 8 || c->force_waves == 12 || c->force_waves == 16))
         p.waves = c->force_waves;
     p.groups = cdiv(N, 64);
     // about 8 waves per SIMD over the 1024 SIMDs (16 at d = 5..7, where more
-    // point chunks measured faster; 2 at d = 8, whose 256-bin partial counts
-    // cost more than the extra waves gain), each sweeping >= 128 points (a
-    // longer chain of point blocks per wave is latency-bound at small N)
-    const int64_t target_waves = d == 8 ? 2048 : (d >= 5 ? 16384 : 8192);
+    // point chunks measured faster, and with 16-wave blocks at d = 4, whose
+    // 2 x 20000 sweep measured 214 us in two chunks against 256 in one; 2 at
+    // d = 8, whose 256-bin partial counts cost more than the extra waves
+    // gain), each sweeping >= 128 points (a longer chain of point blocks per
+    // wave is latency-bound at small N)
+    const int64_t target_waves = d == 8 ? 2048 : (d >= 5 || p.waves == 16 ? 16384 : 8192);
     int64_t chunks = cdiv(target_waves, p.groups * p.waves);
     int64_t max_chunks = std::max<int64_t>(1, N / ((int64_t)p.waves * 128));
     chunks = std::min(chunks, max_chunks);
