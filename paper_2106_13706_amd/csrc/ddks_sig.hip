@@ -91,13 +91,50 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b)
 // log pmf of k successes in m trials at rate lam: binomial (Eq.
 // binomial_probability), or Poisson of mean mu = m lam (Sec. 3's large-sample
 // replacement).  L[k] = log k! for k up to one window past max(n_p, n_q).
+// dk and dm are k and m as doubles (exact: both are far below 2^53), kept
+// by the callers' loops so that no 64-bit conversion runs per term.
 template <int MODEL>
-__device__ __forceinline__ double log_pmf(const double *L, int64_t m, int64_t k, double ll,
-                                          double l1m, double lmu, double mu)
+__device__ __forceinline__ double log_pmf(const double *L, int64_t m, int64_t k, double dm, double dk,
+                                          double ll, double l1m, double lmu, double mu)
 {
-    if constexpr (MODEL == SIG_POISSON) return (double)k * lmu - mu - L[k];
-    return L[m] - L[k] - L[m - k] + (double)k * ll + (double)(m - k) * l1m;
+    if constexpr (MODEL == SIG_POISSON) return dk * lmu - mu - L[k];
+    return L[m] - L[k] - L[m - k] + dk * ll + (dm - dk) * l1m;
 }
+
+// e^x for the log-probabilities x the sums exponentiate, by the table-driven
+// reduction of P. T. P. Tang (ACM TOMS 15(2), 1989): x = (32 m + j) ln2/32 + r
+// with |r| <= ln2/64, e^x = 2^m 2^(j/32) e^r, and e^r - 1 from its Taylor
+// polynomial of degree 6 (remainder below 4e-18 relative at |r| = ln2/64).
+// E[j] = 2^(j/32), j = 0..31, correctly rounded.  ln2/32 is split as
+// EXP_LN2_32_HI (the leading 29 bits of its significand, so n HI is exact for
+// |n| < 2^24) + EXP_LN2_32_LO; both and 32/ln2 come from a 60-digit ln2.
+// Below -746 the result is below half the smallest subnormal: 0.
+static constexpr double EXP_INV_LN2_32 = 0x1.71547652b82fep+5;
+static constexpr double EXP_LN2_32_HI = 0x1.62e42ff000000p-6;
+static constexpr double EXP_LN2_32_LO = -0x1.718432a1b0e26p-40;
+static constexpr double EXP_MIN_ARG = -746.0;
+
+__device__ __forceinline__ double exp_tab(double x, const double *E)
+{
+    const double xc = x > EXP_MIN_ARG ? x : EXP_MIN_ARG;  // keeps n within int range
+    const double n = rint(xc * EXP_INV_LN2_32);
+    const double r = fma(n, -EXP_LN2_32_LO, fma(n, -EXP_LN2_32_HI, xc));
+    const int ni = (int)n;
+    double q = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+    q = fma(r, q, 1.0 / 24.0);
+    q = fma(r, q, 1.0 / 6.0);
+    q = fma(r, q, 0.5);
+    q = fma(r, q, 1.0);
+    const double t = E[ni & 31];
+    const double v = ldexp(fma(t, r * q, t), ni >> 5);  // arithmetic shift: floor(n / 32)
+    return x > EXP_MIN_ARG ? v : 0.0;
+}
+
+// The table E of exp_tab in kernel arguments (filled on the host), copied to
+// each block's LDS.
+struct Exp2Table {
+    double t[32];
+};
 
 __device__ __forceinline__ double wave_scan(double v)  // inclusive, over the 64 lanes
 {
@@ -134,15 +171,16 @@ __host__ __device__ __forceinline__ int64_t window_halfwidth(double sigma, doubl
 // P(X > m), X ~ Poisson(mu), summed directly 64 terms at a time over
 // (m, mu + w] (beyond mu + w the mass is below ~1e-304; L[k] = log k! is
 // tabulated that far), stopping early once the terms stop mattering.
-__device__ double pois_upper_wave(const double *L, int64_t m, double mu, int64_t w)
+__device__ double pois_upper_wave(const double *L, const double *E, int64_t m, double mu, int64_t w)
 {
     const int lane = threadIdx.x & 63;
     const double lmu = log(mu);
     const int64_t kmax = (int64_t)ceil(mu) + w;
     double total = 0.0;
-    for (int64_t k0 = m + 1; k0 <= kmax; k0 += 64) {
+    double dk = (double)(m + 1 + lane);
+    for (int64_t k0 = m + 1; k0 <= kmax; k0 += 64, dk += 64.0) {
         const int64_t k = k0 + lane;
-        const double c = wave_sum(k <= kmax ? exp((double)k * lmu - mu - L[k]) : 0.0);
+        const double c = wave_sum(k <= kmax ? exp_tab(dk * lmu - mu - L[k], E) : 0.0);
         total += c;
         if ((double)k0 > mu && (c == 0.0 || c < total * 1e-18)) break;
     }
@@ -165,22 +203,25 @@ __device__ double block_sum(double v, double *sh)
 // One sample's side of a tail: n trials, pmf parameters, summation window [lo, hi].
 struct SigSide {
     int64_t n, lo, hi;
-    double lmu, mu;
+    double lmu, mu, dn;  // dn = n as a double
 };
 
+// pmf of k (dk = k as a double) on side s.
 template <int MODEL>
-__device__ __forceinline__ double pmf(const double *L, const SigSide &s, int64_t k, double ll, double l1m)
+__device__ __forceinline__ double pmf(const double *L, const double *E, const SigSide &s, int64_t k, double dk,
+                                      double ll, double l1m)
 {
-    return exp(log_pmf<MODEL>(L, s.n, k, ll, l1m, s.lmu, s.mu));
+    return exp_tab(log_pmf<MODEL>(L, s.n, k, s.dn, dk, ll, l1m, s.lmu, s.mu), E);
 }
 
 // sum of the pmf of side s over [k0, k1), one wave.
 template <int MODEL>
-__device__ double range_sum(const double *L, const SigSide &s, int64_t k0, int64_t k1, double ll, double l1m)
+__device__ double range_sum(const double *L, const double *E, const SigSide &s, int64_t k0, int64_t k1, double ll,
+                            double l1m)
 {
     const int lane = threadIdx.x & 63;
-    double v = 0.0;
-    for (int64_t k = k0 + lane; k < k1; k += 64) v += pmf<MODEL>(L, s, k, ll, l1m);
+    double v = 0.0, dk = (double)(k0 + lane);
+    for (int64_t k = k0 + lane; k < k1; k += 64, dk += 64.0) v += pmf<MODEL>(L, E, s, k, dk, ll, l1m);
     return wave_sum(v);
 }
 
@@ -238,8 +279,8 @@ __device__ __forceinline__ void qr_sub(QR &v, const QR &d, int64_t n)
 // spans of the lanes below it (above it, in the descending pass).  An o with
 // no admissible i counts its whole inner mass (inner_tot) once.
 template <int MODEL, int R>
-__device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide &I, int64_t num, double ll,
-                                double l1m)
+__device__ double tail_two_pass(const double *L, const double *E, const SigSide &O, const SigSide &I, int64_t num,
+                                double ll, double l1m)
 {
     const int lane = threadIdx.x & 63;
     constexpr int64_t SPAN = 64 * R;
@@ -257,7 +298,7 @@ __device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide
     {
         const int64_t o0 = O.lo + lane * R;
         QR x = divmod_floor(o0 * I.n - num, O.n), y = divmod_floor(o0 * I.n + num, O.n);
-        double carry = range_sum<MODEL>(L, I, I.lo, tgt_lo(lo_of(divmod_floor(O.lo * I.n - num, O.n))), ll, l1m);
+        double carry = range_sum<MODEL>(L, E, I, I.lo, tgt_lo(lo_of(divmod_floor(O.lo * I.n - num, O.n))), ll, l1m);
         for (int64_t c = 0; c < nch; ++c) {
             const int64_t of = O.lo + c * SPAN + lane * R;
             int64_t T[R + 1];
@@ -276,7 +317,8 @@ __device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 part[r] = acc;
-                for (int64_t i = T[r]; i < T[r + 1]; ++i) acc += pmf<MODEL>(L, I, i, ll, l1m);
+                double di = (double)T[r];
+                for (int64_t i = T[r]; i < T[r + 1]; ++i, di += 1.0) acc += pmf<MODEL>(L, E, I, i, di, ll, l1m);
             }
             const double pre = wave_excl_prefix(acc);
             const double tot = wave_sum(acc);
@@ -284,7 +326,7 @@ __device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide
             for (int r = 0; r < R; ++r) {
                 const int64_t o = of + r;
                 if (o <= O.hi) {
-                    const double po = pmf<MODEL>(L, O, o, ll, l1m);
+                    const double po = pmf<MODEL>(L, E, O, o, (double)of + (double)r, ll, l1m);
                     if (empty[r])
                         p_empty += po;
                     else
@@ -296,14 +338,14 @@ __device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide
             qr_add(y, cstep, O.n);
         }
         double inner_tot = 1.0;  // the whole binomial mass
-        if constexpr (MODEL == SIG_POISSON) inner_tot = carry + range_sum<MODEL>(L, I, T_top, I.hi + 1, ll, l1m);
+        if constexpr (MODEL == SIG_POISSON) inner_tot = carry + range_sum<MODEL>(L, E, I, T_top, I.hi + 1, ll, l1m);
         acc_tail += p_empty * inner_tot;
     }
     // ---- descending pass: mass above hi(o)
     {
         const int64_t o0 = O.lo + (nch - 1) * SPAN + lane * R;
         QR x = divmod_floor(o0 * I.n - num, O.n), y = divmod_floor(o0 * I.n + num, O.n);
-        double carry = range_sum<MODEL>(L, I, U_top, I.hi + 1, ll, l1m);
+        double carry = range_sum<MODEL>(L, E, I, U_top, I.hi + 1, ll, l1m);
         for (int64_t c = nch - 1; c >= 0; --c) {
             const int64_t of = O.lo + c * SPAN + lane * R;
             int64_t U[R + 1];
@@ -321,7 +363,8 @@ __device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide
             double sfx[R], acc = 0.0;
 #pragma unroll
             for (int r = R - 1; r >= 0; --r) {
-                for (int64_t i = U[r + 1] - 1; i >= U[r]; --i) acc += pmf<MODEL>(L, I, i, ll, l1m);
+                double di = (double)(U[r + 1] - 1);
+                for (int64_t i = U[r + 1] - 1; i >= U[r]; --i, di -= 1.0) acc += pmf<MODEL>(L, E, I, i, di, ll, l1m);
                 sfx[r] = acc;
             }
             const double suf = wave_excl_suffix(acc);
@@ -330,7 +373,7 @@ __device__ double tail_two_pass(const double *L, const SigSide &O, const SigSide
             for (int r = 0; r < R; ++r) {
                 const int64_t o = of + r;
                 if (o <= O.hi && !empty[r])
-                    acc_tail += pmf<MODEL>(L, O, o, ll, l1m) * (carry + suf + sfx[r]);
+                    acc_tail += pmf<MODEL>(L, E, O, o, (double)of + (double)r, ll, l1m) * (carry + suf + sfx[r]);
             }
             carry += tot;
             qr_sub(x, cstep, O.n);
@@ -347,8 +390,11 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
                                                           const unsigned long long *__restrict__ hist,
                                                           int64_t n_p, int64_t n_q, uint64_t num_imm,
                                                           const uint64_t *__restrict__ num_dev,
-                                                          double *__restrict__ terms)
+                                                          double *__restrict__ terms, Exp2Table e2)
 {
+    __shared__ double E[32];
+    if (threadIdx.x < 32) E[threadIdx.x] = e2.t[threadIdx.x];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -371,11 +417,13 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
             A.n = n_p;
             A.mu = mup;
             A.lmu = log(mup);
+            A.dn = (double)n_p;
             A.lo = max((int64_t)0, (int64_t)floor(mup) - wp);
             A.hi = min(n_p, (int64_t)ceil(mup) + wp);
             B.n = n_q;
             B.mu = muq;
             B.lmu = log(muq);
+            B.dn = (double)n_q;
             B.lo = max((int64_t)0, (int64_t)floor(muq) - wq);
             B.hi = min(n_q, (int64_t)ceil(muq) + wq);
             // the larger window is the outer one, so that the lanes stay busy
@@ -383,8 +431,8 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
             const bool a_outer = (A.hi - A.lo) >= (B.hi - B.lo);
             const SigSide &O = a_outer ? A : B;
             const SigSide &I = a_outer ? B : A;
-            return (O.hi - O.lo + 1 >= 8 * 64) ? tail_two_pass<MODEL, 8>(L, O, I, num, ll, l1m)
-                                               : tail_two_pass<MODEL, 1>(L, O, I, num, ll, l1m);
+            return (O.hi - O.lo + 1 >= 8 * 64) ? tail_two_pass<MODEL, 8>(L, E, O, I, num, ll, l1m)
+                                               : tail_two_pass<MODEL, 1>(L, E, O, I, num, ll, l1m);
         };
         // A normal approximation of delta (variance lam (1 - lam) (1/n_p + 1/n_q),
         // lam (1/n_p + 1/n_q) for the Poisson model) picks the first window:
@@ -401,7 +449,7 @@ __global__ __launch_bounds__(SIG_THREADS) void k_sig_tail(const double *__restri
         const int64_t wq = window_halfwidth(sq), wp = window_halfwidth(sp);
         if constexpr (MODEL == SIG_POISSON) {
             // mass of either Poisson count beyond its sample size
-            const double ua = pois_upper_wave(L, n_p, mup, wp), ub = pois_upper_wave(L, n_q, muq, wq);
+            const double ua = pois_upper_wave(L, E, n_p, mup, wp), ub = pois_upper_wave(L, E, n_q, muq, wq);
             tail += ua + ub - ua * ub;
         }
         if (lane == 0) {
@@ -480,13 +528,19 @@ hipError_t launch_significance(const uint32_t *counts, int64_t N, int d, int64_t
         hipLaunchKernelGGL(k_sig_hist<false>, dim3(blocks(entries)), dim3(1024), 0, s, counts, entries,
                            n_q, hist, flags);
     }
+    // 2^(j/32), correctly rounded: from the 64-bit-significand long double
+    static const Exp2Table e2 = [] {
+        Exp2Table t;
+        for (int j = 0; j < 32; ++j) t.t[j] = (double)exp2l((long double)j / 32.0L);
+        return t;
+    }();
     const unsigned tb = (unsigned)(rows / 4);  // four waves per block
     if (model == SIG_POISSON)
         hipLaunchKernelGGL(k_sig_tail<SIG_POISSON>, dim3(tb), dim3(SIG_THREADS), 0, s, L, hist, n_p,
-                           n_q, num, num_dev, terms);
+                           n_q, num, num_dev, terms, e2);
     else
         hipLaunchKernelGGL(k_sig_tail<SIG_BINOMIAL>, dim3(tb), dim3(SIG_THREADS), 0, s, L, hist, n_p,
-                           n_q, num, num_dev, terms);
+                           n_q, num, num_dev, terms, e2);
     hipLaunchKernelGGL(k_sig_final, dim3(1), dim3(SIG_THREADS), 0, s, terms, n_q + 1, S);
     return hipGetLastError();
 }
