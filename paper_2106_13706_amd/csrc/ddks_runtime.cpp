@@ -131,14 +131,15 @@ SweepPlan plan_for(ddks_ctx *c, int path, int d, int64_t N, int64_t n_p)
     // 4 waves per block; 8 from d = 4 on, where LDS (the 68 KB pair table at
     // d = 4, 2^d 256-byte bins above) admits few blocks per CU.  At d = 4 the
     // table admits two blocks per CU whatever their size, so from 6144 points
-    // on the blocks take 12 waves, and from 32768 on 16: two of them fill the
-    // CU's 8 waves per SIMD (the sweep's 80 SGPRs allow that many; 214 us
-    // against 216 with 12 at 2 x 20000).  The d = 6, 2 x 100000 sweep
-    // measured fastest with 16 waves as well (8.17 ms, against 8.28 with 12
-    // and 8.35 with 8).
+    // on the blocks take 12 waves.  From 32768 points on every d takes 16: two
+    // such blocks fill a CU's 8 waves per SIMD (the sweep's 80 SGPRs allow
+    // that many).  Kernel times with the default chunks, 8 / 12 / 16 waves, at
+    // 32768 and 131072 points: d = 4 168 / 162 / 157 us and 2.80 / 2.51 / 2.39
+    // ms; d = 6 251 / 251 / 244 us and 3.72 / 3.59 / 3.49 ms; d = 8 313 / 298 /
+    // 289 us and 6.20 / 5.48 / 5.26 ms; d = 2, 3, 5, 7 alike or within 1%.
     p.waves = d >= 4 ? 8 : 4;
     if (d == 4 && N >= 6144) p.waves = 12;
-    if ((d == 4 || d == 6) && N >= 32768) p.waves = 16;
+    if (N >= 32768) p.waves = 16;
     if (c && (c->force_waves == 1 || c->force_waves == 2 || c->force_waves == 4 ||
               c->force_waves == 8 || c->force_waves == 12 || c->force_waves == 16))
         p.waves = c->force_waves;
