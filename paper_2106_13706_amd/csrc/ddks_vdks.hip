@@ -222,20 +222,47 @@ __global__ __launch_bounds__(COMPACT_THREADS) void k_vox_compact(const uint64_t 
 // path (two dimensions each, biased int16), STRIDE words per voxel, and
 // beside them one word of counts per voxel, c_P | c_Q << 16 (meaningful when
 // both fit 16 bits), which the sweep reads into vector registers.
-template <int D>
+//
+// With at most 128 voxels per dimension and d <= 7 (B8) the coordinates go
+// one byte each instead, four dimensions per word, each byte 128 + v: then
+// for an origin o (bytes v_o) the word x - o holds 128 + v_x - v_o in each
+// byte, never below 1, so no byte borrows from the next, and its top bit is
+// [v_x >= v_o]; masked to those bits, one v_dot4_u32_u8 against weights
+// 2^(m+1) adds 256 * (sum of 2^m over those dimensions) to the lane's bin-0
+// address: the bin of orthant code j, 32-bit bins of 64 lanes.  Three vector
+// instructions per voxel at d <= 4 and six at d = 5..7, against five and
+// seven and a half for the int16 signs, v_perm and the address shift.
+template <int D, bool B8 = false>
 struct VLayout {
-    static constexpr int STRIDE = Geo<D>::NREG;
+    static constexpr int STRIDE = B8 ? (D + 3) / 4 : Geo<D>::NREG;
     // voxels per unrolled block: a multiple of four, about 32 scalar registers
-    static constexpr int U = ((32 / STRIDE) / 4) * 4 < 4 ? 4 : ((32 / STRIDE) / 4) * 4;
+    // (8 voxels at most in the byte encoding, whose blocks' counts words and
+    // addresses, 3 vector registers per voxel, would outgrow its few SGPRs)
+    static constexpr int U0 = ((32 / STRIDE) / 4) * 4 < 4 ? 4 : ((32 / STRIDE) / 4) * 4;
+    static constexpr int U = B8 && U0 > 8 ? 8 : U0;
 };
+
+constexpr int VB8_MAX_V = 128;  // voxels per dimension of the byte encoding
+__host__ __device__ constexpr bool vsweep_bytes(int d, int V) { return d <= 7 && V <= VB8_MAX_V; }
+
+// Byte weights of word q of the byte encoding: 2^(m+1) for dimension m = 4q+i.
+__host__ __device__ constexpr uint32_t dot_wts8(int D, int q)
+{
+    uint32_t w = 0;
+    for (int i = 0; i < 4; ++i) {
+        const int m = 4 * q + i;
+        if (m < D) w |= (2u << m) << (8 * i);
+    }
+    return w;
+}
 
 int vox_words(int d) { return (d + 1) / 2 + 1; }
 
-template <int D>
+template <int D, bool B8>
 __global__ void k_vox_encode(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ inc, int64_t M,
                              int V, uint32_t *__restrict__ R, uint32_t *__restrict__ W32)
 {
-    constexpr int S = VLayout<D>::STRIDE;
+    constexpr int S = VLayout<D, B8>::STRIDE;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
          i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t k = keys[i];
@@ -246,8 +273,12 @@ __global__ void k_vox_encode(const uint64_t *__restrict__ keys, const uint64_t *
         for (int m = 0; m < D; ++m) {
             const uint32_t v = (uint32_t)(k % (uint64_t)V);
             k /= (uint64_t)V;
-            const uint32_t r = (v - 32768u) & 0xffffu;
-            w[m >> 1] |= r << (16 * (m & 1));
+            if constexpr (B8) {
+                w[m >> 2] |= (v + 128u) << (8 * (m & 3));
+            } else {
+                const uint32_t r = (v - 32768u) & 0xffffu;
+                w[m >> 1] |= r << (16 * (m & 1));
+            }
         }
 #pragma unroll
         for (int p = 0; p < S; ++p) R[i * S + p] = w[p];
@@ -378,64 +409,119 @@ __device__ __forceinline__ void vfinish(Get get, uint64_t *red, const uint64_t *
     }
 }
 
-// Bin addresses (32-bit bins) of U consecutive voxels of the encoding held in
-// buf (stride VLayout<D>::STRIDE words), as block_addrs computes them for
-// points of the rank path.
-template <int D, int U>
-__device__ __forceinline__ void vblock_addrs(const uint32_t *buf, const Origin<PATH_R16, D> &org, uint32_t base,
-                                             uint32_t (&a)[U])
+// The lane's origin in the byte encoding, its 128 offsets removed.
+template <int D>
+struct VOrigin8 {
+    static constexpr int S = VLayout<D, true>::STRIDE;
+    uint32_t o[S];
+};
+template <int D, bool B8>
+struct VOrgSel {
+    typedef Origin<PATH_R16, D> type;
+};
+template <int D>
+struct VOrgSel<D, true> {
+    typedef VOrigin8<D> type;
+};
+
+// Loads the lane's origin, voxel k of the encoding RV.
+template <int D, bool B8>
+__device__ __forceinline__ void vorigin_load(typename VOrgSel<D, B8>::type &org, const uint32_t *RV, int64_t k)
 {
-    constexpr int S = VLayout<D>::STRIDE;
-    constexpr int NP = Geo<D>::NPERM;
-    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+    constexpr int S = VLayout<D, B8>::STRIDE;
+    if constexpr (B8) {
 #pragma unroll
-    for (int g = 0; g < U; g += 4) {
-        uint32_t R[2][4];
-        uint32_t q[4];
-        if constexpr (D == 5 || D == 6) {
-            // one v_perm serves the second groups of two voxels (dimensions 4, 5)
-            constexpr uint32_t SEL = D == 6 ? 0x0b0a0908u : 0x0c0a0c08u;
+        for (int p = 0; p < S; ++p) org.o[p] = RV[k * S + p] & 0x7f7f7f7fu;
+    } else {
 #pragma unroll
-            for (int u = 0; u < 4; u += 2) {
-                uint32_t r0[Geo<D>::NREG], r1[Geo<D>::NREG];
-                signs<PATH_R16, D>(buf + (g + u) * S, org, r0);
-                signs<PATH_R16, D>(buf + (g + u + 1) * S, org, r1);
-                R[0][u] = group_bytes<D>(r0, 0);
-                R[0][u + 1] = group_bytes<D>(r1, 0);
-                R[1][u] = R[1][u + 1] = __builtin_amdgcn_perm(r1[2], r0[2], SEL);
+        for (int p = 0; p < Layout<PATH_R16, D>::PW; ++p) org.o[p] = p < Geo<D>::NREG ? RV[k * S + p] : 0u;
+    }
+}
+
+// Bin address of one voxel x (S words) against the lane's origin: from the
+// bin-0 address base in the byte encoding, from the bin-KOFF one otherwise.
+template <int D, bool B8>
+__device__ __forceinline__ uint32_t vaddr1(const uint32_t *x, const typename VOrgSel<D, B8>::type &org, uint32_t base)
+{
+    if constexpr (B8) {
+        uint32_t a = base;
+#pragma unroll
+        for (int q = 0; q < VLayout<D, true>::STRIDE; ++q)
+            a = __builtin_amdgcn_udot4((x[q] - org.o[q]) & 0x80808080u, dot_wts8(D, q), a, false);
+        return a;
+    } else {
+        constexpr int NP = Geo<D>::NPERM;
+        uint32_t r[Geo<D>::NREG];
+        signs<PATH_R16, D>(x, org, r);
+        const uint32_t R0 = group_bytes<D>(r, 0);
+        const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+        return addr1<NP>(R0, R1, base, dot_wts(D, 0), dot_wts(D, 1));
+    }
+}
+
+// Bin addresses (32-bit bins) of U consecutive voxels of the encoding held in
+// buf (stride VLayout<D, B8>::STRIDE words), as block_addrs computes them for
+// points of the rank path.
+template <int D, int U, bool B8>
+__device__ __forceinline__ void vblock_addrs(const uint32_t *buf, const typename VOrgSel<D, B8>::type &org,
+                                             uint32_t base, uint32_t (&a)[U])
+{
+    constexpr int S = VLayout<D, B8>::STRIDE;
+    if constexpr (B8) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = vaddr1<D, true>(buf + u * S, org, base);
+    } else {
+        constexpr int NP = Geo<D>::NPERM;
+        const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+#pragma unroll
+        for (int g = 0; g < U; g += 4) {
+            uint32_t R[2][4];
+            uint32_t q[4];
+            if constexpr (D == 5 || D == 6) {
+                // one v_perm serves the second groups of two voxels (dimensions 4, 5)
+                constexpr uint32_t SEL = D == 6 ? 0x0b0a0908u : 0x0c0a0c08u;
+#pragma unroll
+                for (int u = 0; u < 4; u += 2) {
+                    uint32_t r0[Geo<D>::NREG], r1[Geo<D>::NREG];
+                    signs<PATH_R16, D>(buf + (g + u) * S, org, r0);
+                    signs<PATH_R16, D>(buf + (g + u + 1) * S, org, r1);
+                    R[0][u] = group_bytes<D>(r0, 0);
+                    R[0][u + 1] = group_bytes<D>(r1, 0);
+                    R[1][u] = R[1][u + 1] = __builtin_amdgcn_perm(r1[2], r0[2], SEL);
+                }
+                addr4_w2(R, base, q, w0, w1, w1 << 16);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    uint32_t r[Geo<D>::NREG];
+                    signs<PATH_R16, D>(buf + (g + u) * S, org, r);
+                    R[0][u] = group_bytes<D>(r, 0);
+                    R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
+                }
+                addr4<NP>(R, base, q, w0, w1);
             }
-            addr4_w2(R, base, q, w0, w1, w1 << 16);
-        } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint32_t r[Geo<D>::NREG];
-                signs<PATH_R16, D>(buf + (g + u) * S, org, r);
-                R[0][u] = group_bytes<D>(r, 0);
-                R[1][u] = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-            }
-            addr4<NP>(R, base, q, w0, w1);
+            for (int u = 0; u < 4; ++u) a[g + u] = q[u];
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a[g + u] = q[u];
     }
 }
 
 // Voxels [lo, hi) of the encoding RV against the lane's G origins (one per
 // origin group, histogram j at base[j]) into 32-bit bins (c_P | c_Q << 16,
 // each voxel's counts word W32[i] as its increment): the exact sweep's
-// software pipeline over blocks of VLayout<D>::U voxels, each block's loads
-// serving all G origin groups.  The sign words come through scalar loads;
+// software pipeline over blocks of VLayout<D, B8>::U voxels, each block's
+// loads serving all G origin groups.  The coordinate words come through scalar loads;
 // the counts words through vector loads from an address the compiler must
 // treat as per-lane, so that they land in vector registers, where the LDS
 // atomics take their data, without a move per voxel.
-template <int D, int G>
+template <int D, int G, bool B8>
 __device__ __forceinline__ void vsweep_narrow(const uint32_t *__restrict__ RV, const uint32_t *__restrict__ W32,
-                                              int64_t lo, int64_t hi, const Origin<PATH_R16, D> (&org)[G],
+                                              int64_t lo, int64_t hi,
+                                              const typename VOrgSel<D, B8>::type (&org)[G],
                                               const uint32_t (&base)[G])
 {
-    constexpr int S = VLayout<D>::STRIDE;
-    constexpr int U = VLayout<D>::U;
-    constexpr int NP = Geo<D>::NPERM;
+    constexpr int S = VLayout<D, B8>::STRIDE;
+    constexpr int U = VLayout<D, B8>::U;
     // the same address in every lane, held in vector registers (a global
     // pointer: global loads count only against the vector-memory counter, so
     // the waits for the scalar loads and LDS atomics do not include them)
@@ -445,7 +531,7 @@ __device__ __forceinline__ void vsweep_narrow(const uint32_t *__restrict__ RV, c
     gu32 *Wv = (gu32 *)(uintptr_t)wv;
     auto block = [&](const uint32_t (&buf)[U * S], uint32_t (&a)[G][U]) {
 #pragma unroll
-        for (int j = 0; j < G; ++j) vblock_addrs<D, U>(buf, org[j], base[j], a[j]);
+        for (int j = 0; j < G; ++j) vblock_addrs<D, U, B8>(buf, org[j], base[j], a[j]);
     };
     auto adds = [&](const uint32_t (&wt)[U], const uint32_t (&a)[G][U]) {
 #pragma unroll
@@ -494,44 +580,31 @@ __device__ __forceinline__ void vsweep_narrow(const uint32_t *__restrict__ RV, c
             i += 2 * U;
         }
     }
-    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
     for (; i < hi; ++i) {
         uint32_t buf[S];
 #pragma unroll
         for (int e = 0; e < S; ++e) buf[e] = RV[i * S + e];
         const uint32_t wt = Wv[i];
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            uint32_t r[Geo<D>::NREG];
-            signs<PATH_R16, D>(buf, org[j], r);
-            const uint32_t R0 = group_bytes<D>(r, 0);
-            const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
-            lds_add(addr1<NP>(R0, R1, base[j], w0, w1), wt);
-        }
+        for (int j = 0; j < G; ++j) lds_add(vaddr1<D, B8>(buf, org[j], base[j]), wt);
     }
 }
 
 // The same for a chunk with more than 65535 points of a sample, one sample at
 // a time: 32-bit bins of that sample's counts alone (half = 0: c_P, the low
 // word of each voxel's increment; 1: c_Q, the high word), one origin group.
-template <int D>
+template <int D, bool B8>
 __device__ __forceinline__ void vsweep_one_sample(const uint32_t *__restrict__ RV, const uint64_t *__restrict__ inc,
-                                                  int half, int64_t lo, int64_t hi, const Origin<PATH_R16, D> &org,
-                                                  uint32_t base)
+                                                  int half, int64_t lo, int64_t hi,
+                                                  const typename VOrgSel<D, B8>::type &org, uint32_t base)
 {
-    constexpr int S = VLayout<D>::STRIDE;
-    constexpr int NP = Geo<D>::NPERM;
-    const uint32_t w0 = dot_wts(D, 0), w1 = dot_wts(D, 1);
+    constexpr int S = VLayout<D, B8>::STRIDE;
     for (int64_t i = lo; i < hi; ++i) {
         uint32_t buf[S];
 #pragma unroll
         for (int e = 0; e < S; ++e) buf[e] = RV[i * S + e];
-        uint32_t r[Geo<D>::NREG];
-        signs<PATH_R16, D>(buf, org, r);
-        const uint32_t R0 = group_bytes<D>(r, 0);
-        const uint32_t R1 = NP > 1 ? group_bytes<D>(r, 1) : 0u;
         const uint32_t c = (uint32_t)(inc[i] >> (32 * half));
-        if (c) lds_add(addr1<NP>(R0, R1, base, w0, w1), c);
+        if (c) lds_add(vaddr1<D, B8>(buf, org, base), c);
     }
 }
 
@@ -556,8 +629,8 @@ __host__ __device__ constexpr size_t vsweep_lds(int d, int waves, int H)
 // one histogram per sample.  With part null the block scores its origins
 // itself; otherwise it stores its counts as its chunk's rows of the partial
 // counts (plain stores: every entry of every row is written) and k_vscore
-// sums the chunks and scores them.
-template <int D, int W, int G>
+// sums the chunks and scores them.  B8: the byte encoding (VLayout).
+template <int D, int W, int G, bool B8>
 __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ RV,
                                                    const uint32_t *__restrict__ W32,
                                                    const uint64_t *__restrict__ inc,
@@ -566,7 +639,6 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
                                                    const uint32_t *__restrict__ fit,
                                                    uint32_t *__restrict__ part, VBest *__restrict__ bb)
 {
-    constexpr int S = VLayout<D>::STRIDE;
     constexpr int HB = Geo<D>::BINS * 64;  // bins of one histogram
     extern __shared__ uint32_t h32[];
     const int lane = threadIdx.x & 63;
@@ -576,18 +648,18 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
         mode == VFIT_WIDE || (mode == VFIT_PER_CHUNK && __builtin_amdgcn_readfirstlane(fit[blockIdx.y]) != 0u);
 
     for (int i = threadIdx.x; i < (mode == VFIT_WIDE ? 2 : G) * HB; i += W * 64) h32[i] = 0;
-    Origin<PATH_R16, D> org[G];
+    typename VOrgSel<D, B8>::type org[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         const int64_t k = ((int64_t)blockIdx.x * G + j) * 64 + lane;
-        const int64_t kk = k < M ? k : M - 1;
-#pragma unroll
-        for (int p = 0; p < Layout<PATH_R16, D>::PW; ++p) org[j].o[p] = p < Geo<D>::NREG ? RV[kk * S + p] : 0u;
+        vorigin_load<D, B8>(org[j], RV, k < M ? k : M - 1);
     }
+    // the address a voxel's code is added to: bin 0 in the byte encoding,
+    // bin KOFF for the int16 signs' negative dot sums
+    constexpr int B0 = B8 ? 0 : Geo<D>::KOFF;
     uint32_t base[G];
 #pragma unroll
-    for (int j = 0; j < G; ++j)
-        base[j] = (uint32_t)(uintptr_t)(lds_u32 *)(h32 + (size_t)j * HB + Geo<D>::KOFF * 64 + lane);
+    for (int j = 0; j < G; ++j) base[j] = (uint32_t)(uintptr_t)(lds_u32 *)(h32 + (size_t)j * HB + B0 * 64 + lane);
     __syncthreads();
 
     const int64_t c0 = M * (int64_t)blockIdx.y / gridDim.y, c1 = M * ((int64_t)blockIdx.y + 1) / gridDim.y;
@@ -600,8 +672,8 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
 
     if (mode == VFIT_WIDE) {
         // one chunk (G = 1): c_P into the first histogram, c_Q into the second
-        vsweep_one_sample<D>(RV, inc, 0, a, b, org[0], base[0]);
-        vsweep_one_sample<D>(RV, inc, 1, a, b, org[0], base[0] + HB * 4);
+        vsweep_one_sample<D, B8>(RV, inc, 0, a, b, org[0], base[0]);
+        vsweep_one_sample<D, B8>(RV, inc, 1, a, b, org[0], base[0] + HB * 4);
         __syncthreads();
         if (blockIdx.x < groups)
             vfinish<D, W>(
@@ -626,7 +698,7 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
                 __syncthreads();
             }
 #pragma unroll
-            for (int j = 0; j < G; ++j) vsweep_one_sample<D>(RV, inc, half, a, b, org[j], base[j]);
+            for (int j = 0; j < G; ++j) vsweep_one_sample<D, B8>(RV, inc, half, a, b, org[j], base[j]);
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < G; ++j) {
@@ -638,7 +710,7 @@ __global__ __launch_bounds__(W * 64) void k_vsweep(const uint32_t *__restrict__ 
         }
         return;
     }
-    vsweep_narrow<D, G>(RV, W32, a, b, org, base);
+    vsweep_narrow<D, G, B8>(RV, W32, a, b, org, base);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < G; ++j) {
@@ -856,7 +928,7 @@ size_t vsweep_partial_bytes(int64_t M, int d, const VSweepPlan &p)
     return 2 * (size_t)p.chunks * (size_t)((M + 63) / 64) * ((size_t)1 << d) * 64 * sizeof(uint32_t);
 }
 
-template <int D, int W, int G>
+template <int D, int W, int G, bool B8>
 static hipError_t launch_vsweep_w(const uint64_t *keys, const uint64_t *inc, int64_t M, int chunks, int64_t n_p,
                                   int64_t n_q, const uint32_t *RV, const uint32_t *W32, int mode, const uint32_t *fit, void *bb,
                                   void *partial, hipStream_t s)
@@ -866,7 +938,7 @@ static hipError_t launch_vsweep_w(const uint64_t *keys, const uint64_t *inc, int
     static std::once_flag attr;
     if (lds > 64 * 1024)
         std::call_once(attr, [] {
-            if (hipFuncSetAttribute((const void *)k_vsweep<D, W, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            if (hipFuncSetAttribute((const void *)k_vsweep<D, W, G, B8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     MAX_LDS_BYTES) != hipSuccess)
                 (void)hipGetLastError();
         });
@@ -875,7 +947,7 @@ static hipError_t launch_vsweep_w(const uint64_t *keys, const uint64_t *inc, int
     const bool via_partial = chunks > 1;
     uint32_t *Pp = via_partial ? (uint32_t *)partial : nullptr;
     if (via_partial && !Pp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_vsweep<D, W, G>), dim3((unsigned)((groups + G - 1) / G), (unsigned)chunks), dim3(W * 64),
+    hipLaunchKernelGGL((k_vsweep<D, W, G, B8>), dim3((unsigned)((groups + G - 1) / G), (unsigned)chunks), dim3(W * 64),
                        lds, s, RV, W32, inc, keys, M, n_p, n_q, mode, fit, Pp, (VBest *)bb);
     if (via_partial) {
         const uint32_t *f = mode == VFIT_PER_CHUNK ? fit : nullptr;
@@ -892,14 +964,30 @@ static hipError_t launch_vsweep_w(const uint64_t *keys, const uint64_t *inc, int
     return hipGetLastError();
 }
 
-template <int D, int W>
+template <int D, int W, bool B8>
 static hipError_t launch_vsweep_g(int G, const uint64_t *keys, const uint64_t *inc, int64_t M, int chunks,
                                   int64_t n_p, int64_t n_q, const uint32_t *RV, const uint32_t *W32, int mode, const uint32_t *fit,
                                   void *bb, void *partial, hipStream_t s)
 {
     if (G == 2 && mode != VFIT_WIDE)
-        return launch_vsweep_w<D, W, 2>(keys, inc, M, chunks, n_p, n_q, RV, W32, mode, fit, bb, partial, s);
-    return launch_vsweep_w<D, W, 1>(keys, inc, M, chunks, n_p, n_q, RV, W32, mode, fit, bb, partial, s);
+        return launch_vsweep_w<D, W, 2, B8>(keys, inc, M, chunks, n_p, n_q, RV, W32, mode, fit, bb, partial, s);
+    return launch_vsweep_w<D, W, 1, B8>(keys, inc, M, chunks, n_p, n_q, RV, W32, mode, fit, bb, partial, s);
+}
+
+template <int D, bool B8>
+static hipError_t launch_vsweep_e(const uint64_t *keys, const uint64_t *inc, int64_t M, const VSweepPlan &p,
+                                  int V, int64_t n_p, int64_t n_q, uint32_t *RV, const uint32_t *fitp, int mode,
+                                  void *bb, void *partial, hipStream_t s)
+{
+    // the counts words follow the M voxels' coordinate words
+    uint32_t *W32 = RV + M * VLayout<D, B8>::STRIDE;
+    hipLaunchKernelGGL((k_vox_encode<D, B8>), dim3(grid_for(M)), dim3(256), 0, s, keys, inc, M, V, RV, W32);
+    switch (p.waves) {
+    case 4: return launch_vsweep_g<D, 4, B8>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s);
+    case 8: return launch_vsweep_g<D, 8, B8>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s);
+    case 16: return launch_vsweep_g<D, 16, B8>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int D>
@@ -907,9 +995,6 @@ static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int
                                   int V, int64_t n_p, int64_t n_q, uint32_t *RV, uint32_t *fit, void *bb,
                                   void *partial, uint32_t *flags, ResultDev *out, hipStream_t s)
 {
-    // the counts words follow the M voxels' sign words
-    uint32_t *W32 = RV + M * VLayout<D>::STRIDE;
-    hipLaunchKernelGGL(k_vox_encode<D>, dim3(grid_for(M)), dim3(256), 0, s, keys, inc, M, V, RV, W32);
     // chunks of more than 65535 points of a sample cannot take the one-pass
     // bins: with both samples that small no chunk can hold so many; a single
     // chunk holds them all
@@ -920,11 +1005,13 @@ static hipError_t launch_vsweep_d(const uint64_t *keys, const uint64_t *inc, int
         fitp = fit;
     }
     hipError_t e;
-    switch (p.waves) {
-    case 4: e = launch_vsweep_g<D, 4>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s); break;
-    case 8: e = launch_vsweep_g<D, 8>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s); break;
-    case 16: e = launch_vsweep_g<D, 16>(p.per_block, keys, inc, M, p.chunks, n_p, n_q, RV, W32, mode, fitp, bb, partial, s); break;
-    default: return hipErrorInvalidValue;
+    if constexpr (D <= 7) {
+        if (vsweep_bytes(D, V))
+            e = launch_vsweep_e<D, true>(keys, inc, M, p, V, n_p, n_q, RV, fitp, mode, bb, partial, s);
+        else
+            e = launch_vsweep_e<D, false>(keys, inc, M, p, V, n_p, n_q, RV, fitp, mode, bb, partial, s);
+    } else {
+        e = launch_vsweep_e<D, false>(keys, inc, M, p, V, n_p, n_q, RV, fitp, mode, bb, partial, s);
     }
     if (e != hipSuccess) return e;
     const int64_t groups = (M + 63) / 64;

@@ -64,6 +64,19 @@ def test_workload_scale_and_fine_grid(ctx, oracle_mod):
     check(ctx, oracle_mod, P[:3000], Q[:3000], 4096)
 
 
+@pytest.mark.parametrize("d", [1, 3, 4, 7, 8])
+def test_byte_and_int16_encodings(ctx, oracle_mod, d):
+    """Up to 128 voxels per dimension (and d <= 7) the sweep codes voxel
+    coordinates one byte each, from 129 on (and at d = 8) as int16: both sides
+    of the boundary, with coordinates at both ends of the grid."""
+    g = np.random.default_rng(700 + d)
+    for V in (127, 128, 129, 200):
+        P = g.uniform(-1, 1, size=(900, d)).astype(np.float32)
+        Q = (g.uniform(-1, 1, size=(800, d)) * 0.9 + 0.05).astype(np.float32)
+        P[0], P[1] = -1.0, 1.0  # the extents: voxels 0 and V - 1 in every dimension
+        check(ctx, oracle_mod, P, Q, V)
+
+
 def test_device_pointers_and_errors(ctx, oracle_mod):
     import torch
     from paper_2106_13706_amd import native
