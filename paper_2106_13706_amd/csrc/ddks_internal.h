@@ -238,6 +238,9 @@ struct VSweepPlan {
 };
 VSweepPlan vsweep_default_plan(int64_t M);
 bool vsweep_plan_ok(const VSweepPlan &p, int64_t M, int d);
+// Whether the weighted sweep codes the voxel coordinates one byte each (at
+// most 128 voxels per dimension, d <= 7) rather than as int16.
+bool vsweep_uses_bytes(int d, int V);
 // Words per filled voxel of the weighted sweep's encoding.
 int vox_words(int d);
 

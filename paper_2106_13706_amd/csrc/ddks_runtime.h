@@ -187,8 +187,8 @@ void tuner_store_perm(Tuner *t, int path, int d, int64_t n, int waves, int pb);
 bool tuner_lookup_packed(Tuner *t, int path, int d, int64_t n, int *waves);
 void tuner_store_packed(Tuner *t, int path, int d, int64_t n, int waves);
 // vdKS's weighted sweep: the tuned (waves, chunks) for (d, log2 of the filled voxels).
-bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, VSweepPlan *plan);
-void tuner_store_vsweep(Tuner *t, int d, int64_t M, const VSweepPlan &plan);
+bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, bool bytes, VSweepPlan *plan);
+void tuner_store_vsweep(Tuner *t, int d, int64_t M, bool bytes, const VSweepPlan &plan);
 
 // Launches enqueue()'s work on s: by replaying the graph in *exec when
 // *key_have equals key, else by capturing enqueue() into a new graph first.

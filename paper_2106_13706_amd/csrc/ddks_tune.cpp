@@ -73,7 +73,8 @@ static void tuner_store(Tuner *t, int path, int d, int64_t N, int waves, int64_t
 // their own kinds in the first field: the permutation kernel as PERM_KIND +
 // path with (waves, relabellings per block), the packed sweep as
 // PACKED_KIND + path with (waves, 0), vdKS's weighted sweep as VSWEEP_KIND
-// with (waves, chunks + 256 (origin groups per block - 1)).
+// (+ 1 for its byte encoding of the voxel coordinates) with (waves, chunks +
+// 256 (origin groups per block - 1)).
 static constexpr int PERM_KIND = 10, PACKED_KIND = 20;
 
 bool tuner_lookup_perm(Tuner *t, int path, int d, int64_t n, int *waves, int *pb)
@@ -109,11 +110,11 @@ void tuner_store_packed(Tuner *t, int path, int d, int64_t n, int waves)
 
 static constexpr int VSWEEP_KIND = 30;
 
-bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, VSweepPlan *plan)
+bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, bool bytes, VSweepPlan *plan)
 {
     if (!t) return false;
     std::lock_guard<std::mutex> lk(t->m);
-    auto it = t->best.find({VSWEEP_KIND, d, bucket(M)});
+    auto it = t->best.find({VSWEEP_KIND + (bytes ? 1 : 0), d, bucket(M)});
     if (it == t->best.end()) return false;
     plan->waves = it->second.first;
     plan->chunks = (int)(it->second.second & 0xff);
@@ -122,9 +123,9 @@ bool tuner_lookup_vsweep(Tuner *t, int d, int64_t M, VSweepPlan *plan)
 }
 
 // stored as (waves, chunks + 256 (origin groups per block - 1))
-void tuner_store_vsweep(Tuner *t, int d, int64_t M, const VSweepPlan &plan)
+void tuner_store_vsweep(Tuner *t, int d, int64_t M, bool bytes, const VSweepPlan &plan)
 {
-    if (t) tuner_store(t, VSWEEP_KIND, d, M, plan.waves, plan.chunks + 256 * (plan.per_block - 1));
+    if (t) tuner_store(t, VSWEEP_KIND + (bytes ? 1 : 0), d, M, plan.waves, plan.chunks + 256 * (plan.per_block - 1));
 }
 
 bool tune_pending(ddks_ctx *c, int path, int d, int64_t N)

@@ -66,7 +66,7 @@ int tune_vsweep(ddks_ctx *c, const uint64_t *keys, const uint64_t *inc, int64_t 
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st) return st;
-    tuner_store_vsweep(c->tuner, d, M, *best);
+    tuner_store_vsweep(c->tuner, d, M, vsweep_uses_bytes(d, V), *best);
     return DDKS_OK;
 }
 
@@ -171,7 +171,7 @@ extern "C" int ddks_vdks(ddks_ctx *c, const float *P, int64_t n_p, const float *
         VSweepPlan f = c->force_vsweep;
         f.chunks = (int)std::min<int64_t>(f.chunks, M);
         if (vsweep_plan_ok(f, M, d)) plan = f;
-    } else if (!tuner_lookup_vsweep(c->tuner, d, M, &plan) || !vsweep_plan_ok(plan, M, d)) {
+    } else if (!tuner_lookup_vsweep(c->tuner, d, M, vsweep_uses_bytes(d, V), &plan) || !vsweep_plan_ok(plan, M, d)) {
         plan = vsweep_default_plan(M);
         if (c->tuner && !(c->opt_flags & DDKS_NO_AUTOTUNE) && M >= VSWEEP_TUNE_MIN) {
             // time the admissible shapes on this input once per (d, log2 M);

@@ -920,6 +920,8 @@ bool vsweep_plan_ok(const VSweepPlan &p, int64_t M, int d)
            vsweep_lds(d, p.waves, 2) <= (size_t)MAX_LDS_BYTES && (p.per_block == 1 || red <= hist);
 }
 
+bool vsweep_uses_bytes(int d, int V) { return vsweep_bytes(d, V); }
+
 size_t vsweep_partial_bytes(int64_t M, int d, const VSweepPlan &p)
 {
     if (p.chunks <= 1) return 0;

@@ -160,8 +160,9 @@ def test_forced_vsweep_shapes(oracle_mod, shape):
 
 
 def test_vsweep_shape_tuned_and_cached(oracle_mod, tmp_path):
-    """Enough filled voxels to tune the weighted sweep's shape: one kind-30
-    entry lands in the cache file and the result is the oracle's."""
+    """Enough filled voxels to tune the weighted sweep's shape: one entry lands
+    in the cache file, kind 31 for the byte encoding of a 16^4 grid (30 for
+    int16 coordinates), and the result is the oracle's."""
     from paper_2106_13706_amd import native, workloads
     P, Q = workloads.gaussian_scale()
     cache = tmp_path / "tune.txt"
@@ -171,5 +172,5 @@ def test_vsweep_shape_tuned_and_cached(oracle_mod, tmp_path):
         assert r2.num == r.num
     lines = [list(map(int, l.split())) for l in cache.read_text().split("\n") if l.strip()]
     print(f"  cache: {lines}", flush=True)
-    vs = [l for l in lines if l[0] == 30 and l[1] == 4]
+    vs = [l for l in lines if l[0] == 31 and l[1] == 4]
     assert len(vs) == 1 and vs[0][3] in (4, 8, 16) and 1 <= vs[0][4] % 256 <= 16 and vs[0][4] // 256 in (0, 1)
