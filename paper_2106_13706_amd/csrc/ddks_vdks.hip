@@ -236,8 +236,8 @@ template <int D, bool B8 = false>
 struct VLayout {
     static constexpr int STRIDE = B8 ? (D + 3) / 4 : Geo<D>::NREG;
     // voxels per unrolled block: a multiple of four, about 32 scalar registers
-    // (8 voxels at most in the byte encoding, whose blocks' counts words and
-    // addresses, 3 vector registers per voxel, would outgrow its few SGPRs)
+    // (8 at most in the byte encoding: 16-voxel blocks took the kernel past 64
+    // VGPRs at d = 4 and past 96 SGPRs at d = 6, below 8 waves per SIMD)
     static constexpr int U0 = ((32 / STRIDE) / 4) * 4 < 4 ? 4 : ((32 / STRIDE) / 4) * 4;
     static constexpr int U = B8 && U0 > 8 ? 8 : U0;
 };
