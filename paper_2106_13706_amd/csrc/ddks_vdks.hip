@@ -139,12 +139,14 @@ __device__ __forceinline__ uint64_t vox_hash(uint64_t key, uint64_t mask)
 }
 
 // Voxel key of every point, merged into the table (linear probing; the table
-// has at least twice as many slots as points, so every probe ends).
+// has at least twice as many slots as points, so every probe ends).  dense:
+// the grid has no more voxels than the table has slots, so slot = key and a
+// point is one counter increment, with no key to claim first.
 template <int D>
 __global__ __launch_bounds__(256) void k_vox_insert(const float *__restrict__ Z, int64_t N, int64_t n_p,
                                                     int V, const uint32_t *__restrict__ mm,
                                                     uint64_t *__restrict__ tab_key,
-                                                    uint32_t *__restrict__ tab_cnt, uint64_t mask)
+                                                    uint32_t *__restrict__ tab_cnt, uint64_t mask, int dense)
 {
     double lo[D], span[D];
 #pragma unroll
@@ -166,6 +168,10 @@ __global__ __launch_bounds__(256) void k_vox_insert(const float *__restrict__ Z,
             key += (uint64_t)v * scale;
             scale *= (uint64_t)V;
         }
+        if (dense) {
+            atomicAdd(&tab_cnt[2 * key + (i < n_p ? 0 : 1)], 1u);
+            continue;
+        }
         uint64_t h = vox_hash(key, mask);
         while (true) {
             const unsigned long long old = atomicCAS((unsigned long long *)&tab_key[h], VOX_EMPTY, key);
@@ -179,11 +185,13 @@ __global__ __launch_bounds__(256) void k_vox_insert(const float *__restrict__ Z,
 // Filled slots to a list: key, and the 64-bit increment c_P | c_Q << 32.
 // One counter update per block of 1024 slots (a single word updated by
 // every wave or slot serialises across the chip): the filled slots of a
-// block take consecutive places, in slot order within the block.
+// block take consecutive places, in slot order within the block.  dense: a
+// slot is filled when either count is, and its key is its index.
 static constexpr int COMPACT_THREADS = 1024;
 __global__ __launch_bounds__(COMPACT_THREADS) void k_vox_compact(const uint64_t *__restrict__ tab_key,
                                                                  const uint32_t *__restrict__ tab_cnt,
-                                                                 int64_t slots, uint32_t *__restrict__ counter,
+                                                                 int64_t slots, int dense,
+                                                                 uint32_t *__restrict__ counter,
                                                                  uint64_t *__restrict__ keys,
                                                                  uint64_t *__restrict__ inc)
 {
@@ -193,7 +201,13 @@ __global__ __launch_bounds__(COMPACT_THREADS) void k_vox_compact(const uint64_t 
     const int64_t stride = (int64_t)gridDim.x * COMPACT_THREADS;
     for (int64_t h0 = (int64_t)blockIdx.x * COMPACT_THREADS; h0 < slots; h0 += stride) {
         const int64_t h = h0 + threadIdx.x;
-        const uint64_t k = h < slots ? tab_key[h] : VOX_EMPTY;
+        uint64_t k = VOX_EMPTY;
+        if (h < slots) {
+            if (dense)
+                k = (tab_cnt[2 * h] | tab_cnt[2 * h + 1]) != 0u ? (uint64_t)h : VOX_EMPTY;
+            else
+                k = tab_key[h];
+        }
         const bool filled = k != VOX_EMPTY;
         const uint64_t mask = __ballot(filled);
         if (lane == 0) wbase[w] = (uint32_t)__popcll(mask);
@@ -854,20 +868,32 @@ size_t vdks_table_slots(int64_t N)
     return s;
 }
 
+// Whether V^d voxels fit the table's slots, so that the key can be the slot.
+static bool vox_dense(int d, int V, int64_t slots)
+{
+    uint64_t cells = 1;
+    for (int m = 0; m < d; ++m) {
+        cells *= (uint64_t)V;
+        if (cells > (uint64_t)slots) return false;
+    }
+    return true;
+}
+
 template <int D>
 static hipError_t launch_vox_front_d(const float *Z, int64_t N, int64_t n_p, int V, uint32_t *mm,
                                      uint32_t *part, uint64_t *tab_key, uint32_t *tab_cnt, int64_t slots,
                                      uint32_t *counter, uint64_t *keys, uint64_t *inc, hipStream_t s)
 {
+    const int dense = vox_dense(D, V, slots) ? 1 : 0;
     hipLaunchKernelGGL(k_vox_init, dim3(grid_for(slots)), dim3(256), 0, s, mm, D, tab_key, tab_cnt,
                        slots, counter);
     const unsigned rows = grid_for(N, 256, VOX_EXTENT_ROWS);
     hipLaunchKernelGGL(k_vox_minmax<D>, dim3(rows), dim3(256), 0, s, Z, N, part);
     hipLaunchKernelGGL(k_vox_minmax_final<D>, dim3(1), dim3(256), 0, s, part, (int)rows, mm);
     hipLaunchKernelGGL(k_vox_insert<D>, dim3(grid_for(N)), dim3(256), 0, s, Z, N, n_p, V, mm, tab_key,
-                       tab_cnt, (uint64_t)(slots - 1));
+                       tab_cnt, (uint64_t)(slots - 1), dense);
     hipLaunchKernelGGL(k_vox_compact, dim3(grid_for(slots, COMPACT_THREADS, 256)), dim3(COMPACT_THREADS), 0, s,
-                       tab_key, tab_cnt, slots, counter, keys, inc);
+                       tab_key, tab_cnt, slots, dense, counter, keys, inc);
     return hipGetLastError();
 }
 
