@@ -77,6 +77,19 @@ def test_byte_and_int16_encodings(ctx, oracle_mod, d):
         check(ctx, oracle_mod, P, Q, V)
 
 
+@pytest.mark.parametrize("V", [4, 5])
+def test_dense_and_hashed_voxel_tables(ctx, oracle_mod, V):
+    """The voxel table takes the key as its slot when the grid has no more
+    voxels than the table has slots (at least twice the points, a power of
+    two): 60 + 40 points get 256 slots, so a 4^4 grid (256 voxels) is counted
+    directly and a 5^4 grid (625) through the hash."""
+    g = np.random.default_rng(900 + V)
+    P = g.uniform(0, 1, size=(60, 4)).astype(np.float32)
+    Q = g.uniform(0, 1, size=(40, 4)).astype(np.float32) ** 2
+    P[0], P[1] = 0.0, 1.0
+    check(ctx, oracle_mod, P, Q, V)
+
+
 def test_device_pointers_and_errors(ctx, oracle_mod):
     import torch
     from paper_2106_13706_amd import native
