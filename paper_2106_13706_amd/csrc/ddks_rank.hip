@@ -17,8 +17,9 @@
 //                     pooled values below the point, fits 16 bits since
 //                     N <= 65536.
 // N > 65536:
-//   1. k_rank_tiles   sorts tiles of (key, index) pairs (bitonic, in
-//                     registers, wave shuffles and LDS);
+//   1. k_rank_pairs   sorts tiles of (key, index) pairs (the same bitonic
+//                     network on 64-bit values: registers, DPP, permlane
+//                     swaps and LDS);
 //   2. k_rank_place_count adds up, per pair, the pairs below it in every
 //                     tile (binary searches in LDS-staged tiles), and
 //      k_rank_scatter writes each pair at that sorted position;
@@ -71,19 +72,20 @@ __device__ __forceinline__ float point_value(const float *__restrict__ P, int64_
 static constexpr int LOG_STILE = DDKS_STILE_LOG;
 static constexpr int STILE = 1 << LOG_STILE;
 static constexpr int SKPT = DDKS_SORT_KPT;  // keys per thread
-static constexpr int LOG_SKPT = SKPT == 16 ? 4 : 3;
 static constexpr int S32_THREADS = STILE / SKPT;
 static_assert((SKPT == 8 || SKPT == 16) && S32_THREADS >= 256 && S32_THREADS <= 1024, "tile size");
 
-// ---- the tile sort: a bitonic network on SKPT keys per thread (element
-// e = SKPT tid + r of the tile in register r of thread tid), in the form where
+// ---- the tile sort: a bitonic network on KPT values per thread (element
+// e = KPT tid + r of the tile in register r of thread tid), in the form where
 // every compare-exchange puts the minimum at the lower element: phase lk
 // (blocks of 2^lk elements) first pairs e with e ^ (2^lk - 1) (the "flip",
 // which merges two sorted runs read in opposite directions), then e with
-// e ^ j for j = 2^(lk-2) .. 1.  Distances below SKPT are exchanges between a
-// thread's registers; SKPT .. 32 SKPT are lane distances 1 .. 32 within a
+// e ^ j for j = 2^(lk-2) .. 1.  Distances below KPT are exchanges between a
+// thread's registers; KPT .. 32 KPT are lane distances 1 .. 32 within a
 // wave, exchanged through DPP and the gfx950 permlane swaps (no LDS traffic);
-// the three stages that cross waves go through LDS.
+// the stages that cross waves go through LDS.  The values are 32-bit keys
+// (k_rank_sort32) or 64-bit (key, index) pairs (k_rank_pairs), moved as two
+// 32-bit halves along the same lanes.
 
 // DPP controls (row = 16 lanes, bank = 4 lanes of a row).
 constexpr int DPP_QUAD_X1 = 0xB1;  // quad_perm [1,0,3,2]: lane ^ 1
@@ -94,10 +96,19 @@ constexpr int DPP_ROW_SHR = 0x110;  // + n: lane l reads lane l - n of its row
 constexpr int DPP_ROW_MIRROR = 0x140;       // lane ^ 15
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane ^ 7
 
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+__device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp(uint64_t x)
+{
+    return join64(dpp<CTRL>(lo32(x)), dpp<CTRL>(hi32(x)));
 }
 
 // src moved by CTRL into the lanes of the banks in BANKS; old elsewhere.
@@ -106,145 +117,205 @@ __device__ __forceinline__ uint32_t dpp_into(uint32_t old, uint32_t src)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xf, BANKS, false);
 }
-
-// The value of lane l ^ 16 (l ^ 32): a permlane swap of x with itself leaves
-// the partner half in one of its two results.
-__device__ __forceinline__ uint32_t lane_xor16(uint32_t x, int lane)
+template <int CTRL, int BANKS>
+__device__ __forceinline__ uint64_t dpp_into(uint64_t old, uint64_t src)
 {
-    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-    return (lane & 16) ? s[0] : s[1];
+    return join64(dpp_into<CTRL, BANKS>(lo32(old), lo32(src)), dpp_into<CTRL, BANKS>(hi32(old), hi32(src)));
 }
-__device__ __forceinline__ uint32_t lane_xor32(uint32_t x, int lane)
+
+// Permlane swap of x and y (A = 16: the odd 16-lane rows of x with the even
+// rows of y; A = 32: the upper half of x with the lower half of y).
+template <int A>
+__device__ __forceinline__ void permlane_swap(uint32_t &x, uint32_t &y)
 {
-    const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-    return (lane & 32) ? s[0] : s[1];
+    if constexpr (A == 16) {
+        const auto s = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = s[0];
+        y = s[1];
+    } else {
+        const auto s = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = s[0];
+        y = s[1];
+    }
+}
+template <int A>
+__device__ __forceinline__ void permlane_swap(uint64_t &x, uint64_t &y)
+{
+    uint32_t xl = lo32(x), xh = hi32(x), yl = lo32(y), yh = hi32(y);
+    permlane_swap<A>(xl, yl);
+    permlane_swap<A>(xh, yh);
+    x = join64(xl, xh);
+    y = join64(yl, yh);
+}
+
+// The value of lane l ^ A (A = 16 or 32): a permlane swap of x with itself
+// leaves the partner half in one of its two results.
+template <int A, typename T>
+__device__ __forceinline__ T lane_xor(T x, int lane)
+{
+    T a = x, b = x;
+    permlane_swap<A>(a, b);
+    return (lane & A) ? a : b;
 }
 
 // Partner value of a flip within the wave: lane l ^ (2^LM - 1), 1 <= LM <= 6.
-template <int LM>
-__device__ __forceinline__ uint32_t flip_lanes(uint32_t x, int lane)
+template <int LM, typename T>
+__device__ __forceinline__ T flip_lanes(T x, int lane)
 {
     if constexpr (LM == 1) return dpp<DPP_QUAD_X1>(x);
     else if constexpr (LM == 2) return dpp<DPP_QUAD_X3>(x);
     else if constexpr (LM == 3) return dpp<DPP_ROW_HALF_MIRROR>(x);
     else if constexpr (LM == 4) return dpp<DPP_ROW_MIRROR>(x);
-    else if constexpr (LM == 5) return lane_xor16(dpp<DPP_ROW_MIRROR>(x), lane);
-    else return lane_xor32(lane_xor16(dpp<DPP_ROW_MIRROR>(x), lane), lane);
+    else if constexpr (LM == 5) return lane_xor<16>(dpp<DPP_ROW_MIRROR>(x), lane);
+    else return lane_xor<32>(lane_xor<16>(dpp<DPP_ROW_MIRROR>(x), lane), lane);
 }
 
-__device__ __forceinline__ void cmpx(uint32_t &lo, uint32_t &hi)
+template <typename T>
+__device__ __forceinline__ void cmpx(T &lo, T &hi)
 {
-    const uint32_t a = min(lo, hi), b = max(lo, hi);
+    const T a = min(lo, hi), b = max(lo, hi);
     lo = a;
     hi = b;
 }
 
-// A stage whose partner thread is tid ^ M, in another wave (M >= 64), with
-// the partner's registers reversed when FLIP; buf holds S32_THREADS x SKPT words.
-template <int M, bool FLIP>
-__device__ __forceinline__ void sort_cross_wave(uint32_t (&v)[SKPT], int tid, uint4 *buf)
+// The network's shape: KPT values of type T per thread, NT threads, a tile
+// of 2^LOG_TILE = KPT NT values; an LDS exchange buffer of NT x KPT values
+// (16-byte words, WORDS per thread).
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+template <typename T, int KPT, int NT>
+struct Net {
+    static constexpr int LOG_KPT = ilog2(KPT);
+    static constexpr int LOG_TILE = LOG_KPT + ilog2(NT);
+    static constexpr int WORDS = KPT * (int)sizeof(T) / 16;
+    static_assert((KPT == 4 || KPT == 8 || KPT == 16) && (NT == 64 || NT == 256 || NT == 512 || NT == 1024),
+                  "shape");
+    static_assert(WORDS >= 1, "exchange words");
+};
+
+template <typename T, int KPT>
+__device__ __forceinline__ uint4 pack_word(const T (&v)[KPT], int q)
 {
-    const bool lower = (tid & (FLIP ? (M + 1) / 2 : M)) == 0;
-#pragma unroll
-    for (int q = 0; q < SKPT / 4; ++q) buf[q * S32_THREADS + tid] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-    __syncthreads();
-    uint32_t p[SKPT];
-#pragma unroll
-    for (int q = 0; q < SKPT / 4; ++q) {
-        const uint4 x = buf[q * S32_THREADS + (tid ^ M)];
+    if constexpr (sizeof(T) == 4)
+        return make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    else
+        return make_uint4(lo32(v[2 * q]), hi32(v[2 * q]), lo32(v[2 * q + 1]), hi32(v[2 * q + 1]));
+}
+template <typename T, int KPT>
+__device__ __forceinline__ void unpack_word(T (&p)[KPT], int q, uint4 x)
+{
+    if constexpr (sizeof(T) == 4) {
         p[4 * q] = x.x;
         p[4 * q + 1] = x.y;
         p[4 * q + 2] = x.z;
         p[4 * q + 3] = x.w;
+    } else {
+        p[2 * q] = join64(x.x, x.y);
+        p[2 * q + 1] = join64(x.z, x.w);
     }
+}
+
+// A stage whose partner thread is tid ^ M, in another wave (M >= 64), with
+// the partner's registers reversed when FLIP.
+template <typename T, int KPT, int NT, int M, bool FLIP>
+__device__ __forceinline__ void sort_cross_wave(T (&v)[KPT], int tid, uint4 *buf)
+{
+    constexpr int W = Net<T, KPT, NT>::WORDS;
+    const bool lower = (tid & (FLIP ? (M + 1) / 2 : M)) == 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) buf[q * NT + tid] = pack_word(v, q);
+    __syncthreads();
+    T p[KPT];
+#pragma unroll
+    for (int q = 0; q < W; ++q) unpack_word(p, q, buf[q * NT + (tid ^ M)]);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < SKPT; ++r) {
-        const uint32_t x = p[FLIP ? SKPT - 1 - r : r];
+    for (int r = 0; r < KPT; ++r) {
+        const T x = p[FLIP ? KPT - 1 - r : r];
         v[r] = lower ? min(v[r], x) : max(v[r], x);
     }
 }
 
 // Half-cleaner stage j = 2^LJ.
-template <int LJ>
-__device__ __forceinline__ void sort_half(uint32_t (&v)[SKPT], int lane, int tid, uint4 *buf)
+template <typename T, int KPT, int NT, int LJ>
+__device__ __forceinline__ void sort_half(T (&v)[KPT], int lane, int tid, uint4 *buf)
 {
     constexpr int J = 1 << LJ;
-    if constexpr (J < SKPT) {
+    if constexpr (J < KPT) {
 #pragma unroll
-        for (int r = 0; r < SKPT; ++r)
+        for (int r = 0; r < KPT; ++r)
             if (!(r & J)) cmpx(v[r], v[r | J]);
-    } else if constexpr (J <= 2 * SKPT) {
+    } else if constexpr (J <= 2 * KPT) {
         // lane ^ 1, lane ^ 2: partner value by quad_perm
-        constexpr int A = J / SKPT;
+        constexpr int A = J / KPT;
         const bool lower = (lane & A) == 0;
 #pragma unroll
-        for (int r = 0; r < SKPT; ++r) {
-            const uint32_t p = dpp<A == 1 ? DPP_QUAD_X1 : DPP_QUAD_X2>(v[r]);
+        for (int r = 0; r < KPT; ++r) {
+            const T p = dpp<A == 1 ? DPP_QUAD_X1 : DPP_QUAD_X2>(v[r]);
             v[r] = lower ? min(v[r], p) : max(v[r], p);
         }
-    } else if constexpr (J <= 8 * SKPT) {
+    } else if constexpr (J <= 8 * KPT) {
         // lane ^ 4, lane ^ 8 on register pairs (X, Y): row shifts masked by
         // bank put each pair's two elements in one lane (the lower one in
         // X1), compare-exchange, then the inverse shifts put them back
-        constexpr int A = J / SKPT;
+        constexpr int A = J / KPT;
         constexpr int LOW = A == 4 ? 0x5 : 0x3, HIGH = A == 4 ? 0xA : 0xC;
 #pragma unroll
-        for (int b = 0; b < SKPT / 2; ++b) {
-            const uint32_t X = v[2 * b], Y = v[2 * b + 1];
-            const uint32_t X1 = dpp_into<DPP_ROW_SHR + A, HIGH>(X, Y);
-            const uint32_t Y1 = dpp_into<DPP_ROW_SHL + A, LOW>(Y, X);
-            const uint32_t mn = min(X1, Y1), mx = max(X1, Y1);
+        for (int b = 0; b < KPT / 2; ++b) {
+            const T X = v[2 * b], Y = v[2 * b + 1];
+            const T X1 = dpp_into<DPP_ROW_SHR + A, HIGH>(X, Y);
+            const T Y1 = dpp_into<DPP_ROW_SHL + A, LOW>(Y, X);
+            const T mn = min(X1, Y1), mx = max(X1, Y1);
             v[2 * b] = dpp_into<DPP_ROW_SHR + A, HIGH>(mn, mx);
             v[2 * b + 1] = dpp_into<DPP_ROW_SHL + A, LOW>(mx, mn);
         }
-    } else if constexpr (J <= 32 * SKPT) {
+    } else if constexpr (J <= 32 * KPT) {
         // lane ^ 16, lane ^ 32 on register pairs: a permlane swap of the
         // pair puts each pair's two elements in one lane, the same swap undoes it
-        constexpr int A = J / SKPT;
+        constexpr int A = J / KPT;
 #pragma unroll
-        for (int b = 0; b < SKPT / 2; ++b) {
-            const auto s = A == 16 ? __builtin_amdgcn_permlane16_swap(v[2 * b], v[2 * b + 1], false, false)
-                                   : __builtin_amdgcn_permlane32_swap(v[2 * b], v[2 * b + 1], false, false);
-            const uint32_t mn = min(s[0], s[1]), mx = max(s[0], s[1]);
-            const auto t = A == 16 ? __builtin_amdgcn_permlane16_swap(mn, mx, false, false)
-                                   : __builtin_amdgcn_permlane32_swap(mn, mx, false, false);
-            v[2 * b] = t[0];
-            v[2 * b + 1] = t[1];
+        for (int b = 0; b < KPT / 2; ++b) {
+            T x = v[2 * b], y = v[2 * b + 1];
+            permlane_swap<A>(x, y);
+            T mn = min(x, y), mx = max(x, y);
+            permlane_swap<A>(mn, mx);
+            v[2 * b] = mn;
+            v[2 * b + 1] = mx;
         }
     } else {
-        sort_cross_wave<J / SKPT, false>(v, tid, buf);
+        sort_cross_wave<T, KPT, NT, J / KPT, false>(v, tid, buf);
     }
-    if constexpr (LJ > 0) sort_half<LJ - 1>(v, lane, tid, buf);
+    if constexpr (LJ > 0) sort_half<T, KPT, NT, LJ - 1>(v, lane, tid, buf);
 }
 
 // Phase LK: the flip, then the half-cleaners.
-template <int LK>
-__device__ __forceinline__ void sort_phase(uint32_t (&v)[SKPT], int lane, int tid, uint4 *buf)
+template <typename T, int KPT, int NT, int LK>
+__device__ __forceinline__ void sort_phase(T (&v)[KPT], int lane, int tid, uint4 *buf)
 {
     constexpr int K = 1 << LK;
-    if constexpr (K <= SKPT) {
+    if constexpr (K <= KPT) {
 #pragma unroll
-        for (int r = 0; r < SKPT; ++r)
+        for (int r = 0; r < KPT; ++r)
             if (!(r & (K / 2))) cmpx(v[r], v[r ^ (K - 1)]);
-    } else if constexpr (K <= 64 * SKPT) {
-        const bool lower = (lane & (K / (2 * SKPT))) == 0;
-        uint32_t p[SKPT];
+    } else if constexpr (K <= 64 * KPT) {
+        const bool lower = (lane & (K / (2 * KPT))) == 0;
+        T p[KPT];
 #pragma unroll
-        for (int r = 0; r < SKPT; ++r) p[r] = flip_lanes<LK - LOG_SKPT>(v[SKPT - 1 - r], lane);
+        for (int r = 0; r < KPT; ++r) p[r] = flip_lanes<LK - Net<T, KPT, NT>::LOG_KPT>(v[KPT - 1 - r], lane);
 #pragma unroll
-        for (int r = 0; r < SKPT; ++r) v[r] = lower ? min(v[r], p[r]) : max(v[r], p[r]);
+        for (int r = 0; r < KPT; ++r) v[r] = lower ? min(v[r], p[r]) : max(v[r], p[r]);
     } else {
-        sort_cross_wave<K / SKPT - 1, true>(v, tid, buf);
+        sort_cross_wave<T, KPT, NT, K / KPT - 1, true>(v, tid, buf);
     }
-    if constexpr (LK >= 2) sort_half<LK - 2>(v, lane, tid, buf);
+    if constexpr (LK >= 2) sort_half<T, KPT, NT, LK - 2>(v, lane, tid, buf);
 }
 
-template <int LK>
-__device__ __forceinline__ void sort_phases(uint32_t (&v)[SKPT], int lane, int tid, uint4 *buf)
+// Sorts the tile held in v (KPT values per thread, NT threads) ascending:
+// afterwards thread tid holds elements KPT tid .. KPT tid + KPT - 1.
+template <typename T, int KPT, int NT, int LK = 1>
+__device__ __forceinline__ void sort_tile(T (&v)[KPT], int lane, int tid, uint4 *buf)
 {
-    sort_phase<LK>(v, lane, tid, buf);
-    if constexpr (LK < LOG_STILE) sort_phases<LK + 1>(v, lane, tid, buf);
+    sort_phase<T, KPT, NT, LK>(v, lane, tid, buf);
+    if constexpr (LK < Net<T, KPT, NT>::LOG_TILE) sort_tile<T, KPT, NT, LK + 1>(v, lane, tid, buf);
 }
 
 // Sorts tile blockIdx.x of dimension blockIdx.y: K[m][t][0..STILE) = the order
@@ -272,7 +343,7 @@ __global__ __launch_bounds__(S32_THREADS) void k_rank_sort32(const float *__rest
         v[r] = i < N ? order_key(x) : 0xffffffffu;
     }
     if (flags && __any(bad) && lane == 0) atomicOr(flags, 1u);
-    sort_phases<1>(v, lane, tid, buf);
+    sort_tile<uint32_t, SKPT, S32_THREADS>(v, lane, tid, buf);
     uint4 *out = reinterpret_cast<uint4 *>(K + ((size_t)m * tiles + t) * STILE) + tid * (SKPT / 4);
 #pragma unroll
     for (int q = 0; q < SKPT / 4; ++q) out[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
@@ -406,87 +477,51 @@ static constexpr int RC_KPT = DDKS_RC_KPT, RC_TPS = DDKS_RC_TPS;
 // ------------------------------------------------------------ N > 65536
 
 // Sorts (order key << 32 | index) pairs of column m = blockIdx.y, tile t =
-// blockIdx.x, T = 256, 1024 or 4096 pairs per tile (~0 past N).  The same
-// fully unrolled bitonic network as k_rank_sort32 on 64-bit pairs: a thread
-// holds four pairs, partners within a wave go through shuffles and only the
-// stages across waves (T > 256) through double-buffered LDS.  Single-tile
-// sorts (T >= N) write the N sorted pairs straight to S + m * N; otherwise
-// the tile goes to A + (m * tiles + t) * T.
-struct Pair4 {
-    uint64_t v[4];
-};
+// blockIdx.x, KPT x NT pairs per tile (~0 past N): 256 (4 x 64), 1024
+// (4 x 256) or TILE = 4096 (8 x 512), by the network of k_rank_sort32 on
+// 64-bit values (partners within a wave through DPP and permlane swaps, only
+// the stages across waves through LDS).  Thread tid reads pairs t * tile +
+// tid + NT r (the index travels in the pair, so the sort does not care).
+// S != nullptr: one tile holds the whole column, whose N pairs are written
+// sorted to S + m * N.  Otherwise the sorted tile goes to A + (m * tiles + t)
+// * tile, and pos (the sorted positions that k_rank_place_count accumulates)
+// is cleared at the same entries.
+#ifndef DDKS_PAIR_KPT
+#define DDKS_PAIR_KPT 8
+#endif
+static constexpr int PAIR_KPT = DDKS_PAIR_KPT;
+static constexpr int PAIR_THREADS = TILE / PAIR_KPT;
 
-// S != nullptr: one tile holds the whole column, written sorted to S.
-// Otherwise the sorted tile goes to A, and pos (the sorted positions that
-// k_rank_place_count accumulates) is cleared at the same entries.
-template <int T>
-__global__ __launch_bounds__(T / 4) void k_rank_tiles(const float *__restrict__ Z, int64_t N, int d,
-                                                      int64_t tiles, uint64_t *__restrict__ A,
-                                                      uint64_t *__restrict__ S, uint32_t *__restrict__ pos)
+template <int KPT, int NT>
+__global__ __launch_bounds__(NT) void k_rank_pairs(const float *__restrict__ Z, int64_t N, int d,
+                                                   int64_t tiles, uint64_t *__restrict__ A,
+                                                   uint64_t *__restrict__ S, uint32_t *__restrict__ pos)
 {
-    constexpr int THREADS = T / 4;
-    constexpr int LOG_T = T == 256 ? 8 : (T == 1024 ? 10 : 12);
-    static_assert(T == 256 || T == 1024 || T == 4096, "tile sizes");
-    __shared__ Pair4 buf[2][T > 256 ? THREADS : 1];
+    constexpr int TP = KPT * NT;
+    __shared__ uint4 buf[NT > 64 ? NT * Net<uint64_t, KPT, NT>::WORDS : 1];
     const int m = blockIdx.y;
     const int64_t t = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int e0 = 4 * tid;
-    uint64_t v[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint64_t v[KPT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t i = t * T + e0 + r;
+    for (int r = 0; r < KPT; ++r) {
+        const int64_t i = t * TP + tid + (int64_t)r * NT;
         v[r] = i < N ? ((uint64_t)order_key(Z[i * d + m]) << 32) | (uint64_t)i : ~0ull;
     }
-    int cur = 0;
-#pragma unroll
-    for (int lk = 1; lk <= LOG_T; ++lk) {
-        const int k = 1 << lk;
-#pragma unroll
-        for (int lj = lk - 1; lj >= 0; --lj) {
-            const int j = 1 << lj;
-            if (j >= 4) {
-                const bool keep_min = ((e0 & j) == 0) == ((e0 & k) == 0);
-                uint64_t pv[4];
-                if (j >= 256) {
-                    if constexpr (T > 256) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) buf[cur][tid].v[r] = v[r];
-                        __syncthreads();
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) pv[r] = buf[cur][tid ^ (j >> 2)].v[r];
-                        cur ^= 1;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) pv[r] = __shfl_xor(v[r], j >> 2, 64);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = keep_min ? min(v[r], pv[r]) : max(v[r], pv[r]);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (r & j) continue;
-                    const bool up = (((e0 + r) & k) == 0);
-                    const uint64_t lo = min(v[r], v[r | j]), hi = max(v[r], v[r | j]);
-                    v[r] = up ? lo : hi;
-                    v[r | j] = up ? hi : lo;
-                }
-            }
-        }
-    }
+    sort_tile<uint64_t, KPT, NT>(v, lane, tid, buf);
+    const int e0 = KPT * tid;
     if (S) {
         uint64_t *out = S + (size_t)m * N;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < KPT; ++r)
             if (e0 + r < N) out[e0 + r] = v[r];
     } else {
-        const size_t base = ((size_t)m * tiles + t) * T;
+        const size_t base = ((size_t)m * tiles + t) * TP + e0;
+        uint4 *a = reinterpret_cast<uint4 *>(A + base);  // A and TP: 16-byte multiples
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            A[base + e0 + r] = v[r];
-            pos[base + e0 + r] = 0u;
-        }
+        for (int q = 0; q < KPT / 2; ++q) a[q] = make_uint4(lo32(v[2 * q]), hi32(v[2 * q]), lo32(v[2 * q + 1]), hi32(v[2 * q + 1]));
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) pos[base + r] = 0u;
     }
 }
 
@@ -734,23 +769,23 @@ size_t sort_columns_scratch_bytes(int64_t N, int C)
 hipError_t launch_sort_columns(const float *X, int64_t N, int C, void *scratch, uint64_t **S_out,
                                hipStream_t st)
 {
-    if (N < 1 || C < 1 || C > 65535 || N > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (N < 1 || C < 1 || C > 65535 || N > 0x7fffffffLL || ((uintptr_t)scratch & 15)) return hipErrorInvalidValue;
     const int64_t tiles = tiles_of(N);
     uint64_t *A = (uint64_t *)scratch;
     uint64_t *S = A + (size_t)C * tiles * TILE;
     uint32_t *pos = (uint32_t *)(S + (size_t)C * N);
     if (tiles == 1) {  // one tile: the sorted tile is the sorted column
         if (N <= 256)
-            hipLaunchKernelGGL(k_rank_tiles<256>, dim3(1, C), dim3(64), 0, st, X, N, C, tiles, A, S, pos);
+            hipLaunchKernelGGL((k_rank_pairs<4, 64>), dim3(1, C), dim3(64), 0, st, X, N, C, tiles, A, S, pos);
         else if (N <= 1024)
-            hipLaunchKernelGGL(k_rank_tiles<1024>, dim3(1, C), dim3(256), 0, st, X, N, C, tiles, A, S, pos);
+            hipLaunchKernelGGL((k_rank_pairs<4, 256>), dim3(1, C), dim3(256), 0, st, X, N, C, tiles, A, S, pos);
         else
-            hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3(1, C), dim3(TILE / 4), 0, st, X, N, C, tiles, A, S,
+            hipLaunchKernelGGL((k_rank_pairs<PAIR_KPT, PAIR_THREADS>), dim3(1, C), dim3(PAIR_THREADS), 0, st, X, N, C, tiles, A, S,
                                pos);
         *S_out = S;
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3((unsigned)tiles, C), dim3(TILE / 4), 0, st, X, N, C, tiles,
+    hipLaunchKernelGGL((k_rank_pairs<PAIR_KPT, PAIR_THREADS>), dim3((unsigned)tiles, C), dim3(PAIR_THREADS), 0, st, X, N, C, tiles,
                        A, (uint64_t *)nullptr, pos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -784,13 +819,14 @@ hipError_t launch_rank16(const float *Z, int64_t N, int d, uint32_t *R, void *sc
     uint16_t *R16 = (uint16_t *)R;
     hipError_t e;
     if (N <= 65536) return launch_rank16_pq(Z, N, Z, 0, d, R, scratch, nullptr, st);
+    if ((uintptr_t)scratch & 15) return hipErrorInvalidValue;  // the tile sort stores 16-byte words
     uint64_t *A = (uint64_t *)scratch;
     uint64_t *S = A + (size_t)d * tiles * TILE;
     uint32_t *C = (uint32_t *)(S + (size_t)d * N);
     const int64_t segs = (N + SEG - 1) / SEG;
     const RankTables tabs = rank16_tables(scratch, N, d);
     uint32_t *pos = tabs.RS + (size_t)d * (N + 1);
-    hipLaunchKernelGGL(k_rank_tiles<TILE>, dim3((unsigned)tiles, d), dim3(TILE / 4), 0, st, Z, N, d,
+    hipLaunchKernelGGL((k_rank_pairs<PAIR_KPT, PAIR_THREADS>), dim3((unsigned)tiles, d), dim3(PAIR_THREADS), 0, st, Z, N, d,
                        tiles, A, (uint64_t *)nullptr, pos);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_place(A, N, d, tiles, pos, S, st)) != hipSuccess) return e;
