@@ -11,8 +11,9 @@
 // lists, |c_P(r) n_Q - c_Q(r) n_P| at the largest, over the distinct
 // distances r; D is the largest over the corners.
 //
-// Device work: extents (order-key minima and maxima per dimension), normalised coordinates,
-// the N x (d + 1) distance matrix (one thread per point and corner), each
+// Device work: extents (order-key minima and maxima per dimension), the
+// N x (d + 1) distance matrix of the normalised coordinates (formed on the
+// fly; one thread per point and corner below 32 dimensions), each
 // column sorted as (key, index) pairs, then per corner a segmented scan of
 // first-sample labels along the sorted order that scores the end of every
 // run of equal distances.
@@ -40,12 +41,15 @@ __device__ __forceinline__ float rd_from_key(uint32_t k)
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-__global__ void k_rd_extent_init(uint32_t *__restrict__ key, int d)
+__global__ void k_rd_extent_init(uint32_t *__restrict__ key, int d, unsigned long long *__restrict__ corner_num,
+                                 int C)
 {
     for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < d; m += gridDim.x * blockDim.x) {
         key[2 * m] = 0xffffffffu;  // running minimum
         key[2 * m + 1] = 0u;       // running maximum
     }
+    // the per-corner maxima that k_rd_score raises
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) corner_num[c] = 0ull;
 }
 
 // Per-dimension extents as order keys: block (chunk, m) reduces its share of
@@ -83,22 +87,18 @@ __global__ __launch_bounds__(256) void k_rd_extent(const float *__restrict__ Z, 
     }
 }
 
-// Normalised coordinates u (N x d), each value (x - lo) / (hi - lo) rounded once
-// per operation.
-__global__ void k_rd_norm(const float *__restrict__ Z, int64_t N, int d, const uint32_t *__restrict__ lohi,
-                          float *__restrict__ U)
+// Normalised coordinate u of value x in dimension m: (x - lo) / (hi - lo),
+// each operation rounded on its own; 0 in a constant dimension.
+__device__ __forceinline__ float rd_u(float x, const uint32_t *__restrict__ lohi, int m)
 {
-    const int64_t total = N * d;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int m = (int)(e % d);
-        const float lo = rd_from_key(lohi[2 * m]), hi = rd_from_key(lohi[2 * m + 1]);
-        U[e] = hi > lo ? __fdiv_rn(__fsub_rn(Z[e], lo), __fsub_rn(hi, lo)) : 0.0f;
-    }
+    const float lo = rd_from_key(lohi[2 * m]), hi = rd_from_key(lohi[2 * m + 1]);
+    return hi > lo ? __fdiv_rn(__fsub_rn(x, lo), __fsub_rn(hi, lo)) : 0.0f;
 }
 
-// Dist[i * C + c] = sum over m ascending of (u_m - [c == m + 1])^2, C = d + 1.
-__global__ void k_rd_dist(const float *__restrict__ U, int64_t N, int d, float *__restrict__ Dist)
+// Dist[i * C + c] = sum over m ascending of (u_m - [c == m + 1])^2, C = d + 1,
+// u_m formed from Z on the fly (a thread per (point, corner); d < 32).
+__global__ void k_rd_dist(const float *__restrict__ Z, const uint32_t *__restrict__ lohi, int64_t N, int d,
+                          float *__restrict__ Dist)
 {
     const int C = d + 1;
     const int64_t total = N * C;
@@ -106,10 +106,10 @@ __global__ void k_rd_dist(const float *__restrict__ U, int64_t N, int d, float *
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / C;
         const int c = (int)(e % C);
-        const float *u = U + i * d;
+        const float *z = Z + i * d;
         float acc = 0.0f;
         for (int m = 0; m < d; ++m) {
-            const float t = __fsub_rn(u[m], c == m + 1 ? 1.0f : 0.0f);
+            const float t = __fsub_rn(rd_u(z[m], lohi, m), c == m + 1 ? 1.0f : 0.0f);
             acc = __fadd_rn(acc, __fmul_rn(t, t));
         }
         Dist[e] = acc;
@@ -122,7 +122,8 @@ __global__ void k_rd_dist(const float *__restrict__ U, int64_t N, int d, float *
 // by the rounded (u_m - 1)^2, so both squares are formed once per point and
 // staged in LDS (2 d <= 8192 floats); the operations and their order are
 // those of k_rd_dist.
-__global__ __launch_bounds__(1024) void k_rd_dist_rows(const float *__restrict__ U, int64_t N, int d,
+__global__ __launch_bounds__(1024) void k_rd_dist_rows(const float *__restrict__ Z,
+                                                       const uint32_t *__restrict__ lohi, int64_t N, int d,
                                                        float *__restrict__ Dist)
 {
     extern __shared__ float sq[];  // sq[m] = u_m^2, sq[d + m] = (u_m - 1)^2
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(1024) void k_rd_dist_rows(const float *__restrict__
     for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
         __syncthreads();  // the previous point's squares have been used
         for (int m = threadIdx.x; m < d; m += blockDim.x) {
-            const float u = U[i * d + m];
+            const float u = rd_u(Z[i * d + m], lohi, m);
             const float t = __fsub_rn(u, 1.0f);
             sq[m] = __fmul_rn(u, u);
             sq[d + m] = __fmul_rn(t, t);
@@ -147,11 +148,6 @@ __global__ __launch_bounds__(1024) void k_rd_dist_rows(const float *__restrict__
             Dist[i * C + c] = acc;
         }
     }
-}
-
-__global__ void k_rd_zero(unsigned long long *__restrict__ v, int n)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = 0ull;
 }
 
 // cnt[m * segs + g] = first-sample points among sorted positions of segment g.
@@ -286,7 +282,6 @@ size_t rdks_scratch_bytes(int64_t N, int d)
     const int C = d + 1;
     size_t b = 0;
     b += (size_t)2 * d * sizeof(uint32_t);      // extents (order keys)
-    b += (size_t)N * d * sizeof(float);         // U
     b += (size_t)N * C * sizeof(float);         // Dist
     b += (size_t)C * rd_segs(N) * sizeof(uint32_t) + 256;
     b += sort_columns_scratch_bytes(N, C);
@@ -301,28 +296,24 @@ hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scra
     char *base = (char *)scratch;
     uint32_t *lohi = (uint32_t *)base;
     base += ((size_t)2 * d * sizeof(uint32_t) + 255) & ~(size_t)255;
-    float *U = (float *)base;
-    base += ((size_t)N * d * sizeof(float) + 255) & ~(size_t)255;
     float *Dist = (float *)base;
     base += ((size_t)N * C * sizeof(float) + 255) & ~(size_t)255;
     uint32_t *cnt = (uint32_t *)base;
     const int64_t segs = rd_segs(N);
     base += ((size_t)C * segs * sizeof(uint32_t) + 255) & ~(size_t)255;
     auto grid = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); };
-    hipLaunchKernelGGL(k_rd_extent_init, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, lohi, d);
+    hipLaunchKernelGGL(k_rd_extent_init, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, s, lohi, d, corner_num, C);
     const unsigned chunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 4095) / 4096, RD_EXTENT_CHUNKS));
     hipLaunchKernelGGL(k_rd_extent, dim3(chunks, (unsigned)d), dim3(256), 0, s, Z, N, d, lohi);
-    hipLaunchKernelGGL(k_rd_norm, dim3(grid(N * d)), dim3(256), 0, s, Z, N, d, lohi, U);
     if (d >= RD_ROWS_MIN_D)
         hipLaunchKernelGGL(k_rd_dist_rows, dim3((unsigned)std::min<int64_t>(N, 4096)), dim3(1024),
-                           (size_t)2 * d * sizeof(float), s, U, N, d, Dist);
+                           (size_t)2 * d * sizeof(float), s, Z, lohi, N, d, Dist);
     else
-        hipLaunchKernelGGL(k_rd_dist, dim3(grid(N * C)), dim3(256), 0, s, U, N, d, Dist);
+        hipLaunchKernelGGL(k_rd_dist, dim3(grid(N * C)), dim3(256), 0, s, Z, lohi, N, d, Dist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint64_t *S = nullptr;
     if ((e = launch_sort_columns(Dist, N, C, base, &S, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rd_zero, dim3(grid(C)), dim3(256), 0, s, corner_num, C);
     hipLaunchKernelGGL(k_rd_seg, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p, cnt);
     hipLaunchKernelGGL(k_rd_score, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p,
                        N - n_p, cnt, corner_num);
