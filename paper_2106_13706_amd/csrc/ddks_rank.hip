@@ -73,7 +73,7 @@ static constexpr int LOG_STILE = DDKS_STILE_LOG;
 static constexpr int STILE = 1 << LOG_STILE;
 static constexpr int SKPT = DDKS_SORT_KPT;  // keys per thread
 static constexpr int S32_THREADS = STILE / SKPT;
-static_assert((SKPT == 8 || SKPT == 16) && S32_THREADS >= 256 && S32_THREADS <= 1024, "tile size");
+static_assert((SKPT == 4 || SKPT == 8 || SKPT == 16) && S32_THREADS >= 256 && S32_THREADS <= 1024, "tile size");
 
 // ---- the tile sort: a bitonic network on KPT values per thread (element
 // e = KPT tid + r of the tile in register r of thread tid), in the form where

@@ -26,8 +26,11 @@
 
 namespace ddks {
 
-static constexpr int RD_SEG = 4096;       // sorted positions per scan segment
-static constexpr int RD_THREADS = 1024;   // four positions per thread
+// Scan segments of 1024 sorted positions, 256 threads of four: a column of
+// 40000 positions gives 40 blocks per corner (4096-position segments of 1024
+// threads took 10.7 us to score at d = 4 against 50 blocks in all).
+static constexpr int RD_SEG = 1024;       // sorted positions per scan segment
+static constexpr int RD_THREADS = 256;    // four positions per thread
 
 // Order-preserving image of a finite fp32 value (-0 is mapped to +0
 // upstream): unsigned comparison of images == fp32 comparison.
@@ -172,50 +175,65 @@ __global__ __launch_bounds__(RD_THREADS) void k_rd_seg(const uint64_t *__restric
 }
 
 // Scores every run end of segment g of corner m and folds the maximum into
-// corner_num[m].
-__global__ __launch_bounds__(RD_THREADS) void k_rd_score(const uint64_t *__restrict__ S, int64_t N,
-                                                         int64_t segs, int64_t n_p, int64_t n_q,
-                                                         const uint32_t *__restrict__ cnt,
-                                                         unsigned long long *__restrict__ corner_num)
+// corner_num[m].  NT threads of RD_PER positions each: NT = RD_THREADS covers
+// a segment; a column of one segment (N <= RD_SEG, cnt unread) may take a
+// smaller block that still covers its N positions.
+static constexpr int RD_PER = RD_SEG / RD_THREADS;
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rd_score(const uint64_t *__restrict__ S, int64_t N,
+                                                 int64_t segs, int64_t n_p, int64_t n_q,
+                                                 const uint32_t *__restrict__ cnt,
+                                                 unsigned long long *__restrict__ corner_num)
 {
-    constexpr int PER = RD_SEG / RD_THREADS;
-    __shared__ uint32_t scan[RD_THREADS];
-    __shared__ int64_t before;
+    constexpr int PER = RD_PER;
+    constexpr int NW = NT / 64;
+    __shared__ uint32_t wsum[NW];
+    __shared__ unsigned long long before;
     __shared__ unsigned long long bmax;
     const int m = blockIdx.y;
     const int64_t g = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t *Sm = S + (size_t)m * N;
-    if (threadIdx.x == 0) {
-        int64_t b = 0;
-        for (int64_t h = 0; h < g; ++h) b += cnt[(size_t)m * segs + h];
-        before = b;
+    if (tid == 0) {
+        before = 0ull;
         bmax = 0ull;
     }
-    const int64_t p0 = g * RD_SEG + (int64_t)threadIdx.x * PER;
+    // the thread's PER pairs and the next one (its last run may end there),
+    // all loaded up front
+    const int64_t p0 = g * RD_SEG + (int64_t)tid * PER;
+    uint64_t v[PER + 1];
+#pragma unroll
+    for (int e = 0; e <= PER; ++e) v[e] = p0 + e < N ? Sm[p0 + e] : ~0ull;
+    int64_t b = 0;  // first-sample points of the earlier segments
+    for (int64_t h = tid; h < g; h += NT) b += cnt[(size_t)m * segs + h];
+    __syncthreads();
+    if (b) atomicAdd(&before, (unsigned long long)b);
     uint32_t lab[PER];
     uint32_t c = 0;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-        const int64_t p = p0 + e;
-        lab[e] = (p < N && (int64_t)(uint32_t)Sm[p] < n_p) ? 1u : 0u;
+        lab[e] = (p0 + e < N && (int64_t)(uint32_t)v[e] < n_p) ? 1u : 0u;
         c += lab[e];
     }
-    scan[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 1; off < RD_THREADS; off <<= 1) {  // inclusive block scan
-        const uint32_t v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0u;
-        __syncthreads();
-        scan[threadIdx.x] += v;
-        __syncthreads();
+    uint32_t x = c;  // inclusive scan within the wave, then over the waves
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
+        if (lane >= off) x += y;
     }
-    int64_t cp = before + scan[threadIdx.x] - c;  // first-sample points before p0
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t wb = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) wb += q < w ? wsum[q] : 0u;
+    int64_t cp = (int64_t)before + wb + x - c;  // first-sample points before p0
     unsigned long long best = 0ull;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int64_t p = p0 + e;
         if (p >= N) break;
         cp += lab[e];
-        const bool run_end = p + 1 == N || (Sm[p + 1] >> 32) != (Sm[p] >> 32);
+        const bool run_end = p + 1 == N || (v[e + 1] >> 32) != (v[e] >> 32);
         if (!run_end) continue;
         const int64_t cq = (p + 1) - cp;
         const int64_t sd = cp * n_q - cq * n_p;
@@ -224,7 +242,7 @@ __global__ __launch_bounds__(RD_THREADS) void k_rd_score(const uint64_t *__restr
     }
     atomicMax(&bmax, best);
     __syncthreads();
-    if (threadIdx.x == 0 && bmax > 0ull) atomicMax(&corner_num[m], bmax);
+    if (tid == 0 && bmax > 0ull) atomicMax(&corner_num[m], bmax);
 }
 
 // D = the largest corner numerator; ties go to the lowest corner (one block).
@@ -314,9 +332,16 @@ hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scra
     if (e != hipSuccess) return e;
     uint64_t *S = nullptr;
     if ((e = launch_sort_columns(Dist, N, C, base, &S, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rd_seg, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p, cnt);
-    hipLaunchKernelGGL(k_rd_score, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p,
-                       N - n_p, cnt, corner_num);
+    if (segs > 1) {
+        hipLaunchKernelGGL(k_rd_seg, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p, cnt);
+        hipLaunchKernelGGL(k_rd_score<RD_THREADS>, dim3((unsigned)segs, C), dim3(RD_THREADS), 0, s, S, N, segs,
+                           n_p, N - n_p, cnt, corner_num);
+    } else if (N <= 64 * RD_PER) {  // one segment: no counts of earlier segments to read
+        hipLaunchKernelGGL(k_rd_score<64>, dim3(1, C), dim3(64), 0, s, S, N, segs, n_p, N - n_p, cnt, corner_num);
+    } else {
+        hipLaunchKernelGGL(k_rd_score<RD_THREADS>, dim3(1, C), dim3(RD_THREADS), 0, s, S, N, segs, n_p, N - n_p,
+                           cnt, corner_num);
+    }
     hipLaunchKernelGGL(k_rd_final, dim3(1), dim3(1024), 0, s, corner_num, C, flags, out);
     return hipGetLastError();
 }
