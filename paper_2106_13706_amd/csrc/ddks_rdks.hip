@@ -129,7 +129,8 @@ __global__ __launch_bounds__(1024) void k_rd_dist_rows(const float *__restrict__
                                                        const uint32_t *__restrict__ lohi, int64_t N, int d,
                                                        float *__restrict__ Dist)
 {
-    extern __shared__ float sq[];  // sq[m] = u_m^2, sq[d + m] = (u_m - 1)^2
+    extern __shared__ float4 sq4[];  // as floats: sq[m] = u_m^2, sq[d + m] = (u_m - 1)^2
+    float *sq = reinterpret_cast<float *>(sq4);
     const int C = d + 1;
     for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
         __syncthreads();  // the previous point's squares have been used
@@ -141,13 +142,25 @@ __global__ __launch_bounds__(1024) void k_rd_dist_rows(const float *__restrict__
         }
         __syncthreads();
         for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            // the same additions in the same order, the squares read four at
+            // a time where they are 16-byte aligned
             float acc = 0.0f;
             const int j = c - 1;  // the replaced term (none for the origin corner)
-#pragma unroll 8
-            for (int m = 0; m < j; ++m) acc = __fadd_rn(acc, sq[m]);
+            int m = 0;
+#pragma unroll 2
+            for (; m + 4 <= j; m += 4) {
+                const float4 q = sq4[m >> 2];
+                acc = __fadd_rn(__fadd_rn(__fadd_rn(__fadd_rn(acc, q.x), q.y), q.z), q.w);
+            }
+            for (; m < j; ++m) acc = __fadd_rn(acc, sq[m]);
             if (j >= 0) acc = __fadd_rn(acc, sq[d + j]);
-#pragma unroll 8
-            for (int m = j + 1; m < d; ++m) acc = __fadd_rn(acc, sq[m]);
+            for (m = j + 1; m < d && (m & 3); ++m) acc = __fadd_rn(acc, sq[m]);
+#pragma unroll 2
+            for (; m + 4 <= d; m += 4) {
+                const float4 q = sq4[m >> 2];
+                acc = __fadd_rn(__fadd_rn(__fadd_rn(__fadd_rn(acc, q.x), q.y), q.z), q.w);
+            }
+            for (; m < d; ++m) acc = __fadd_rn(acc, sq[m]);
             Dist[i * C + c] = acc;
         }
     }
