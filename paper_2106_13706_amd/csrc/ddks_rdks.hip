@@ -334,7 +334,7 @@ hipError_t launch_rdks(const float *Z, int64_t N, int64_t n_p, int d, void *scra
     base += ((size_t)C * segs * sizeof(uint32_t) + 255) & ~(size_t)255;
     auto grid = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); };
     hipLaunchKernelGGL(k_rd_extent_init, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, s, lohi, d, corner_num, C);
-    const unsigned chunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 4095) / 4096, RD_EXTENT_CHUNKS));
+    const unsigned chunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 1023) / 1024, RD_EXTENT_CHUNKS));
     hipLaunchKernelGGL(k_rd_extent, dim3(chunks, (unsigned)d), dim3(256), 0, s, Z, N, d, lohi);
     if (d >= RD_ROWS_MIN_D)
         hipLaunchKernelGGL(k_rd_dist_rows, dim3((unsigned)std::min<int64_t>(N, 4096)), dim3(1024),
